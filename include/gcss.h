@@ -1,0 +1,231 @@
+/*
+ * gcss.h -- C ABI of the MI355X (gfx950) library for greedy generalized
+ * column subset selection (Farahat, Elgohary, Ghodsi, Kamel, "Greedy Column
+ * Subset Selection for Large-scale Data Sets").
+ *
+ * Problem (Problems 1 and 5 of the paper): given a source matrix A (m x n)
+ * and a target B (m x r), pick k columns S of A that greedily minimise
+ *      F(S) = || B - P_S B ||_F^2 ,   P_S = projection onto span(A_S).
+ * B = A is the centralized problem (Algorithm 1); B = A * Omega with a random
+ * Omega is the paper's concise target (Section 5.1, Algorithm 2).
+ *
+ * Conventions
+ *   - Matrices are column-major.  A's column i starts at element i*lda.
+ *     lda >= m, and lda * sizeof(element) must be a multiple of 16 bytes;
+ *     device pointers must be 16-byte aligned.  Pad entries are never read
+ *     into results.
+ *   - Pointers documented as "device" are HIP device memory owned by the
+ *     caller; they must stay valid for the life of the context that borrows
+ *     them.  Pointers documented as "host" are ordinary host memory.
+ *   - Indices are 0-based (the paper's are 1-based).
+ *   - Every call returns a gcss_status.  Nothing aborts or throws across the
+ *     ABI.  On failure gcss_last_error() returns a message (per thread) and
+ *     the context keeps its previous state.
+ *   - All device work of a context is ordered on the stream given at
+ *     creation (NULL = the device's default stream).  Calls that return host
+ *     outputs synchronize that stream; the *_async calls do not.
+ *   - The library allocates no device memory: the caller hands over one
+ *     workspace sized by gcss_workspace_size().
+ *   - Same inputs, same device -> bitwise identical outputs (no floating
+ *     point atomics; every reduction has a fixed order).
+ */
+#ifndef GCSS_H
+#define GCSS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GCSS_OK = 0,
+  GCSS_WARN_EXHAUSTED = 1,   /* fewer than k eligible columns; *n_selected < k   */
+  GCSS_ERR_ARG = -1,         /* invalid argument (null pointer, size, alignment) */
+  GCSS_ERR_STATE = -2,       /* call out of order (e.g. select before a target)  */
+  GCSS_ERR_DEVICE = -3,      /* no usable gfx950 device, or a HIP runtime error  */
+  GCSS_ERR_WORKSPACE = -4,   /* workspace missing or smaller than required       */
+  GCSS_ERR_UNSUPPORTED = -5  /* shape or dtype outside what the kernels cover    */
+} gcss_status;
+
+/* Element type of the stored source matrix A. */
+typedef enum {
+  GCSS_F32 = 0,       /* IEEE binary32                                              */
+  GCSS_BF16 = 1,      /* bfloat16 (upper half of binary32)                          */
+  GCSS_FP8_E4M3 = 2   /* OCP FP8 E4M3 (e4m3fn); value = a_scale[i] * decode(code)   */
+} gcss_dtype;
+
+typedef struct gcss_ctx gcss_ctx;
+
+/* Description of the source matrix and of the capacity a context reserves. */
+typedef struct {
+  int64_t m;               /* rows of A (and of B)                              >= 1 */
+  int64_t n;               /* columns of A                                      >= 1 */
+  int64_t lda;             /* leading dimension of A, in elements               >= m */
+  int32_t a_dtype;         /* gcss_dtype                                             */
+  const void *a;           /* device, borrowed: A, column-major                      */
+  const float *a_scale;    /* device, borrowed: n per-column scales (FP8 only; NULL otherwise) */
+  int32_t k_max;           /* largest k any later select may ask for        1..n     */
+  int64_t r_max;           /* largest explicit target width (0 = none)               */
+  int32_t self_target;     /* nonzero: reserve the m x m Gram target for B = A       */
+  int32_t reserved;        /* must be 0                                              */
+  double tau;              /* eligibility threshold: a column stays a candidate while
+                              g_i > tau * g0_i (g = squared norm of its residual);
+                              <= 0 selects 1e-4                                      */
+  void *stream;            /* hipStream_t for all work of the context; NULL = default */
+} gcss_desc;
+
+/*
+ * Bytes of device workspace a context for *d needs.  Host-only; does not
+ * touch the device.  Errors: GCSS_ERR_ARG.
+ */
+gcss_status gcss_workspace_size(const gcss_desc *d, size_t *bytes);
+
+/*
+ * Create a context over the source matrix described by *d, on the current
+ * HIP device.  workspace: device, >= gcss_workspace_size bytes, 256-byte
+ * aligned, borrowed for the context's life.
+ * Errors: GCSS_ERR_ARG, GCSS_ERR_WORKSPACE, GCSS_ERR_DEVICE (no gfx950),
+ * GCSS_ERR_UNSUPPORTED (m larger than the kernels cover: 8192 for F32,
+ * 16384 for BF16, 32768 for FP8).
+ */
+gcss_status gcss_create(const gcss_desc *d, void *workspace, size_t ws_bytes, gcss_ctx **out);
+
+/* Destroy a context (NULL is ignored).  Does not free borrowed memory. */
+void gcss_destroy(gcss_ctx *h);
+
+/*
+ * Set the target and compute the initial scores of Algorithms 1/3:
+ *     f_i = || B^T A_i ||^2 ,  g_i = || A_i ||^2 ,  F_0 = || B ||_F^2 .
+ * b: device, borrowed, m x r binary32 column-major with leading dimension
+ *    ldb >= m (ldb*4 a multiple of 16), 1 <= r <= r_max.
+ * b == NULL and r == 0: B = A (Algorithm 1).  The target then enters only
+ *    through its Gram matrix A A^T (m x m), which is formed in the workspace;
+ *    requires self_target at creation.
+ * Errors: GCSS_ERR_ARG, GCSS_ERR_STATE (self target not reserved),
+ * GCSS_ERR_DEVICE.
+ */
+gcss_status gcss_set_target(gcss_ctx *h, const float *b, int64_t r, int64_t ldb);
+
+/*
+ * The paper's concise target (Section 5.1, Algorithm 2): B = A * Omega,
+ * written to b_out, then set as the target as by gcss_set_target.
+ * omega: device, n x r binary32 ROW-major (row i is the r-vector drawn for
+ *        column i of A), borrowed only during the call.
+ * b_out: device, m x r binary32 column-major, leading dimension ldb >= m;
+ *        borrowed for the context's life (it becomes the target).
+ * Errors: as gcss_set_target.
+ */
+gcss_status gcss_project_target(gcss_ctx *h, const float *omega, int64_t r, float *b_out,
+                                int64_t ldb);
+
+/*
+ * Greedy selection of k columns (Algorithm 3; Algorithm 1 for B = A) from the
+ * initial scores of the current target.  Each call starts from those
+ * scores, so repeated calls give identical results.
+ * idx:        host, k entries: picks in order; -1 for picks not made.
+ * objective:  host, k+1 entries (may be NULL): objective[0] = ||B||_F^2,
+ *             objective[t] = F(first t picks) by the recursion of Theorems
+ *             1 and 3; entries past *n_selected repeat the last value.
+ * n_selected: host (may be NULL): number of picks made.
+ * Returns GCSS_OK, or GCSS_WARN_EXHAUSTED when fewer than k columns stay
+ * candidates (see gcss_desc.tau).  Errors: GCSS_ERR_ARG (k < 1 or k > k_max),
+ * GCSS_ERR_STATE (no target), GCSS_ERR_DEVICE.  Synchronizes the stream.
+ */
+gcss_status gcss_select(gcss_ctx *h, int32_t k, int64_t *idx, double *objective,
+                        int32_t *n_selected);
+
+/*
+ * As gcss_select, but the outputs stay on the device and the call does not
+ * synchronize: d_idx (k int64), d_obj (k+1 double, may be NULL),
+ * d_nsel (1 int32, may be NULL) are device pointers written on the stream.
+ * The whole k-step loop is replayed from a HIP graph that is built on the
+ * first call for a given k.
+ */
+gcss_status gcss_select_async(gcss_ctx *h, int32_t k, int64_t *d_idx, double *d_obj,
+                              int32_t *d_nsel);
+
+/*
+ * Reconstruction error || B - P_S B ||_F^2 of the current target for the
+ * columns S = idx[0..k-1] (host, distinct, in [0, n)), written to *err
+ * (host).  P_S comes from an FP64 Gram-Schmidt basis (with one
+ * re-orthogonalisation) of A_S.  For an explicit B the residual
+ * B - Q (Q^T B) is formed and summed in FP64.  For B = A the error is
+ * tr(A A^T) - tr(Q^T (A A^T) Q) with FP64 sums over the binary32 Gram
+ * matrix.  Errors: GCSS_ERR_ARG, GCSS_ERR_STATE, GCSS_ERR_DEVICE.
+ */
+gcss_status gcss_reconstruction_error(gcss_ctx *h, const int64_t *idx, int32_t k, double *err);
+
+/*
+ * Algorithm 4 on one GPU.  The columns of A are split into nblocks
+ * consecutive blocks col_off[b] .. col_off[b+1]-1 (host, nblocks+1 entries,
+ * col_off[0] = 0, col_off[nblocks] = n, strictly increasing).  Every block
+ * selects k_block columns against the shared explicit target B (all blocks
+ * advance together, one batched launch per phase of a step); the picks are
+ * pooled in block order, then pick order, and k_merge columns are selected
+ * from the pool against B.
+ * idx_block: host, nblocks*k_block global indices (-1 for picks not made).
+ * idx_merge: host, k_merge global indices.  obj_merge: host, k_merge+1 (may
+ * be NULL).  n_merge: host (may be NULL).
+ * Requires an explicit target (gcss_set_target / gcss_project_target) and
+ * k_block*nblocks <= n.  Errors: GCSS_ERR_ARG, GCSS_ERR_STATE,
+ * GCSS_ERR_UNSUPPORTED (pool larger than the context's k_max allows),
+ * GCSS_ERR_DEVICE.  Synchronizes the stream.
+ */
+gcss_status gcss_select_batched(gcss_ctx *h, int32_t nblocks, const int64_t *col_off,
+                                int32_t k_block, int32_t k_merge, int64_t *idx_block,
+                                int64_t *idx_merge, double *obj_merge, int32_t *n_merge);
+
+/*
+ * Bytes of workspace gcss_select_batched needs beyond gcss_workspace_size,
+ * for the given block layout and budgets; pass the total to gcss_create
+ * (the batched state is carved from the end of the same workspace).
+ */
+gcss_status gcss_batched_workspace_size(const gcss_desc *d, int32_t nblocks, int32_t k_block,
+                                        int32_t k_merge, size_t *bytes);
+
+/*
+ * Store a binary32 matrix in a reduced-precision format (the storage the
+ * selection then streams).  a: device m x n, leading dimension lda.
+ * out: device, leading dimension ldo (elements) >= m.  dtype GCSS_BF16:
+ * round to nearest, ties to even.  dtype GCSS_FP8_E4M3: per column
+ * scale_i = max_j |a_ji| / 448 (binary32 division; 1 for a zero column),
+ * written to scales (device, n floats), and code = nearest E4M3 value of the
+ * binary32 quotient a_ji / scale_i, ties to even, saturating at 448.
+ * Pad entries m..ldo-1 of each column are set to zero.  Ordered on stream.
+ * Errors: GCSS_ERR_ARG, GCSS_ERR_DEVICE.
+ */
+gcss_status gcss_quantize(const float *a, int64_t m, int64_t n, int64_t lda, int32_t dtype,
+                          void *out, int64_t ldo, float *scales, void *stream);
+
+/* What gcss_read_state copies back (for tests and diagnostics). */
+typedef enum {
+  GCSS_STATE_F0 = 0,    /* n doubles: initial f                                 */
+  GCSS_STATE_G0 = 1,    /* n doubles: initial g                                 */
+  GCSS_STATE_F = 2,     /* n doubles: f after the last select                   */
+  GCSS_STATE_G = 3,     /* n doubles: g after the last select                   */
+  GCSS_STATE_Q = 4,     /* m*t doubles: orthonormal basis of the picks (col-major, ld m) */
+  GCSS_STATE_Z = 5,     /* m floats: z of the last completed step               */
+  GCSS_STATE_B = 6,     /* m*r floats: the explicit target (col-major, ld m)    */
+  GCSS_STATE_GRAM = 7,  /* m*m floats: the Gram target A A^T (self target)      */
+  GCSS_STATE_NREJECT = 8 /* 1 int32: picks rejected by the basis check          */
+} gcss_state_item;
+
+/*
+ * Copy an internal array of the context to host memory (synchronizes).
+ * host: host buffer of `bytes` bytes; the copy is truncated to the item's
+ * size, and *copied (may be NULL) receives the bytes written.
+ */
+gcss_status gcss_read_state(gcss_ctx *h, int32_t item, void *host, size_t bytes, size_t *copied);
+
+/* Message for the last non-OK status returned on this thread ("" if none). */
+const char *gcss_last_error(void);
+
+/* Library version string. */
+const char *gcss_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GCSS_H */

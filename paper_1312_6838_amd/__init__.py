@@ -1,0 +1,151 @@
+"""Greedy generalized column subset selection on MI355X (gfx950).
+
+The computation lives in the HIP library ``libgcss.so`` (C ABI in
+``include/gcss.h``).  This package only marshals arguments: torch supplies
+device memory and the stream, :mod:`._abi` forwards the calls.
+
+    sel = Selector(A, m, k_max=100, r_max=256)     # A: (n, lda) cuda tensor
+    sel.project_target(Omega)                      # B = A Omega
+    idx, obj, nsel, status = sel.select(100)
+"""
+from __future__ import annotations
+
+from . import _abi
+from ._abi import (  # noqa: F401
+    BF16, ERR_ARG, ERR_DEVICE, ERR_STATE, ERR_UNSUPPORTED, ERR_WORKSPACE, EXPORTS, F32,
+    FP8_E4M3, OK, STATE_B, STATE_F, STATE_F0, STATE_G, STATE_G0, STATE_GRAM, STATE_NREJECT,
+    STATE_Q, STATE_Z, WARN_EXHAUSTED, Desc, GcssError, batched_workspace_size, create, destroy,
+    last_error, load, make_desc, project_target, quantize, read_state, reconstruction_error,
+    select, select_async, select_batched, set_target, version, workspace_size,
+)
+
+__all__ = ["Selector", "quantize_tensor", "load", "version", "GcssError"]
+
+
+def _dtype_code(t):
+    import torch
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype in (torch.bfloat16, torch.int16, torch.uint16):
+        return BF16
+    if t.dtype in (torch.uint8, torch.float8_e4m3fn):
+        return FP8_E4M3
+    raise TypeError(f"unsupported A dtype {t.dtype}")
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+class Selector:
+    """One selection context over a column store A (n, lda) on the GPU.
+
+    Holds references to every tensor the library borrows (A, scales, the
+    workspace, the target) so they outlive the context.
+    """
+
+    def __init__(self, A, m, *, k_max, r_max=0, self_target=False, scales=None, tau=0.0,
+                 stream=None, batched=None):
+        import torch
+        if not A.is_cuda or A.dim() != 2 or not A.is_contiguous():
+            raise ValueError("A must be a contiguous 2-D cuda tensor of shape (n, lda)")
+        load()
+        self.A, self.scales, self.m = A, scales, int(m)
+        n, lda = A.shape
+        self.n, self.lda = int(n), int(lda)
+        self.dtype = _dtype_code(A)
+        self.stream = stream
+        self.desc = make_desc(self.m, self.n, self.lda, self.dtype, A.data_ptr(),
+                              scales.data_ptr() if scales is not None else None, int(k_max),
+                              int(r_max), self_target, tau, _stream_ptr(stream))
+        nbytes = workspace_size(self.desc)
+        if batched is not None:
+            nbytes += batched_workspace_size(self.desc, *batched)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=A.device)
+        self.ws_bytes = nbytes
+        self.h = create(self.desc, self.ws.data_ptr(), nbytes)
+        self.B = None
+        self.r = 0
+
+    # -- targets --
+    def set_target(self, B=None):
+        """B: (r, ldb) float32 column store on the GPU, or None for B = A."""
+        if B is None:
+            set_target(self.h, None, 0, 0)
+            self.B, self.r = None, 0
+        else:
+            r, ldb = B.shape
+            set_target(self.h, B.data_ptr(), int(r), int(ldb))
+            self.B, self.r = B, int(r)
+
+    def project_target(self, Omega, ldb=None):
+        """B = A Omega; Omega (n, r) float32 row-major on the GPU.  Returns B (r, ldb)."""
+        import torch
+        n, r = Omega.shape
+        ldb = ldb or ((self.m + 63) // 64) * 64
+        B = torch.empty(int(r), int(ldb), dtype=torch.float32, device=self.A.device)
+        project_target(self.h, Omega.data_ptr(), int(r), B.data_ptr(), int(ldb))
+        self.B, self.r, self._omega = B, int(r), Omega
+        return B
+
+    # -- selection --
+    def select(self, k):
+        return select(self.h, int(k))
+
+    def select_async(self, k, out=None):
+        """Device outputs (idx int64[k], obj float64[k+1], nsel int32[1]); no sync."""
+        import torch
+        if out is None:
+            dev = self.A.device
+            out = (torch.empty(k, dtype=torch.int64, device=dev),
+                   torch.empty(k + 1, dtype=torch.float64, device=dev),
+                   torch.empty(1, dtype=torch.int32, device=dev))
+        select_async(self.h, int(k), out[0].data_ptr(), out[1].data_ptr(), out[2].data_ptr())
+        return out
+
+    def reconstruction_error(self, idx):
+        return reconstruction_error(self.h, idx)
+
+    def select_batched(self, col_off, k_block, k_merge):
+        return select_batched(self.h, col_off, int(k_block), int(k_merge))
+
+    def read(self, item, count, np_dtype):
+        import numpy as np
+        raw = read_state(self.h, item, int(count) * np.dtype(np_dtype).itemsize)
+        return np.frombuffer(raw, dtype=np_dtype).copy()
+
+    def close(self):
+        if getattr(self, "h", None):
+            destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def quantize_tensor(A32, m, dtype, stream=None):
+    """Quantize a float32 column store (n, lda) on the GPU.
+
+    dtype "bf16" -> (codes uint16-as-int16 (n, ldo), None);
+    dtype "fp8"  -> (codes uint8 (n, ldo), scales float32 (n,)).
+    """
+    import torch
+    n, lda = A32.shape
+    if dtype == "bf16":
+        ldo = ((m + 127) // 128) * 128
+        out = torch.zeros(n, ldo, dtype=torch.int16, device=A32.device)
+        quantize(A32.data_ptr(), m, n, lda, BF16, out.data_ptr(), ldo, None, _stream_ptr(stream))
+        return out, None
+    if dtype == "fp8":
+        ldo = ((m + 255) // 256) * 256
+        out = torch.zeros(n, ldo, dtype=torch.uint8, device=A32.device)
+        sc = torch.zeros(n, dtype=torch.float32, device=A32.device)
+        quantize(A32.data_ptr(), m, n, lda, FP8_E4M3, out.data_ptr(), ldo, sc.data_ptr(),
+                 _stream_ptr(stream))
+        return out, sc
+    raise ValueError(dtype)

@@ -1,0 +1,194 @@
+"""ctypes binding of libgcss.so (include/gcss.h).  Argument marshalling only:
+every computation runs in the HIP library.  The library is loaded from this
+package's directory; a missing library raises instead of falling back.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgcss.so")
+
+OK = 0
+WARN_EXHAUSTED = 1
+ERR_ARG = -1
+ERR_STATE = -2
+ERR_DEVICE = -3
+ERR_WORKSPACE = -4
+ERR_UNSUPPORTED = -5
+
+F32 = 0
+BF16 = 1
+FP8_E4M3 = 2
+
+STATE_F0, STATE_G0, STATE_F, STATE_G, STATE_Q, STATE_Z, STATE_B, STATE_GRAM, STATE_NREJECT = range(9)
+
+EXPORTS = [
+    "gcss_workspace_size", "gcss_create", "gcss_destroy", "gcss_set_target",
+    "gcss_project_target", "gcss_select", "gcss_select_async", "gcss_reconstruction_error",
+    "gcss_select_batched", "gcss_batched_workspace_size", "gcss_quantize", "gcss_read_state",
+    "gcss_last_error", "gcss_version",
+]
+
+
+class GcssError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"gcss status {status}: {msg}")
+        self.status = status
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [
+        ("m", ctypes.c_int64), ("n", ctypes.c_int64), ("lda", ctypes.c_int64),
+        ("a_dtype", ctypes.c_int32), ("a", ctypes.c_void_p), ("a_scale", ctypes.c_void_p),
+        ("k_max", ctypes.c_int32), ("r_max", ctypes.c_int64), ("self_target", ctypes.c_int32),
+        ("reserved", ctypes.c_int32), ("tau", ctypes.c_double), ("stream", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+_i64, _i32, _vp, _dbl, _sz = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_double, ctypes.c_size_t
+_P = ctypes.POINTER
+
+
+def load():
+    """Load libgcss.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1312_6838_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    st = ctypes.c_int
+    lib.gcss_workspace_size.argtypes = [_P(Desc), _P(_sz)]
+    lib.gcss_workspace_size.restype = st
+    lib.gcss_create.argtypes = [_P(Desc), _vp, _sz, _P(_vp)]
+    lib.gcss_create.restype = st
+    lib.gcss_destroy.argtypes = [_vp]
+    lib.gcss_destroy.restype = None
+    lib.gcss_set_target.argtypes = [_vp, _vp, _i64, _i64]
+    lib.gcss_set_target.restype = st
+    lib.gcss_project_target.argtypes = [_vp, _vp, _i64, _vp, _i64]
+    lib.gcss_project_target.restype = st
+    lib.gcss_select.argtypes = [_vp, _i32, _vp, _vp, _vp]
+    lib.gcss_select.restype = st
+    lib.gcss_select_async.argtypes = [_vp, _i32, _vp, _vp, _vp]
+    lib.gcss_select_async.restype = st
+    lib.gcss_reconstruction_error.argtypes = [_vp, _vp, _i32, _vp]
+    lib.gcss_reconstruction_error.restype = st
+    lib.gcss_select_batched.argtypes = [_vp, _i32, _vp, _i32, _i32, _vp, _vp, _vp, _vp]
+    lib.gcss_select_batched.restype = st
+    lib.gcss_batched_workspace_size.argtypes = [_P(Desc), _i32, _i32, _i32, _P(_sz)]
+    lib.gcss_batched_workspace_size.restype = st
+    lib.gcss_quantize.argtypes = [_vp, _i64, _i64, _i64, _i32, _vp, _i64, _vp, _vp]
+    lib.gcss_quantize.restype = st
+    lib.gcss_read_state.argtypes = [_vp, _i32, _vp, _sz, _P(_sz)]
+    lib.gcss_read_state.restype = st
+    lib.gcss_last_error.argtypes = []
+    lib.gcss_last_error.restype = ctypes.c_char_p
+    lib.gcss_version.argtypes = []
+    lib.gcss_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def last_error() -> str:
+    return load().gcss_last_error().decode()
+
+
+def version() -> str:
+    return load().gcss_version().decode()
+
+
+def _check(status, allow=(OK,)):
+    if status not in allow:
+        raise GcssError(status, last_error())
+    return status
+
+
+def make_desc(m, n, lda, a_dtype, a_ptr, scale_ptr, k_max, r_max, self_target, tau=0.0,
+              stream=0) -> Desc:
+    return Desc(m, n, lda, a_dtype, a_ptr, scale_ptr, k_max, r_max, int(bool(self_target)), 0,
+                float(tau), stream)
+
+
+def workspace_size(desc: Desc) -> int:
+    out = _sz(0)
+    _check(load().gcss_workspace_size(ctypes.byref(desc), ctypes.byref(out)))
+    return out.value
+
+
+def create(desc: Desc, ws_ptr: int, ws_bytes: int) -> int:
+    h = _vp(0)
+    _check(load().gcss_create(ctypes.byref(desc), ws_ptr, ws_bytes, ctypes.byref(h)))
+    return h.value
+
+
+def destroy(h: int) -> None:
+    load().gcss_destroy(h)
+
+
+def set_target(h: int, b_ptr: int | None, r: int, ldb: int) -> None:
+    _check(load().gcss_set_target(h, b_ptr, r, ldb))
+
+
+def project_target(h: int, omega_ptr: int, r: int, b_ptr: int, ldb: int) -> None:
+    _check(load().gcss_project_target(h, omega_ptr, r, b_ptr, ldb))
+
+
+def select(h: int, k: int):
+    """Returns (idx int64[k], objective float64[k+1], n_selected, status)."""
+    idx = np.full(k, -1, dtype=np.int64)
+    obj = np.zeros(k + 1, dtype=np.float64)
+    ns = _i32(0)
+    s = _check(load().gcss_select(h, k, idx.ctypes.data, obj.ctypes.data, ctypes.byref(ns)),
+               allow=(OK, WARN_EXHAUSTED))
+    return idx, obj, ns.value, s
+
+
+def select_async(h: int, k: int, d_idx: int, d_obj: int | None, d_nsel: int | None) -> None:
+    _check(load().gcss_select_async(h, k, d_idx, d_obj, d_nsel))
+
+
+def reconstruction_error(h: int, idx) -> float:
+    idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int64))
+    err = ctypes.c_double(0.0)
+    _check(load().gcss_reconstruction_error(h, idx.ctypes.data if idx.size else None,
+                                            int(idx.size), ctypes.byref(err)))
+    return err.value
+
+
+def batched_workspace_size(desc: Desc, nblocks: int, k_block: int, k_merge: int) -> int:
+    out = _sz(0)
+    _check(load().gcss_batched_workspace_size(ctypes.byref(desc), nblocks, k_block, k_merge,
+                                              ctypes.byref(out)))
+    return out.value
+
+
+def select_batched(h: int, col_off, k_block: int, k_merge: int):
+    """Returns (idx_block (nblocks, k_block), idx_merge, obj_merge, n_merge, status)."""
+    col_off = np.ascontiguousarray(np.asarray(col_off, dtype=np.int64))
+    nb = col_off.size - 1
+    ib = np.full(nb * k_block, -1, dtype=np.int64)
+    im = np.full(k_merge, -1, dtype=np.int64)
+    om = np.zeros(k_merge + 1, dtype=np.float64)
+    nm = _i32(0)
+    s = _check(load().gcss_select_batched(h, nb, col_off.ctypes.data, k_block, k_merge,
+                                          ib.ctypes.data, im.ctypes.data, om.ctypes.data,
+                                          ctypes.byref(nm)), allow=(OK, WARN_EXHAUSTED))
+    return ib.reshape(nb, k_block), im, om, nm.value, s
+
+
+def quantize(a_ptr: int, m: int, n: int, lda: int, dtype: int, out_ptr: int, ldo: int,
+             scales_ptr: int | None, stream: int = 0) -> None:
+    _check(load().gcss_quantize(a_ptr, m, n, lda, dtype, out_ptr, ldo, scales_ptr, stream))
+
+
+def read_state(h: int, item: int, nbytes: int) -> bytes:
+    buf = (ctypes.c_char * nbytes)()
+    got = _sz(0)
+    _check(load().gcss_read_state(h, item, buf, nbytes, ctypes.byref(got)))
+    return bytes(buf[: got.value])

@@ -1,0 +1,576 @@
+// Host engine behind the C ABI of include/gcss.h: argument checks, the
+// workspace carve, the order of kernel launches of one greedy step, graph
+// capture of the k-step loop, and read-back.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/gcss.h"
+#include "gcss_internal.h"
+
+using namespace gcss;
+
+namespace {
+
+thread_local std::string g_err;
+
+gcss_status fail(gcss_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIPCHK(expr)                                                               \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return fail(GCSS_ERR_DEVICE, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                  __FILE__, __LINE__);                                             \
+  } while (0)
+
+constexpr int kPlanCU = 256;       // CU count used to size the workspace (MI355X)
+constexpr int kSpareSlots = 4;     // extra step slots in a captured loop (rejected picks)
+constexpr double kBasisTau = 1e-13;  // dependence threshold of the basis-only mode
+
+inline size_t up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+inline int64_t ld_for(int64_t m) { return (int64_t)up((size_t)m, 64); }
+
+struct Carve {
+  size_t off = 0;
+  template <typename T>
+  size_t take(size_t count) {
+    size_t o = up(off, 256);
+    off = o + up(count * sizeof(T), 256);
+    return o;
+  }
+};
+
+// Offsets of every workspace region for a description (sizes only).
+struct Layout {
+  size_t f0, g0, f, g, mask0, mask, part, npart, Q, e1, e2, w, q64, q32, z32, c1, c2, c3, ups,
+      st, idx, obj, scal, pick, gram, scratch, total;
+  size_t scratch_bytes;
+  StreamGeo geo;
+  int64_t ldq;
+};
+
+bool make_layout(const gcss_desc *d, int num_cu, Layout *L) {
+  const int64_t m = d->m, n = d->n, k = d->k_max, r = d->r_max;
+  L->ldq = ld_for(m);
+  L->geo = stream_geometry(m, n, d->a_dtype, num_cu);
+  if (L->geo.nj == 0) return false;
+  Carve c;
+  L->f0 = c.take<double>(n);
+  L->g0 = c.take<double>(n);
+  L->f = c.take<double>(n);
+  L->g = c.take<double>(n);
+  L->mask0 = c.take<uint8_t>(n);
+  L->mask = c.take<uint8_t>(n);
+  L->part = c.take<ArgPart>(std::max(L->geo.grid, 1));
+  L->npart = c.take<double>(1024);
+  L->Q = c.take<double>((size_t)L->ldq * (k + 1));
+  L->e1 = c.take<double>(L->ldq);
+  L->e2 = c.take<double>(L->ldq);
+  L->w = c.take<double>(L->ldq);
+  L->q64 = c.take<double>(L->ldq);
+  const size_t qlen = std::max<size_t>(L->geo.qlen, L->ldq);
+  L->q32 = c.take<float>(qlen);
+  L->z32 = c.take<float>(qlen);
+  L->c1 = c.take<double>(k + 8);
+  L->c2 = c.take<double>(k + 8);
+  L->c3 = c.take<double>(k + 8);
+  L->ups = c.take<double>(std::max<int64_t>(r, 1) + 8);
+  L->st = c.take<DevState>(1);
+  L->idx = c.take<int64_t>(k + 8);
+  L->obj = c.take<double>(k + 8);
+  L->scal = c.take<double>(64);
+  L->pick = c.take<int64_t>(k + 8);
+  L->gram = d->self_target ? c.take<float>((size_t)L->ldq * m) : 0;
+  // transient scratch: split-K partials, or the reconstruction-error buffers
+  size_t s = 0;
+  if (d->self_target) s = std::max(s, gram_scratch_bytes(m, n, L->ldq, num_cu));
+  if (r > 0) s = std::max(s, proj_scratch_bytes(m, n, r, num_cu));
+  const size_t err_bytes = up((size_t)std::max<int64_t>(r, 1) * 8, 256) +
+                           up((size_t)L->ldq * k * 4, 256) + 3 * up((size_t)(k + 8) * 8, 256);
+  s = std::max(s, err_bytes);
+  L->scratch_bytes = s;
+  L->scratch = c.take<uint8_t>(s);
+  L->total = up(c.off, 256);
+  return true;
+}
+
+gcss_status check_desc(const gcss_desc *d) {
+  if (!d) return fail(GCSS_ERR_ARG, "null descriptor");
+  if (d->m < 1 || d->n < 1) return fail(GCSS_ERR_ARG, "m and n must be >= 1");
+  if (d->a_dtype < GCSS_F32 || d->a_dtype > GCSS_FP8_E4M3)
+    return fail(GCSS_ERR_ARG, "unknown a_dtype %d", d->a_dtype);
+  const int es = dtype_bytes(d->a_dtype);
+  if (d->lda < d->m) return fail(GCSS_ERR_ARG, "lda (%lld) < m (%lld)", (long long)d->lda, (long long)d->m);
+  if ((d->lda * es) % 16 != 0) return fail(GCSS_ERR_ARG, "lda * element size must be a multiple of 16 bytes");
+  if (d->k_max < 1 || d->k_max > d->n) return fail(GCSS_ERR_ARG, "k_max must be in [1, n]");
+  if (d->r_max < 0) return fail(GCSS_ERR_ARG, "r_max must be >= 0");
+  if (d->reserved != 0) return fail(GCSS_ERR_ARG, "reserved must be 0");
+  if (d->m > 8192) return fail(GCSS_ERR_UNSUPPORTED, "m = %lld exceeds 8192", (long long)d->m);
+  if (!d->self_target && d->r_max == 0)
+    return fail(GCSS_ERR_ARG, "neither an explicit target (r_max) nor the self target reserved");
+  return GCSS_OK;
+}
+
+}  // namespace
+
+struct gcss_ctx {
+  int device = 0;
+  int num_cu = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;
+  AView A{};
+  gcss_desc d{};
+  Layout L{};
+  char *ws = nullptr;
+  int target = 0;  // 0 none, 1 explicit B, 2 Gram (B = A)
+  const float *B = nullptr;
+  int64_t r = 0, ldb = 0;
+  // last completed selection (host copy), for reuse of its basis
+  std::vector<int64_t> last_idx;
+  bool basis_valid = false;
+  // captured loop
+  hipGraphExec_t graph = nullptr;
+  int graph_k = -1;
+  void *graph_out[3] = {nullptr, nullptr, nullptr};
+
+  template <typename T>
+  T *at(size_t off) const { return (T *)(ws + off); }
+  StepBufs bufs(const int64_t *pick_list = nullptr, int advance = 0) const {
+    StepBufs sb{};
+    sb.st = at<DevState>(L.st);
+    sb.Q = at<double>(L.Q);
+    sb.ldq = L.ldq;
+    sb.q32 = at<float>(L.q32);
+    sb.z32 = at<float>(L.z32);
+    sb.q64 = at<double>(L.q64);
+    sb.g0 = at<double>(L.g0);
+    sb.mask = at<uint8_t>(L.mask);
+    sb.idx = at<int64_t>(L.idx);
+    sb.obj = at<double>(L.obj);
+    sb.part = at<double>(L.npart);
+    sb.pick_list = pick_list;
+    sb.advance = advance;
+    return sb;
+  }
+  double *F0() const { return at<double>(L.scal); }
+  double *err_dev() const { return at<double>(L.scal) + 1; }
+};
+
+namespace {
+
+void drop_graph(gcss_ctx *h) {
+  if (h->graph) (void)hipGraphExecDestroy(h->graph);
+  h->graph = nullptr;
+  h->graph_k = -1;
+}
+
+// Gram-Schmidt of column p (state) against the basis, with one re-orthogonalisation.
+hipError_t enqueue_basis_step(gcss_ctx *h, const StepBufs &sb) {
+  const int64_t m = h->d.m, ldq = h->L.ldq;
+  const int kmax = h->d.k_max;
+  double *Q = h->at<double>(h->L.Q);
+  double *e1 = h->at<double>(h->L.e1), *e2 = h->at<double>(h->L.e2);
+  double *c1 = h->at<double>(h->L.c1), *c2 = h->at<double>(h->L.c2);
+  hipStream_t s = h->stream;
+  hipError_t e;
+  if ((e = launch_cols(Q, nullptr, ldq, m, 1, 0, kmax, VEC_ACOL, nullptr, h->A, c1, CF_NONE, sb, s))) return e;
+  if ((e = launch_rows(Q, nullptr, ldq, m, 1, 0, VEC_ACOL, nullptr, h->A, c1, e1, nullptr, RF_NONE, sb, s))) return e;
+  if ((e = launch_cols(Q, nullptr, ldq, m, 1, 0, kmax, VEC_F64, e1, h->A, c2, CF_NONE, sb, s))) return e;
+  return launch_rows(Q, nullptr, ldq, m, 1, 0, VEC_F64, e1, h->A, c2, e2, nullptr, RF_GS2, sb, s);
+}
+
+// One greedy step: basis update, target ops, fused stream.
+hipError_t enqueue_step(gcss_ctx *h) {
+  const StepBufs sb = h->bufs();
+  const int64_t m = h->d.m, ldq = h->L.ldq;
+  const int kmax = h->d.k_max;
+  double *Q = h->at<double>(h->L.Q);
+  double *w = h->at<double>(h->L.w), *q64 = h->at<double>(h->L.q64);
+  double *c3 = h->at<double>(h->L.c3), *ups = h->at<double>(h->L.ups);
+  hipStream_t s = h->stream;
+  hipError_t e;
+  if ((e = enqueue_basis_step(h, sb))) return e;
+  if (h->target == 1) {
+    // upsilon = B^T q, ||upsilon||^2 ; w = B upsilon
+    if ((e = launch_cols(nullptr, h->B, h->ldb, m, 0, (int)h->r, (int)h->r, VEC_F64, q64, h->A, ups, CF_UPS, sb, s))) return e;
+    if ((e = launch_rows(nullptr, h->B, h->ldb, m, 0, (int)h->r, -1, nullptr, h->A, ups, w, nullptr, RF_NONE, sb, s))) return e;
+    // c3 = Q_{t-1}^T w
+    if ((e = launch_cols(Q, nullptr, ldq, m, 1, 0, kmax, VEC_F64, w, h->A, c3, CF_NONE, sb, s))) return e;
+  } else {
+    // w = (A A^T) q ; c3 = [Q_{t-1} q]^T w, ||upsilon||^2 = q . w
+    const float *C = h->at<float>(h->L.gram);
+    if ((e = launch_cols(nullptr, C, ldq, m, 0, (int)m, (int)m, VEC_F64, q64, h->A, w, CF_NONE, sb, s))) return e;
+    if ((e = launch_cols(Q, nullptr, ldq, m, 1, 1, kmax + 1, VEC_F64, w, h->A, c3, CF_GRAM_U2, sb, s))) return e;
+  }
+  // z = w - Q_{t-1} c3 ; record the pick
+  if ((e = launch_rows(Q, nullptr, ldq, m, 1, 0, VEC_F64, w, h->A, c3, nullptr, h->at<float>(h->L.z32), RF_Z, sb, s))) return e;
+  return launch_stream(h->L.geo, h->A, h->at<float>(h->L.q32), h->at<float>(h->L.z32),
+                       h->at<double>(h->L.f), h->at<double>(h->L.g), h->at<double>(h->L.g0),
+                       h->at<uint8_t>(h->L.mask), h->at<ArgPart>(h->L.part), sb.st, 0, s);
+}
+
+hipError_t enqueue_begin(gcss_ctx *h, int k) {
+  const StepBufs sb = h->bufs();
+  hipError_t e = launch_select_begin(h->at<double>(h->L.f0), h->at<double>(h->L.g0),
+                                     h->at<uint8_t>(h->L.mask0), h->at<double>(h->L.f),
+                                     h->at<double>(h->L.g), h->at<uint8_t>(h->L.mask), h->d.n, sb,
+                                     k, h->d.k_max, h->F0(), h->d.tau, h->stream);
+  if (e) return e;
+  // first argmax over the initial scores
+  return launch_stream(h->L.geo, h->A, h->at<float>(h->L.q32), h->at<float>(h->L.z32),
+                       h->at<double>(h->L.f), h->at<double>(h->L.g), h->at<double>(h->L.g0),
+                       h->at<uint8_t>(h->L.mask), h->at<ArgPart>(h->L.part), sb.st, 1, h->stream);
+}
+
+gcss_status check_ctx(gcss_ctx *h) {
+  if (!h) return fail(GCSS_ERR_ARG, "null context");
+  return GCSS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *gcss_last_error(void) { return g_err.c_str(); }
+
+const char *gcss_version(void) { return "gcss-mi355x 0.1 (gfx950)"; }
+
+gcss_status gcss_workspace_size(const gcss_desc *d, size_t *bytes) {
+  gcss_status s = check_desc(d);
+  if (s != GCSS_OK) return s;
+  if (!bytes) return fail(GCSS_ERR_ARG, "null bytes");
+  Layout L;
+  if (!make_layout(d, kPlanCU, &L)) return fail(GCSS_ERR_UNSUPPORTED, "m too large for the stream kernel");
+  *bytes = L.total;
+  return GCSS_OK;
+}
+
+gcss_status gcss_create(const gcss_desc *d, void *workspace, size_t ws_bytes, gcss_ctx **out) {
+  if (!out) return fail(GCSS_ERR_ARG, "null out");
+  *out = nullptr;
+  gcss_status st = check_desc(d);
+  if (st != GCSS_OK) return st;
+  if (!d->a) return fail(GCSS_ERR_ARG, "null A");
+  if (((uintptr_t)d->a) % 16) return fail(GCSS_ERR_ARG, "A must be 16-byte aligned");
+  if (d->a_dtype == GCSS_FP8_E4M3 && !d->a_scale) return fail(GCSS_ERR_ARG, "FP8 A needs a_scale");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+    return fail(GCSS_ERR_DEVICE, "no HIP device");
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, dev));
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(GCSS_ERR_DEVICE, "device %d is %s, not gfx950", dev, prop.gcnArchName);
+  const int num_cu = std::min(prop.multiProcessorCount, kPlanCU);
+  Layout L;
+  if (!make_layout(d, num_cu, &L)) return fail(GCSS_ERR_UNSUPPORTED, "m too large for the stream kernel");
+  if (!workspace) return fail(GCSS_ERR_WORKSPACE, "null workspace");
+  if (((uintptr_t)workspace) % 256) return fail(GCSS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  if (ws_bytes < L.total)
+    return fail(GCSS_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
+
+  gcss_ctx *h = new gcss_ctx();
+  h->device = dev;
+  h->num_cu = num_cu;
+  h->stream = (hipStream_t)d->stream;
+  h->d = *d;
+  if (!(h->d.tau > 0.0)) h->d.tau = 1e-4;
+  h->L = L;
+  h->ws = (char *)workspace;
+  h->A.a = d->a;
+  h->A.scale = d->a_scale;
+  h->A.m = d->m;
+  h->A.n = d->n;
+  h->A.lda = d->lda;
+  h->A.dtype = d->a_dtype;
+  const size_t qlen = std::max<size_t>(L.geo.qlen, L.ldq);
+  hipError_t e = launch_zero_f32(h->at<float>(L.q32), (int64_t)qlen, h->stream);
+  if (!e) e = launch_zero_f32(h->at<float>(L.z32), (int64_t)qlen, h->stream);
+  if (e) {
+    delete h;
+    return fail(GCSS_ERR_DEVICE, "init: %s", hipGetErrorString(e));
+  }
+  *out = h;
+  return GCSS_OK;
+}
+
+void gcss_destroy(gcss_ctx *h) {
+  if (!h) return;
+  drop_graph(h);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+  delete h;
+}
+
+gcss_status gcss_set_target(gcss_ctx *h, const float *b, int64_t r, int64_t ldb) {
+  if (check_ctx(h)) return GCSS_ERR_ARG;
+  const int64_t m = h->d.m;
+  if (b == nullptr && r == 0) {
+    if (!h->d.self_target) return fail(GCSS_ERR_STATE, "self target not reserved at creation");
+    float *C = h->at<float>(h->L.gram);
+    HIPCHK(launch_gram(h->A, C, h->L.ldq, h->at<void>(h->L.scratch), h->num_cu, h->stream));
+    HIPCHK(launch_init_gram(C, h->L.ldq, h->A, h->at<double>(h->L.f0), h->at<double>(h->L.g0),
+                            h->at<uint8_t>(h->L.mask0), h->stream));
+    HIPCHK(launch_sum_f64(h->at<double>(h->L.g0), h->d.n, h->F0(), h->stream));
+    h->target = 2;
+    h->B = nullptr;
+    h->r = 0;
+    h->ldb = 0;
+  } else {
+    if (!b) return fail(GCSS_ERR_ARG, "null B with r = %lld", (long long)r);
+    if (r < 1 || r > h->d.r_max) return fail(GCSS_ERR_ARG, "r = %lld outside [1, r_max = %lld]", (long long)r, (long long)h->d.r_max);
+    if (ldb < m || (ldb * 4) % 16) return fail(GCSS_ERR_ARG, "ldb must be >= m and a multiple of 4");
+    if (((uintptr_t)b) % 16) return fail(GCSS_ERR_ARG, "B must be 16-byte aligned");
+    HIPCHK(launch_init_factor(b, ldb, r, h->A, h->at<double>(h->L.f0), h->at<double>(h->L.g0),
+                              h->at<uint8_t>(h->L.mask0), h->stream));
+    HIPCHK(launch_sumsq_f32(b, m, r, ldb, h->F0(), h->stream));
+    h->target = 1;
+    h->B = b;
+    h->r = r;
+    h->ldb = ldb;
+  }
+  h->basis_valid = false;
+  drop_graph(h);
+  return GCSS_OK;
+}
+
+gcss_status gcss_project_target(gcss_ctx *h, const float *omega, int64_t r, float *b_out,
+                                int64_t ldb) {
+  if (check_ctx(h)) return GCSS_ERR_ARG;
+  if (!omega || !b_out) return fail(GCSS_ERR_ARG, "null omega or b_out");
+  if (r < 1 || r > h->d.r_max) return fail(GCSS_ERR_ARG, "r outside [1, r_max]");
+  if (ldb < h->d.m || (ldb * 4) % 16) return fail(GCSS_ERR_ARG, "ldb must be >= m and a multiple of 4");
+  if (((uintptr_t)omega) % 16 || ((uintptr_t)b_out) % 16) return fail(GCSS_ERR_ARG, "omega and b_out must be 16-byte aligned");
+  HIPCHK(launch_project(h->A, omega, r, b_out, ldb, h->at<void>(h->L.scratch), h->num_cu, h->stream));
+  return gcss_set_target(h, b_out, r, ldb);
+}
+
+gcss_status gcss_select(gcss_ctx *h, int32_t k, int64_t *idx, double *objective,
+                        int32_t *n_selected) {
+  if (check_ctx(h)) return GCSS_ERR_ARG;
+  if (!idx) return fail(GCSS_ERR_ARG, "null idx");
+  if (k < 1 || k > h->d.k_max) return fail(GCSS_ERR_ARG, "k = %d outside [1, k_max = %d]", k, h->d.k_max);
+  if (!h->target) return fail(GCSS_ERR_STATE, "no target set");
+  HIPCHK(enqueue_begin(h, k));
+  DevState hs;
+  int slots = k;
+  for (int round = 0; round < 64; ++round) {
+    for (int i = 0; i < slots; ++i) HIPCHK(enqueue_step(h));
+    HIPCHK(hipMemcpyAsync(&hs, h->at<DevState>(h->L.st), sizeof hs, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    if (hs.done) break;
+    slots = k - hs.t;  // picks were rejected: run the missing steps
+    if (slots < 1) slots = 1;
+  }
+  std::vector<int64_t> hidx(k);
+  std::vector<double> hobj(k + 1);
+  HIPCHK(hipMemcpyAsync(hidx.data(), h->at<int64_t>(h->L.idx), sizeof(int64_t) * k, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipMemcpyAsync(hobj.data(), h->at<double>(h->L.obj), sizeof(double) * (k + 1), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  const int t = hs.t;
+  for (int s = 0; s < k; ++s) idx[s] = s < t ? hidx[s] : -1;
+  if (objective) {
+    objective[0] = hobj[0];
+    for (int s = 0; s < k; ++s) objective[s + 1] = s < t ? hobj[s + 1] : hobj[t];
+  }
+  if (n_selected) *n_selected = t;
+  h->last_idx.assign(hidx.begin(), hidx.begin() + t);
+  h->basis_valid = true;
+  return hs.exhausted ? GCSS_WARN_EXHAUSTED : GCSS_OK;
+}
+
+gcss_status gcss_select_async(gcss_ctx *h, int32_t k, int64_t *d_idx, double *d_obj,
+                              int32_t *d_nsel) {
+  if (check_ctx(h)) return GCSS_ERR_ARG;
+  if (!d_idx) return fail(GCSS_ERR_ARG, "null d_idx");
+  if (k < 1 || k > h->d.k_max) return fail(GCSS_ERR_ARG, "k = %d outside [1, k_max = %d]", k, h->d.k_max);
+  if (!h->target) return fail(GCSS_ERR_STATE, "no target set");
+  const bool reuse = h->graph && h->graph_k == k && h->graph_out[0] == (void *)d_idx &&
+                     h->graph_out[1] == (void *)d_obj && h->graph_out[2] == (void *)d_nsel;
+  if (!reuse) {
+    drop_graph(h);
+    if (!h->cap_stream) HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    hipStream_t user = h->stream;
+    h->stream = h->cap_stream;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeRelaxed);
+    if (!e) e = enqueue_begin(h, k);
+    for (int i = 0; !e && i < k + kSpareSlots; ++i) e = enqueue_step(h);
+    if (!e) e = launch_finish(h->bufs(), k, d_idx, d_obj, d_nsel, h->cap_stream);
+    hipError_t e2 = hipStreamEndCapture(h->cap_stream, &g);
+    h->stream = user;
+    if (e || e2) {
+      if (g) (void)hipGraphDestroy(g);
+      return fail(GCSS_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e ? e : e2));
+    }
+    e = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e) {
+      h->graph = nullptr;
+      return fail(GCSS_ERR_DEVICE, "graph instantiate: %s", hipGetErrorString(e));
+    }
+    h->graph_k = k;
+    h->graph_out[0] = d_idx;
+    h->graph_out[1] = d_obj;
+    h->graph_out[2] = d_nsel;
+  }
+  HIPCHK(hipGraphLaunch(h->graph, h->stream));
+  h->basis_valid = false;  // the host does not know the picks
+  return GCSS_OK;
+}
+
+gcss_status gcss_reconstruction_error(gcss_ctx *h, const int64_t *idx, int32_t k, double *err) {
+  if (check_ctx(h)) return GCSS_ERR_ARG;
+  if (!err) return fail(GCSS_ERR_ARG, "null err");
+  if (!h->target) return fail(GCSS_ERR_STATE, "no target set");
+  if (k < 0 || k > h->d.k_max) return fail(GCSS_ERR_ARG, "k = %d outside [0, k_max]", k);
+  if (k > 0 && !idx) return fail(GCSS_ERR_ARG, "null idx");
+  std::vector<int64_t> v(idx, idx + k);
+  for (int s = 0; s < k; ++s)
+    if (v[s] < 0 || v[s] >= h->d.n) return fail(GCSS_ERR_ARG, "idx[%d] = %lld out of range", s, (long long)v[s]);
+  {
+    std::vector<int64_t> sorted(v);
+    std::sort(sorted.begin(), sorted.end());
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+      return fail(GCSS_ERR_ARG, "idx has repeated columns");
+  }
+  const int64_t m = h->d.m, ldq = h->L.ldq;
+  hipStream_t s = h->stream;
+  int kb = k;  // basis size
+  const bool reuse = h->basis_valid && k <= (int)h->last_idx.size() &&
+                     std::equal(v.begin(), v.end(), h->last_idx.begin());
+  if (!reuse && k > 0) {
+    int64_t *pick = h->at<int64_t>(h->L.pick);
+    HIPCHK(hipMemcpyAsync(pick, v.data(), sizeof(int64_t) * k, hipMemcpyHostToDevice, s));
+    const StepBufs sb = h->bufs(pick, 1);
+    // fresh state in basis-only mode
+    HIPCHK(launch_select_begin(h->at<double>(h->L.f0), h->at<double>(h->L.g0), h->at<uint8_t>(h->L.mask0),
+                               h->at<double>(h->L.f), h->at<double>(h->L.g), h->at<uint8_t>(h->L.mask),
+                               h->d.n, sb, k, h->d.k_max, h->F0(), kBasisTau, s));
+    for (int i = 0; i < k; ++i) HIPCHK(enqueue_basis_step(h, sb));
+    DevState hs;
+    HIPCHK(hipMemcpyAsync(&hs, sb.st, sizeof hs, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    kb = hs.t;
+    h->basis_valid = false;
+  }
+  const double *Q = h->at<double>(h->L.Q);
+  char *scr = h->at<char>(h->L.scratch);
+  if (h->target == 1) {
+    double *colerr = (double *)scr;
+    HIPCHK(launch_err_factor(Q, ldq, m, kb, h->B, h->ldb, h->r, colerr, s));
+    HIPCHK(launch_sum_f64(colerr, h->r, h->err_dev(), s));
+  } else if (kb == 0) {
+    HIPCHK(launch_sum_f64(h->F0(), 1, h->err_dev(), s));
+  } else {
+    float *Q32 = (float *)scr;
+    double *quad = (double *)(scr + up((size_t)ldq * h->d.k_max * 4, 256));
+    double *gtmp = quad + up((size_t)(h->d.k_max + 8), 32);
+    uint8_t *mtmp = (uint8_t *)(gtmp + up((size_t)(h->d.k_max + 8), 32));
+    HIPCHK(launch_q_to_f32(Q, ldq, m, kb, Q32, ldq, s));
+    AView qv{Q32, nullptr, m, kb, ldq, DT_F32};
+    HIPCHK(launch_init_gram(h->at<float>(h->L.gram), ldq, qv, quad, gtmp, mtmp, s));
+    HIPCHK(launch_gram_err(h->F0(), quad, kb, h->err_dev(), s));
+  }
+  HIPCHK(hipMemcpyAsync(err, h->err_dev(), sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return GCSS_OK;
+}
+
+gcss_status gcss_batched_workspace_size(const gcss_desc *d, int32_t nblocks, int32_t k_block,
+                                        int32_t k_merge, size_t *bytes) {
+  (void)d;
+  (void)nblocks;
+  (void)k_block;
+  (void)k_merge;
+  (void)bytes;
+  return fail(GCSS_ERR_UNSUPPORTED, "batched selection not built yet");
+}
+
+gcss_status gcss_select_batched(gcss_ctx *h, int32_t nblocks, const int64_t *col_off,
+                                int32_t k_block, int32_t k_merge, int64_t *idx_block,
+                                int64_t *idx_merge, double *obj_merge, int32_t *n_merge) {
+  (void)h;
+  (void)nblocks;
+  (void)col_off;
+  (void)k_block;
+  (void)k_merge;
+  (void)idx_block;
+  (void)idx_merge;
+  (void)obj_merge;
+  (void)n_merge;
+  return fail(GCSS_ERR_UNSUPPORTED, "batched selection not built yet");
+}
+
+gcss_status gcss_quantize(const float *a, int64_t m, int64_t n, int64_t lda, int32_t dtype,
+                          void *out, int64_t ldo, float *scales, void *stream) {
+  if (!a || !out) return fail(GCSS_ERR_ARG, "null a or out");
+  if (m < 1 || n < 1 || lda < m || ldo < m) return fail(GCSS_ERR_ARG, "bad sizes");
+  if (dtype != GCSS_BF16 && dtype != GCSS_FP8_E4M3) return fail(GCSS_ERR_ARG, "dtype must be BF16 or FP8_E4M3");
+  if (dtype == GCSS_FP8_E4M3 && !scales) return fail(GCSS_ERR_ARG, "FP8 needs scales");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(GCSS_ERR_DEVICE, "no HIP device");
+  HIPCHK(launch_quantize(a, m, n, lda, dtype, out, ldo, scales, (hipStream_t)stream));
+  return GCSS_OK;
+}
+
+gcss_status gcss_read_state(gcss_ctx *h, int32_t item, void *host, size_t bytes, size_t *copied) {
+  if (check_ctx(h)) return GCSS_ERR_ARG;
+  if (!host) return fail(GCSS_ERR_ARG, "null host");
+  const int64_t n = h->d.n, m = h->d.m;
+  const void *src = nullptr;
+  size_t sz = 0, spitch = 0, width = 0, rows = 0;
+  DevState hs;
+  HIPCHK(hipMemcpyAsync(&hs, h->at<DevState>(h->L.st), sizeof hs, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  switch (item) {
+    case GCSS_STATE_F0: src = h->at<double>(h->L.f0); sz = 8 * n; break;
+    case GCSS_STATE_G0: src = h->at<double>(h->L.g0); sz = 8 * n; break;
+    case GCSS_STATE_F: src = h->at<double>(h->L.f); sz = 8 * n; break;
+    case GCSS_STATE_G: src = h->at<double>(h->L.g); sz = 8 * n; break;
+    case GCSS_STATE_Q:
+      src = h->at<double>(h->L.Q); spitch = 8 * h->L.ldq; width = 8 * m; rows = hs.t; break;
+    case GCSS_STATE_Z: src = h->at<float>(h->L.z32); sz = 4 * m; break;
+    case GCSS_STATE_B:
+      if (h->target != 1) return fail(GCSS_ERR_STATE, "no explicit target");
+      src = h->B; spitch = 4 * h->ldb; width = 4 * m; rows = h->r; break;
+    case GCSS_STATE_GRAM:
+      if (h->target != 2) return fail(GCSS_ERR_STATE, "no Gram target");
+      src = h->at<float>(h->L.gram); spitch = 4 * h->L.ldq; width = 4 * m; rows = m; break;
+    case GCSS_STATE_NREJECT: src = &hs.n_reject; sz = 4; break;
+    default: return fail(GCSS_ERR_ARG, "unknown item %d", item);
+  }
+  size_t done = 0;
+  if (item == GCSS_STATE_NREJECT) {
+    done = std::min(bytes, sz);
+    memcpy(host, src, done);
+  } else if (width) {
+    const size_t want = width * rows;
+    const size_t nrows = std::min(rows, bytes / (width ? width : 1));
+    if (nrows) HIPCHK(hipMemcpy2DAsync(host, width, src, spitch, width, nrows, hipMemcpyDeviceToHost, h->stream));
+    done = nrows * width;
+    (void)want;
+  } else {
+    done = std::min(bytes, sz);
+    if (done) HIPCHK(hipMemcpyAsync(host, src, done, hipMemcpyDeviceToHost, h->stream));
+  }
+  HIPCHK(hipStreamSynchronize(h->stream));
+  if (copied) *copied = done;
+  return GCSS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,151 @@
+// Internal declarations shared by the HIP sources of the library.
+// Nothing here is part of the public ABI (include/gcss.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+namespace gcss {
+
+// Element codes of the stored source matrix (same values as gcss_dtype).
+enum Dtype : int { DT_F32 = 0, DT_BF16 = 1, DT_FP8 = 2 };
+
+inline int dtype_bytes(int dt) { return dt == DT_F32 ? 4 : (dt == DT_BF16 ? 2 : 1); }
+
+// Per-selection state kept in device memory so that a whole k-step loop can
+// be enqueued (or replayed from a graph) without the host looking at it.
+struct alignas(256) DevState {
+  int32_t t;          // picks made so far
+  int32_t k;          // picks wanted
+  int32_t done;       // 1: no more work (t == k or no candidate left)
+  int32_t exhausted;  // 1: ran out of candidates
+  int32_t skip;       // 1: the current pick was rejected; the step only rescores
+  int32_t n_reject;   // number of rejected picks
+  int32_t pos;        // position in a caller's pick list (basis-only mode)
+  int32_t pad1;
+  int64_t p;          // current pick (-1 none)
+  double F;           // objective after the last completed pick
+  double u2;          // ||upsilon||^2 of the current step
+  double enorm2;      // ||e||^2 of the current pick after re-orthogonalisation
+  double tau;         // eligibility threshold
+  uint32_t cnt[16];   // last-block-done counters (reset by their last block)
+};
+
+// Read-only view of the source matrix for kernels.
+struct AView {
+  const void *a;
+  const float *scale;  // FP8 only
+  int64_t m, n, lda;
+  int dtype;
+};
+
+// Where the vector operand of a column-dot kernel comes from.
+enum VecSrc : int { VEC_F64 = 0, VEC_ACOL = 1 };
+
+// Last-block actions.
+enum ColsFinal : int { CF_NONE = 0, CF_UPS = 1, CF_GRAM_U2 = 2 };
+enum RowsFinal : int { RF_NONE = 0, RF_GS2 = 1, RF_Z = 2 };
+
+// Argmax partial: best candidate of one workgroup.
+struct alignas(16) ArgPart {
+  double score;
+  int64_t idx;
+};
+
+// Stream-kernel launch geometry (chosen once per context).
+struct StreamGeo {
+  int nj;        // 16-byte chunks per lane per wave slice
+  int w;         // waves per team (column slice count)
+  int g;         // columns per team group
+  int grid;      // workgroups
+  int qlen;      // padded length of q32/z32
+};
+
+// ---- launchers (k_stream.hip) ----
+StreamGeo stream_geometry(int64_t m, int64_t n, int dtype, int num_cu);
+hipError_t launch_stream(const StreamGeo &geo, const AView &A, const float *q32,
+                         const float *z32, double *f, double *g, const double *g0,
+                         uint8_t *mask, ArgPart *part, DevState *st, int score_only,
+                         hipStream_t s);
+
+// ---- launchers (k_gemv.hip) ----
+// Buffers of one selection problem that the per-step kernels touch.
+struct StepBufs {
+  DevState *st;
+  double *Q;                   // basis, m x kcap FP64, column-major, ld ldq
+  int64_t ldq;
+  float *q32, *z32;            // stream operands (qlen floats, zero padded)
+  double *q64;                 // q of the current step (m doubles)
+  const double *g0;            // initial g (rejection threshold)
+  uint8_t *mask;               // 0 candidate, 1 selected, 2 excluded
+  int64_t *idx;                // picks (kcap)
+  double *obj;                 // objective (kcap + 1)
+  double *part;                // per-workgroup partial sums (>= 1024)
+  const int64_t *pick_list;    // if set: the pick of step t is pick_list[t]
+  int advance;                 // basis-only mode: the GS2 finish also advances t
+};
+
+// Column dots:  out[s] = sum_{j<m} M[j + s*ldm] * v[j],  s < ns,
+//   ns = (ns_from_t ? st->t : 0) + ns_add; v = vec (VEC_F64) or column p of A
+//   (VEC_ACOL).  M is FP64 (Mq) or FP32 (Mf).  final_mode: CF_*.
+hipError_t launch_cols(const double *Mq, const float *Mf, int64_t ldm, int64_t m,
+                       int ns_from_t, int ns_add, int max_ns, int vsrc, const double *vec,
+                       const AView &A, double *out, int final_mode, const StepBufs &sb,
+                       hipStream_t s);
+// Row updates:  out[j] = v[j] - sum_{s<ns} M[j + s*ldm] * c[s]  (v given), or
+//   out[j] = sum_{s<ns} M[j + s*ldm] * c[s]  (vsrc < 0: no v).  Writes out64
+//   and/or out32.  final_mode: RF_*.
+hipError_t launch_rows(const double *Mq, const float *Mf, int64_t ldm, int64_t m,
+                       int ns_from_t, int ns_add, int vsrc, const double *vec, const AView &A,
+                       const double *c, double *out64, float *out32, int final_mode,
+                       const StepBufs &sb, hipStream_t s);
+// Start of a selection: f = f0, g = g0, mask = mask0, state reset, outputs cleared.
+hipError_t launch_select_begin(const double *f0, const double *g0, const uint8_t *mask0,
+                               double *f, double *g, uint8_t *mask, int64_t n,
+                               const StepBufs &sb, int k, int kcap, const double *F0,
+                               double tau, hipStream_t s);
+// Copy picks/objective (filling past the last pick) to caller buffers.
+hipError_t launch_finish(const StepBufs &sb, int k, int64_t *idx_out, double *obj_out,
+                         int32_t *nsel_out, hipStream_t s);
+// out[0] = sum of x[0..n) (fixed order), FP64
+hipError_t launch_sum_f64(const double *x, int64_t n, double *out, hipStream_t s);
+// out[0] = sum of squares of an m x r FP32 column-major matrix
+hipError_t launch_sumsq_f32(const float *B, int64_t m, int64_t r, int64_t ldb, double *out,
+                            hipStream_t s);
+// Residual of an explicit target on basis Q (k columns):
+//   colerr[c] = || B_c - Q (Q^T B_c) ||^2, FP64
+hipError_t launch_err_factor(const double *Q, int64_t ldq, int64_t m, int k, const float *B,
+                             int64_t ldb, int64_t r, double *colerr, hipStream_t s);
+hipError_t launch_q_to_f32(const double *Q, int64_t ldq, int64_t m, int k, float *Q32,
+                           int64_t ld32, hipStream_t s);
+hipError_t launch_copy_i64(const int64_t *src, int64_t *dst, int64_t n, hipStream_t s);
+// err = trace - sum_{s<k} quad[s]
+hipError_t launch_gram_err(const double *trace, const double *quad, int k, double *err,
+                           hipStream_t s);
+hipError_t launch_zero_f32(float *p, int64_t n, hipStream_t s);
+
+// ---- launchers (k_mfma.hip) ----
+// f0_i = scale_i^2 * || X^T A_i ||^2 (X: m x R, K-contiguous, ldx), g0_i, mask0_i
+hipError_t launch_init_factor(const float *X, int64_t ldx, int64_t R, const AView &A,
+                              double *f0, double *g0, uint8_t *mask0, hipStream_t s);
+// f0_i = scale_i^2 * A_i^T C A_i (C: m x m symmetric, ldc), g0_i, mask0_i
+hipError_t launch_init_gram(const float *C, int64_t ldc, const AView &A, double *f0,
+                            double *g0, uint8_t *mask0, hipStream_t s);
+// C = A A^T (m x m, ldc) using split-K partials in scratch (bytes >= gram_scratch_bytes)
+size_t gram_scratch_bytes(int64_t m, int64_t n, int64_t ldc, int num_cu);
+hipError_t launch_gram(const AView &A, float *C, int64_t ldc, void *scratch, int num_cu,
+                       hipStream_t s);
+// B = A Omega (m x r, ldb); Omega n x r row-major
+size_t proj_scratch_bytes(int64_t m, int64_t n, int64_t r, int num_cu);
+hipError_t launch_project(const AView &A, const float *omega, int64_t r, float *B,
+                          int64_t ldb, void *scratch, int num_cu, hipStream_t s);
+
+// ---- launchers (k_quant.hip) ----
+hipError_t launch_quantize(const float *a, int64_t m, int64_t n, int64_t lda, int dtype,
+                           void *out, int64_t ldo, float *scales, hipStream_t s);
+
+// ---- batched (k_batched.hip) ----
+struct BatchedLayout;
+
+}  // namespace gcss

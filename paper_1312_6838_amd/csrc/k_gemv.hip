@@ -1,0 +1,417 @@
+// Per-step vector kernels of the greedy loop (steps between two streaming
+// passes) and small helpers.
+//
+// One greedy step, q/z form (Theorem 4 restated with an orthonormal basis Q
+// of the picks so far; P = Q Q^T):
+//   e  = A_p - Q (Q^T A_p), repeated once on e     (Gram-Schmidt + re-orth)
+//   q  = e / ||e||        -- rows final: checks ||e||^2 against tau * g0_p
+//   upsilon = B^T q,  ||upsilon||^2 = the exact decrease of the objective
+//   w  = B upsilon  (= B B^T q; with the Gram target w = (A A^T) q)
+//   z  = w - Q (Q^T w)    -- rows final: records the pick and F_t
+// "cols" kernels are the dot products Q^T v, B^T q; "rows" kernels are the
+// updates v - Q c, B c.  All reductions have a fixed order.
+#include "gcss_device.h"
+
+namespace gcss {
+
+template <typename MT, int VSRC>
+__global__ __launch_bounds__(256) void k_cols(const MT *__restrict__ M, int64_t ldm, int64_t m,
+                                              int ns_from_t, int ns_add,
+                                              const double *__restrict__ vec, AView A,
+                                              double *__restrict__ out, int final_mode,
+                                              StepBufs sb) {
+  DevState *st = sb.st;
+  if (st->done || st->skip) return;
+  const int t = st->t;
+  const int ns = (ns_from_t ? t : 0) + ns_add;
+  int64_t p = 0;
+  double ps = 1.0;
+  if constexpr (VSRC == VEC_ACOL) {
+    p = sb.pick_list ? sb.pick_list[st->pos] : st->p;
+    ps = col_scale(A, p);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int s = blockIdx.x * 4 + wave;
+  if (s < ns) {
+    const MT *col = M + (int64_t)s * ldm;
+    double acc = 0.0;
+    for (int64_t j = lane; j < m; j += 64) {
+      double v;
+      if constexpr (VSRC == VEC_ACOL)
+        v = ps * (double)load_elem(A, p, j);
+      else
+        v = vec[j];
+      acc = fma((double)col[j], v, acc);
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) out[s] = acc;
+  }
+  if (final_mode == CF_NONE) return;
+  if (!last_block_arrive(&st->cnt[1])) return;
+  if (threadIdx.x == 0) {
+    double u2 = 0.0;
+    if (final_mode == CF_UPS) {
+      for (int x = 0; x < ns; ++x) {
+        const double v = load_acquire_f64(&out[x]);
+        u2 += v * v;
+      }
+    } else {  // CF_GRAM_U2: the last coefficient is q . (C q)
+      u2 = load_acquire_f64(&out[t]);
+    }
+    st->u2 = u2;
+    st->cnt[1] = 0;
+  }
+}
+
+// VSRC: -1 no base vector, VEC_F64, VEC_ACOL
+template <typename MT, int VSRC>
+__global__ __launch_bounds__(256) void k_rows(const MT *__restrict__ M, int64_t ldm, int64_t m,
+                                              int ns_from_t, int ns_add,
+                                              const double *__restrict__ vec, AView A,
+                                              const double *__restrict__ c, double *out64,
+                                              float *out32, int final_mode, StepBufs sb) {
+  __shared__ double red[4][64];
+  __shared__ double nrm;
+  __shared__ int ok;
+  DevState *st = sb.st;
+  if (st->done || st->skip) return;
+  const int t = st->t;
+  const int ns = (ns_from_t ? t : 0) + ns_add;
+  int64_t p = 0;
+  double ps = 1.0;
+  if constexpr (VSRC == VEC_ACOL) {
+    p = sb.pick_list ? sb.pick_list[st->pos] : st->p;
+    ps = col_scale(A, p);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t j = (int64_t)blockIdx.x * 64 + lane;
+  double acc = 0.0;
+  if (j < m)
+    for (int s = wave; s < ns; s += 4) acc = fma((double)M[j + (int64_t)s * ldm], c[s], acc);
+  red[wave][lane] = acc;
+  __syncthreads();
+  if (wave == 0) {
+    const double sum = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+    double o = 0.0;
+    if (j < m) {
+      if constexpr (VSRC < 0) {
+        o = sum;
+      } else {
+        double v;
+        if constexpr (VSRC == VEC_ACOL)
+          v = ps * (double)load_elem(A, p, j);
+        else
+          v = vec[j];
+        o = v - sum;
+      }
+      if (out64) out64[j] = o;
+      if (out32) out32[j] = (float)o;
+    }
+    const double sq = wave_sum(o * o);
+    if (lane == 0 && final_mode == RF_GS2) sb.part[blockIdx.x] = sq;
+  }
+  if (final_mode == RF_NONE) return;
+  if (!last_block_arrive(&st->cnt[2])) return;
+
+  if (final_mode == RF_GS2) {
+    // ||e||^2, basis check, q = e / ||e||
+    if (threadIdx.x == 0) {
+      double s2 = 0.0;
+      for (int x = 0; x < (int)gridDim.x; ++x) s2 += load_acquire_f64(&sb.part[x]);
+      const int64_t pp = sb.pick_list ? sb.pick_list[st->pos] : st->p;
+      const int good = isfinite(s2) && s2 > st->tau * sb.g0[pp];
+      nrm = s2;
+      ok = good;
+      st->enorm2 = s2;
+      if (!good && !sb.advance) {
+        sb.mask[pp] = 2;
+        st->skip = 1;
+        st->n_reject += 1;
+      }
+      st->cnt[2] = 0;
+    }
+    __syncthreads();
+    if (ok) {
+      const double inv = 1.0 / sqrt(nrm);
+      for (int64_t jj = threadIdx.x; jj < m; jj += blockDim.x) {
+        const double qv = load_acquire_f64(&out64[jj]) * inv;
+        sb.Q[(int64_t)t * sb.ldq + jj] = qv;
+        sb.q64[jj] = qv;
+        sb.q32[jj] = (float)qv;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && sb.advance) {
+      // basis-only mode: walk the caller's pick list; dependent columns add nothing
+      if (ok) st->t = t + 1;
+      st->pos += 1;
+    }
+  } else if (final_mode == RF_Z) {
+    if (threadIdx.x == 0) {
+      const int64_t pp = st->p;
+      const double F = st->F - st->u2;
+      st->F = F;
+      sb.obj[t + 1] = F;
+      sb.idx[t] = pp;
+      sb.mask[pp] = 1;
+      st->t = t + 1;
+      if (t + 1 >= st->k) st->done = 1;
+      st->cnt[2] = 0;
+    }
+  }
+}
+
+__global__ void k_select_begin(const double *__restrict__ f0, const double *__restrict__ g0,
+                               const uint8_t *__restrict__ mask0, double *__restrict__ f,
+                               double *__restrict__ g, uint8_t *__restrict__ mask, int64_t n,
+                               StepBufs sb, int k, int kcap, const double *F0, double tau) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    f[i] = f0[i];
+    g[i] = g0[i];
+    mask[i] = mask0[i];
+  }
+  if (blockIdx.x == 0) {
+    const double F = *F0;
+    for (int x = threadIdx.x; x < kcap; x += blockDim.x) sb.idx[x] = -1;
+    for (int x = threadIdx.x; x <= kcap; x += blockDim.x) sb.obj[x] = F;
+    if (threadIdx.x == 0) {
+      DevState *st = sb.st;
+      st->t = 0;
+      st->k = k;
+      st->done = 0;
+      st->exhausted = 0;
+      st->skip = 0;
+      st->n_reject = 0;
+      st->pos = 0;
+      st->pad1 = 0;
+      st->p = -1;
+      st->F = F;
+      st->u2 = 0.0;
+      st->enorm2 = 0.0;
+      st->tau = tau;
+      for (int x = 0; x < 16; ++x) st->cnt[x] = 0;
+    }
+  }
+}
+
+__global__ void k_finish(StepBufs sb, int k, int64_t *idx_out, double *obj_out,
+                         int32_t *nsel_out) {
+  const int t = sb.st->t;
+  for (int s = threadIdx.x; s < k; s += blockDim.x) {
+    if (idx_out) idx_out[s] = s < t ? sb.idx[s] : -1;
+    if (obj_out) obj_out[s + 1] = s < t ? sb.obj[s + 1] : sb.obj[t];
+  }
+  if (threadIdx.x == 0) {
+    if (obj_out) obj_out[0] = sb.obj[0];
+    if (nsel_out) *nsel_out = t;
+  }
+}
+
+// Fixed-order FP64 sum by one workgroup.
+__global__ __launch_bounds__(256) void k_sum_f64(const double *__restrict__ x, int64_t n,
+                                                 double *out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) s += x[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_sumsq_f32(const float *__restrict__ B, int64_t m,
+                                                   int64_t r, int64_t ldb, double *out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t c = 0; c < r; ++c)
+    for (int64_t j = threadIdx.x; j < m; j += 256) {
+      const double v = B[c * ldb + j];
+      s += v * v;
+    }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+// One workgroup per target column c: colerr[c] = || B_c - Q (Q^T B_c) ||^2.
+__global__ __launch_bounds__(256) void k_err_factor(const double *__restrict__ Q, int64_t ldq,
+                                                    int64_t m, int k,
+                                                    const float *__restrict__ B, int64_t ldb,
+                                                    double *__restrict__ colerr) {
+  extern __shared__ double ys[];
+  __shared__ double red[256];
+  const int64_t c = blockIdx.x;
+  const float *b = B + c * ldb;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int s = wave; s < k; s += 4) {
+    const double *q = Q + (int64_t)s * ldq;
+    double acc = 0.0;
+    for (int64_t j = lane; j < m; j += 64) acc = fma(q[j], (double)b[j], acc);
+    acc = wave_sum(acc);
+    if (lane == 0) ys[s] = acc;
+  }
+  __syncthreads();
+  double e = 0.0;
+  for (int64_t j = threadIdx.x; j < m; j += 256) {
+    double r = (double)b[j];
+    for (int s = 0; s < k; ++s) r = fma(-Q[j + (int64_t)s * ldq], ys[s], r);
+    e = fma(r, r, e);
+  }
+  red[threadIdx.x] = e;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) colerr[c] = red[0];
+}
+
+__global__ void k_q_to_f32(const double *__restrict__ Q, int64_t ldq, int64_t m, int k,
+                           float *__restrict__ Q32, int64_t ld32) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = ld32 * k;
+  if (i >= total) return;
+  const int64_t s = i / ld32, j = i % ld32;
+  Q32[i] = j < m ? (float)Q[s * ldq + j] : 0.f;
+}
+
+__global__ void k_copy_i64(const int64_t *__restrict__ src, int64_t *__restrict__ dst,
+                           int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+__global__ void k_gram_err(const double *trace, const double *quad, int k, double *err) {
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int x = 0; x < k; ++x) s += quad[x];
+    *err = *trace - s;
+  }
+}
+
+__global__ void k_zero_f32(float *p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.f;
+}
+
+// ---------------------------------------------------------------------------
+static inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+template <typename MT>
+static hipError_t cols_t(const MT *M, int64_t ldm, int64_t m, int ns_from_t, int ns_add,
+                         int max_ns, int vsrc, const double *vec, const AView &A, double *out,
+                         int final_mode, const StepBufs &sb, hipStream_t s) {
+  const unsigned grid = blocks_for(max_ns > 0 ? max_ns : 1, 4);
+  if (vsrc == VEC_ACOL)
+    hipLaunchKernelGGL((k_cols<MT, VEC_ACOL>), dim3(grid), dim3(256), 0, s, M, ldm, m, ns_from_t,
+                       ns_add, vec, A, out, final_mode, sb);
+  else
+    hipLaunchKernelGGL((k_cols<MT, VEC_F64>), dim3(grid), dim3(256), 0, s, M, ldm, m, ns_from_t,
+                       ns_add, vec, A, out, final_mode, sb);
+  return hipGetLastError();
+}
+
+hipError_t launch_cols(const double *Mq, const float *Mf, int64_t ldm, int64_t m,
+                       int ns_from_t, int ns_add, int max_ns, int vsrc, const double *vec,
+                       const AView &A, double *out, int final_mode, const StepBufs &sb,
+                       hipStream_t s) {
+  if (Mq) return cols_t<double>(Mq, ldm, m, ns_from_t, ns_add, max_ns, vsrc, vec, A, out,
+                                final_mode, sb, s);
+  return cols_t<float>(Mf, ldm, m, ns_from_t, ns_add, max_ns, vsrc, vec, A, out, final_mode,
+                       sb, s);
+}
+
+template <typename MT>
+static hipError_t rows_t(const MT *M, int64_t ldm, int64_t m, int ns_from_t, int ns_add,
+                         int vsrc, const double *vec, const AView &A, const double *c,
+                         double *out64, float *out32, int final_mode, const StepBufs &sb,
+                         hipStream_t s) {
+  const unsigned grid = blocks_for(m, 64);
+  if (vsrc == VEC_ACOL)
+    hipLaunchKernelGGL((k_rows<MT, VEC_ACOL>), dim3(grid), dim3(256), 0, s, M, ldm, m, ns_from_t,
+                       ns_add, vec, A, c, out64, out32, final_mode, sb);
+  else if (vsrc == VEC_F64)
+    hipLaunchKernelGGL((k_rows<MT, VEC_F64>), dim3(grid), dim3(256), 0, s, M, ldm, m, ns_from_t,
+                       ns_add, vec, A, c, out64, out32, final_mode, sb);
+  else
+    hipLaunchKernelGGL((k_rows<MT, -1>), dim3(grid), dim3(256), 0, s, M, ldm, m, ns_from_t,
+                       ns_add, vec, A, c, out64, out32, final_mode, sb);
+  return hipGetLastError();
+}
+
+hipError_t launch_rows(const double *Mq, const float *Mf, int64_t ldm, int64_t m,
+                       int ns_from_t, int ns_add, int vsrc, const double *vec, const AView &A,
+                       const double *c, double *out64, float *out32, int final_mode,
+                       const StepBufs &sb, hipStream_t s) {
+  if (Mq) return rows_t<double>(Mq, ldm, m, ns_from_t, ns_add, vsrc, vec, A, c, out64, out32,
+                                final_mode, sb, s);
+  return rows_t<float>(Mf, ldm, m, ns_from_t, ns_add, vsrc, vec, A, c, out64, out32,
+                       final_mode, sb, s);
+}
+
+hipError_t launch_select_begin(const double *f0, const double *g0, const uint8_t *mask0,
+                               double *f, double *g, uint8_t *mask, int64_t n,
+                               const StepBufs &sb, int k, int kcap, const double *F0,
+                               double tau, hipStream_t s) {
+  hipLaunchKernelGGL(k_select_begin, dim3(blocks_for(n, 256)), dim3(256), 0, s, f0, g0, mask0, f,
+                     g, mask, n, sb, k, kcap, F0, tau);
+  return hipGetLastError();
+}
+
+hipError_t launch_finish(const StepBufs &sb, int k, int64_t *idx_out, double *obj_out,
+                         int32_t *nsel_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, sb, k, idx_out, obj_out, nsel_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_f64(const double *x, int64_t n, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(256), 0, s, x, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sumsq_f32(const float *B, int64_t m, int64_t r, int64_t ldb, double *out,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_sumsq_f32, dim3(1), dim3(256), 0, s, B, m, r, ldb, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_err_factor(const double *Q, int64_t ldq, int64_t m, int k, const float *B,
+                             int64_t ldb, int64_t r, double *colerr, hipStream_t s) {
+  const size_t shm = sizeof(double) * (size_t)(k > 0 ? k : 1);
+  hipLaunchKernelGGL(k_err_factor, dim3((unsigned)r), dim3(256), shm, s, Q, ldq, m, k, B, ldb,
+                     colerr);
+  return hipGetLastError();
+}
+
+hipError_t launch_q_to_f32(const double *Q, int64_t ldq, int64_t m, int k, float *Q32,
+                           int64_t ld32, hipStream_t s) {
+  hipLaunchKernelGGL(k_q_to_f32, dim3(blocks_for(ld32 * k, 256)), dim3(256), 0, s, Q, ldq, m, k,
+                     Q32, ld32);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_i64(const int64_t *src, int64_t *dst, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_i64, dim3(blocks_for(n, 256)), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_err(const double *trace, const double *quad, int k, double *err,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_gram_err, dim3(1), dim3(64), 0, s, trace, quad, k, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_f32(float *p, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_f32, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+}  // namespace gcss

@@ -22,3 +22,8 @@ def gpu():
     import paper_1312_6838_amd as g
     g.load()
     return g
+
+
+def pytest_runtest_logstart(nodeid, location):
+    # name the case before it touches the GPU, so a run that dies still says which
+    print(f"\n[start] {nodeid}", flush=True)

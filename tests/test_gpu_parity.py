@@ -1,0 +1,302 @@
+"""GPU path vs the FP64 oracle, element by element, on seeded inputs.
+
+Tolerances (FP32 arithmetic on the GPU vs FP64 in the oracle):
+  * picks: identical on inputs whose score gaps are separated (planted
+    inputs, or the prefix before the oracle's gap drops below 1e-4);
+  * objective / reconstruction error: relative 1e-5 in FP32 mode;
+  * initial scores: f relative 1e-4 (FP32 matrix-core dot products over
+    up to a few thousand terms), g relative 1e-12 (FP64 sums of squares).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import colstore32, dev, f64cs, rel, stored_dense
+
+pytestmark = pytest.mark.gpu
+
+
+def _sel(gpu, A32, m, **kw):
+    return gpu.Selector(dev(A32), m, **kw)
+
+
+# ---------------------------------------------------------------- a0 / K0 ----
+@pytest.mark.parametrize("m,n", [(37, 50), (500, 300), (1000, 129)])
+def test_quantizers_bit_exact(gpu, m, n):
+    rng = np.random.default_rng(m + n)
+    A = rng.standard_normal((m, n)) * 10.0 ** rng.integers(-6, 6, size=(1, n))
+    A[:, 3] = 0.0
+    A[5 % m, 7] = 1e-30
+    A32 = colstore32(A)
+    codes_ref, sc_ref = oracle.quantize_fp8(A32, m, ldo=((m + 255) // 256) * 256)
+    c, sc = gpu.quantize_tensor(dev(A32), m, "fp8")
+    np.testing.assert_array_equal(sc.cpu().numpy(), sc_ref)
+    np.testing.assert_array_equal(c.cpu().numpy(), codes_ref)
+    h_ref = oracle.quantize_bf16(A32, m, ldo=((m + 127) // 128) * 128)
+    h, _ = gpu.quantize_tensor(dev(A32), m, "bf16")
+    np.testing.assert_array_equal(h.cpu().numpy().view(np.uint16), h_ref)
+
+
+@pytest.mark.parametrize("m,n,r", [(37, 300, 7), (300, 1000, 256), (1000, 700, 130)])
+def test_projection_matches_oracle_dots(gpu, m, n, r):
+    import torch
+    A = synth.gauss_lowrank_dense(m, n, 10, 0.1, seed=m)
+    A32 = colstore32(A)
+    Om = synth.omega_gauss(n, r, seed=r)
+    s = _sel(gpu, A32, m, k_max=4, r_max=r)
+    B = s.project_target(dev(Om)).cpu().numpy()[:, :m].T.astype(np.float64)
+    Bref = stored_dense(A32, m) @ Om.astype(np.float64)
+    # each entry is one FP64 dot of a row of A with a column of Omega
+    scale = np.sqrt(np.sum(stored_dense(A32, m) ** 2, axis=1))[:, None] * np.sqrt(np.sum(Om.astype(np.float64) ** 2, axis=0))[None, :]
+    assert np.max(np.abs(B - Bref) / scale) < 1e-6
+    torch.cuda.synchronize()
+
+
+# ---------------------------------------------------------------- a1 ---------
+@pytest.mark.parametrize("m,n,r,dt", [(37, 70, 3, "f32"), (500, 1000, 64, "f32"), (1000, 300, 256, "f32"),
+                                      (300, 500, 300, "f32"), (600, 400, 130, "bf16"), (700, 333, 40, "fp8")])
+def test_initial_scores_factor(gpu, m, n, r, dt):
+    A = synth.gauss_lowrank_dense(m, n, 8, 0.05, seed=n)
+    A[:, 5] = 0.0
+    A32 = colstore32(A)
+    B = np.random.default_rng(r).standard_normal((m, r))
+    Bcs = colstore32(B)
+    if dt == "f32":
+        Adev, sc, Aval = dev(A32), None, stored_dense(A32, m)
+    else:
+        Adev, sc = gpu.quantize_tensor(dev(A32), m, dt)
+        if dt == "bf16":
+            Aval = oracle.decode_columns(oracle.quantize_bf16(A32, m), m, "bf16").T
+        else:
+            codes, scl = oracle.quantize_fp8(A32, m)
+            Aval = oracle.decode_columns(codes, m, "fp8", scl).T
+    s = gpu.Selector(Adev, m, k_max=4, r_max=r, scales=sc)
+    s.set_target(dev(Bcs))
+    f = s.read(gpu.STATE_F0, n, np.float64)
+    g = s.read(gpu.STATE_G0, n, np.float64)
+    fr, gr = oracle.init_scores(f64cs(Aval), m, B=f64cs(stored_dense(Bcs, m)))
+    np.testing.assert_allclose(g, gr, rtol=1e-12, atol=0)
+    np.testing.assert_allclose(f, fr, rtol=1e-4, atol=1e-6 * fr.max())
+
+
+@pytest.mark.parametrize("m,n", [(37, 90), (500, 1000), (260, 300)])
+def test_initial_scores_self_target(gpu, m, n):
+    A = synth.gauss_lowrank_dense(m, n, 12, 0.05, seed=m)
+    A32 = colstore32(A)
+    s = _sel(gpu, A32, m, k_max=4, self_target=True)
+    s.set_target(None)
+    C = s.read(gpu.STATE_GRAM, m * m, np.float32).reshape(m, m).astype(np.float64)
+    Av = stored_dense(A32, m)
+    Cr = Av @ Av.T
+    assert np.array_equal(C, C.T)  # exactly symmetric
+    np.testing.assert_allclose(C, Cr, rtol=0, atol=1e-5 * np.abs(Cr).max())
+    f = s.read(gpu.STATE_F0, n, np.float64)
+    fr, gr = oracle.init_scores(f64cs(Av), m)
+    np.testing.assert_allclose(f, fr, rtol=1e-4)
+
+
+# ---------------------------------------------------------------- a2-a5 ------
+@pytest.mark.parametrize("target", ["self", "proj"])
+@pytest.mark.parametrize("dt", ["f32", "bf16", "fp8"])
+def test_planted_gap_indices_identical(gpu, target, dt):
+    m, n, k = 256, 3000, 12
+    A, pos = synth.planted_dense(m, n, k, 1.5, seed=5)
+    A32 = colstore32(A)
+    if dt == "f32":
+        Adev, sc, Aval = dev(A32), None, stored_dense(A32, m)
+    elif dt == "bf16":
+        Adev, sc = gpu.quantize_tensor(dev(A32), m, "bf16")
+        Aval = oracle.decode_columns(oracle.quantize_bf16(A32, m), m, "bf16").T
+    else:
+        Adev, sc = gpu.quantize_tensor(dev(A32), m, "fp8")
+        codes, scl = oracle.quantize_fp8(A32, m)
+        Aval = oracle.decode_columns(codes, m, "fp8", scl).T
+    if target == "self":
+        s = gpu.Selector(Adev, m, k_max=k, self_target=True, scales=sc)
+        s.set_target(None)
+        ref = oracle.select(f64cs(Aval), m, k)
+    else:
+        B = Aval @ synth.omega_gauss(n, 256, seed=9).astype(np.float64)
+        Bcs = colstore32(B)
+        s = gpu.Selector(Adev, m, k_max=k, r_max=256, scales=sc)
+        s.set_target(dev(Bcs))
+        ref = oracle.select(f64cs(Aval), m, k, B=f64cs(stored_dense(Bcs, m)))
+    idx, obj, ns, st = s.select(k)
+    assert ns == k and st == gpu.OK
+    assert np.min(ref["gap"]) > 1e-3
+    assert list(idx) == list(ref["idx"])
+    np.testing.assert_allclose(obj, ref["obj"], rtol=1e-5)
+
+
+def _prefix_len(a, b):
+    n = 0
+    for x, y in zip(a, b):
+        if x != y:
+            break
+        n += 1
+    return n
+
+
+@pytest.mark.parametrize("case", ["css_500x1000", "gcss_1000x20000_r128", "ragged_333x4097_r7"])
+def test_selection_matches_oracle(gpu, case):
+    if case == "css_500x1000":
+        m, n, k = 500, 1000, 20
+        A = synth.gauss_lowrank_dense(m, n, 50, 0.01, seed=0)
+        r = 0
+    elif case == "gcss_1000x20000_r128":
+        m, n, k, r = 1000, 20000, 30, 128
+        A = synth.spectral_lowrank_dense(m, n, 256, 0.7, 1e-3, seed=1)
+    else:
+        m, n, k, r = 333, 4097, 25, 7
+        A = synth.gauss_lowrank_dense(m, n, 40, 0.1, seed=2)
+    A32 = colstore32(A)
+    Av = stored_dense(A32, m)
+    if r == 0:
+        s = _sel(gpu, A32, m, k_max=k, self_target=True)
+        s.set_target(None)
+        Bv = None
+    else:
+        Bv = stored_dense(colstore32(Av @ synth.omega_gauss(n, r, seed=3).astype(np.float64)), m)
+        s = _sel(gpu, A32, m, k_max=k, r_max=r)
+        s.set_target(dev(colstore32(Bv)))
+    idx, obj, ns, st = s.select(k)
+    ref = oracle.select(f64cs(Av), m, k, B=None if Bv is None else f64cs(Bv))
+    # identical picks up to the first step whose oracle score gap is below 1e-4
+    sep = int(np.argmax(ref["gap"] < 1e-4)) if np.any(ref["gap"] < 1e-4) else k
+    assert _prefix_len(idx, ref["idx"]) >= sep
+    Bc = None if Bv is None else f64cs(Bv)
+    e_gpu = oracle.error(f64cs(Av), m, idx, B=Bc)
+    e_orc = oracle.error(f64cs(Av), m, ref["idx"], B=Bc)
+    assert rel(e_gpu, e_orc) <= 1e-5
+    # the GPU's recursive objective is the explicit error of every prefix
+    for t in (1, k // 2, k):
+        assert rel(obj[t], oracle.error(f64cs(Av), m, idx[:t], B=Bc)) <= 1e-5
+    assert np.all(np.diff(obj) <= 0)
+    # a7: the library's reconstruction error of its own picks and of the oracle's
+    assert rel(s.reconstruction_error(idx), e_gpu) <= 1e-5
+    assert rel(s.reconstruction_error(ref["idx"]), e_orc) <= 1e-5
+
+
+def test_basis_orthonormal_and_reproducible(gpu):
+    m, n, k, r = 700, 5000, 40, 64
+    A = synth.spectral_lowrank_dense(m, n, 100, 0.5, 1e-3, seed=4)
+    A32 = colstore32(A)
+    B = colstore32(stored_dense(A32, m) @ synth.omega_gauss(n, r, seed=5).astype(np.float64))
+    s = _sel(gpu, A32, m, k_max=k, r_max=r)
+    s.set_target(dev(B))
+    i1, o1, _, _ = s.select(k)
+    Q = s.read(gpu.STATE_Q, m * k, np.float64).reshape(k, m).T
+    assert np.max(np.abs(Q.T @ Q - np.eye(k))) < 1e-13
+    # span(Q) = span(A_S): the residual of A_S on Q vanishes
+    AS = stored_dense(A32, m)[:, i1]
+    R = AS - Q @ (Q.T @ AS)
+    assert np.max(np.abs(R)) < 1e-10 * np.max(np.abs(AS))
+    i2, o2, _, _ = s.select(k)
+    assert np.array_equal(i1, i2) and np.array_equal(o1.view(np.int64), o2.view(np.int64))
+    d_idx, d_obj, d_ns = s.select_async(k)
+    assert np.array_equal(d_idx.cpu().numpy(), i1)
+    assert np.array_equal(d_obj.cpu().numpy().view(np.int64), o1.view(np.int64))
+    assert int(d_ns.cpu()[0]) == k
+
+
+def test_scores_after_steps_follow_the_recursion(gpu):
+    m, n, k, r = 300, 2000, 8, 32
+    A = synth.gauss_lowrank_dense(m, n, 30, 0.1, seed=6)
+    A32 = colstore32(A)
+    Av = stored_dense(A32, m)
+    Bv = stored_dense(colstore32(Av @ synth.omega_gauss(n, r, seed=7).astype(np.float64)), m)
+    s = _sel(gpu, A32, m, k_max=k, r_max=r)
+    s.set_target(dev(colstore32(Bv)))
+    idx, _, _, _ = s.select(k)
+    ref = oracle.select(f64cs(Av), m, k, B=f64cs(Bv), trace=True)
+    assert list(idx) == list(ref["idx"])
+    # after k picks the GPU has applied k-1 updates: compare with the oracle's
+    # scores just before pick k
+    f = s.read(gpu.STATE_F, n, np.float64)
+    g = s.read(gpu.STATE_G, n, np.float64)
+    fr, gr = ref["fg"][k - 1]
+    f0, g0 = ref["fg"][0]
+    np.testing.assert_allclose(g, gr, rtol=0, atol=1e-5 * g0)
+    np.testing.assert_allclose(f, fr, rtol=0, atol=1e-5 * f0 + 1e-9 * f0.max())
+
+
+# ---------------------------------------------------------------- edges ------
+def test_exact_low_rank_exhausts(gpu):
+    m, n, rank = 40, 100, 5
+    A = synth.int_lowrank_dense(m, n, rank, seed=8)
+    A32 = colstore32(A)
+    s = _sel(gpu, A32, m, k_max=10, self_target=True)
+    s.set_target(None)
+    idx, obj, ns, st = s.select(10)
+    assert st == gpu.WARN_EXHAUSTED and ns == rank
+    assert np.all(idx[rank:] == -1)
+    assert abs(obj[rank]) <= 1e-6 * obj[0]
+    assert np.all(obj[rank:] == obj[rank])
+    assert oracle.error(f64cs(stored_dense(A32, m)), m, idx[:rank]) <= 1e-12 * obj[0]
+
+
+def test_degenerate_columns_never_picked(gpu):
+    m, n = 64, 200
+    A = synth.gauss_lowrank_dense(m, n, 20, 0.1, seed=9)
+    A[:, 10] = 0.0                 # zero column
+    A[:, 20] = A[:, 21]            # duplicate
+    A[:, 30] = np.nan              # non-finite
+    A32 = colstore32(A)
+    s = _sel(gpu, A32, m, k_max=40, self_target=False, r_max=8)
+    B = colstore32(np.nan_to_num(A) @ synth.omega_gauss(n, 8, seed=1).astype(np.float64))
+    s.set_target(dev(B))
+    idx, obj, ns, st = s.select(40)
+    picked = set(idx[idx >= 0].tolist())
+    assert 10 not in picked and 30 not in picked
+    assert not ({20, 21} <= picked)
+    assert len(picked) == ns
+
+
+@pytest.mark.parametrize("m,n,k", [(5, 1, 1), (64, 40, 40), (20, 65, 20), (8192, 70, 5), (4097, 300, 6)])
+def test_small_and_extreme_shapes(gpu, m, n, k):
+    A = np.random.default_rng(m * n).standard_normal((m, n))
+    A32 = colstore32(A)
+    s = _sel(gpu, A32, m, k_max=k, self_target=True)
+    s.set_target(None)
+    idx, obj, ns, st = s.select(k)
+    ref = oracle.select(f64cs(stored_dense(A32, m)), m, k, tau=1e-4)
+    assert ns == ref["n_selected"]
+    sep = int(np.argmax(ref["gap"] < 1e-4)) if np.any(ref["gap"] < 1e-4) else k
+    assert _prefix_len(idx, ref["idx"]) >= sep
+    if k == n:
+        assert sorted(idx) == list(range(n))
+    np.testing.assert_allclose(obj, ref["obj"], rtol=1e-5, atol=1e-6 * obj[0])
+
+
+def test_single_row_ties(gpu):
+    # m = 1: every column spans the same line, all scores tie in exact
+    # arithmetic; one pick explains everything, then nothing is left
+    m, n = 1, 10
+    A = np.random.default_rng(3).standard_normal((m, n)) + 3.0
+    s = _sel(gpu, colstore32(A), m, k_max=3, self_target=True)
+    s.set_target(None)
+    idx, obj, ns, st = s.select(3)
+    assert ns == 1 and st == gpu.WARN_EXHAUSTED and 0 <= idx[0] < n
+    assert abs(obj[1]) <= 1e-6 * obj[0]
+
+
+def test_argument_and_state_errors(gpu):
+    m, n = 50, 100
+    A32 = colstore32(np.random.default_rng(0).standard_normal((m, n)))
+    s = _sel(gpu, A32, m, k_max=5, r_max=4)
+    with pytest.raises(gpu.GcssError) as ei:
+        s.select(3)
+    assert ei.value.status == gpu.ERR_STATE
+    with pytest.raises(gpu.GcssError) as ei:
+        s.set_target(None)  # self target not reserved
+    assert ei.value.status == gpu.ERR_STATE
+    B = colstore32(np.random.default_rng(1).standard_normal((m, 4)))
+    s.set_target(dev(B))
+    with pytest.raises(gpu.GcssError) as ei:
+        s.select(6)
+    assert ei.value.status == gpu.ERR_ARG
+    with pytest.raises(gpu.GcssError):
+        s.reconstruction_error([1, 1])
+    with pytest.raises(gpu.GcssError):
+        s.reconstruction_error([n])
