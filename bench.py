@@ -1,0 +1,259 @@
+#!/usr/bin/env python3
+"""Benchmark of the greedy column subset selection hot path on one MI355X.
+
+One step = the whole path on one synthetic input already resident in HBM:
+target preparation (Gram matrix for B = A, or B = A Omega), initial scores,
+the k-step selection loop, and the reconstruction error of the picks.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--dtype D]
+
+Prints one JSON line: value = n*k / t_step (score updates per second over
+the whole step), plus the roofline of the fused streaming kernel (HBM
+bytes per launch over its event-timed duration) and the FP64 CPU oracle
+timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+METRIC = "score updates/s (n·k/t)"
+
+WORKLOADS = {
+    # name: (synth workload key, default dtype)
+    "css_4096x65536_k200": "f32",
+    "css_500x1000_k20": "f32",
+    "gcss_2048x1048576_r256_k100": "f32",
+    "gcss_fp8_8192x262144_r512_k500": "fp8",
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_inputs(name, dtype, seed=0):
+    import torch
+
+    import paper_1312_6838_amd as g
+    import synth
+
+    w = synth.workload(name)
+    m = w["m"]
+    n = w["n"]
+    if w["kind"] == "spectral":
+        A32 = synth.spectral_lowrank_torch(m, n, w["rank"], w["decay"], w["noise"], seed)
+    else:
+        A32 = synth.gauss_lowrank_torch(m, n, w["rank"], w["noise"], seed)
+    scales = None
+    if dtype == "f32":
+        A = A32
+    elif dtype in ("bf16", "fp8"):
+        A, scales = g.quantize_tensor(A32, m, dtype)
+    else:
+        raise ValueError(dtype)
+    Om = None
+    if w["target"] == "proj":
+        Om = synth.omega_gauss_torch(n, w["r"], seed + 1)
+    torch.cuda.synchronize()
+    return w, A32, A, scales, Om
+
+
+def algorithmic_bytes_per_column(m, dtype):
+    # one read of the column + f, g read and written in FP64 (+ the FP8 scale)
+    b = {"f32": 4, "bf16": 2, "fp8": 1}[dtype]
+    return m * b + 32 + (4 if dtype == "fp8" else 0)
+
+
+def read_traffic(workload, dtype, src_sha, launches_bytes):
+    """HBM bytes per stream launch from committed rocprofv3 counter summaries."""
+    path = os.path.join(ROOT, "profiles", f"k_stream_{workload}_{dtype}_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha256") != src_sha:
+        return None
+    try:
+        fetch = float(kv["fetch_kib_per_dispatch"]) / float(kv["copy_fetch_scale"])
+        write = float(kv["write_kib_per_dispatch"]) / float(kv["copy_write_scale"])
+    except (KeyError, ValueError, ZeroDivisionError):
+        return None
+    return (fetch + write) * 1024.0
+
+
+def cpu_baseline(w, A32, Om, target_seconds=15.0):
+    """The FP64 oracle on a smaller instance of the workload (first n_s columns)."""
+    import numpy as np
+
+    import oracle
+
+    m, n, k = w["m"], w["n"], w.get("k", 20)
+    self_target = w["target"] == "self"
+    r = w.get("r", 0)
+
+    def run(ns):
+        import torch
+        Acs = A32[:ns, :m].to(torch.float64).cpu().numpy()
+        B = None
+        if not self_target:
+            Bs = (A32[:ns, :m].to(torch.float64).T @ Om[:ns].to(torch.float64)).cpu().numpy()
+            B = np.ascontiguousarray(Bs.T)
+        kk = min(k, ns)
+        t0 = time.perf_counter()
+        oracle.select(Acs, m, kk, B=B)
+        return time.perf_counter() - t0, ns * kk
+
+    ns = min(n, 1024)
+    t, upd = run(ns)
+    # self target: the initial scores cost m*ns^2; explicit target: linear in ns
+    if ns < n and t < target_seconds / 2:
+        grow = math.sqrt(target_seconds / max(t, 1e-3)) if self_target else target_seconds / max(t, 1e-3)
+        ns = int(min(n, max(ns, ns * grow)))
+        ns = max(64, (ns // 64) * 64)
+        t, upd = run(ns)
+    kk = min(k, ns)
+    desc = (f"first {ns} of {n} columns, m={m}, k={kk}, "
+            + ("B = A" if self_target else f"B = A_s Omega_s (r={r})")
+            + ", FP64 oracle incl. initial scores")
+    return {"value": upd / t, "unit": "score updates/s", "cores": oracle.num_threads(),
+            "kind": "oracle", "sample": desc, "seconds": round(t, 3)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="css_4096x65536_k200", choices=sorted(WORKLOADS))
+    ap.add_argument("--dtype", default=None, choices=["f32", "bf16", "fp8"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--out", default=None)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs the selection on one GPU only; --gpus N > 1 is not "
+              "supported (DESIGN.md describes how the path would shard over GPUs).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1312_6838_amd as g
+
+    dtype = args.dtype or WORKLOADS[args.workload]
+    torch.cuda.set_device(0)
+    log(f"[bench] generating {args.workload} ({dtype})")
+    w, A32, A, scales, Om = make_inputs(args.workload, dtype)
+    m, n, k = w["m"], w["n"], w["k"]
+    self_target = w["target"] == "self"
+    r = w.get("r", 0)
+    lda = A.shape[1]
+
+    sel = g.Selector(A, m, k_max=k, r_max=r, self_target=self_target, scales=scales)
+    state = {}
+
+    def step():
+        if self_target:
+            sel.set_target(None)
+        else:
+            sel.project_target(Om)
+        idx, obj, ns, st = sel.select(k)
+        err = sel.reconstruction_error(idx[:ns])
+        state.update(idx=idx, obj=obj, ns=ns, err=err)
+
+    log(f"[bench] warmup x{args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    sel.profile(True)
+    log(f"[bench] timing x{args.steps}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = sel.profile()
+    sel.profile(False)
+    ms_step = (t1 - t0) / args.steps * 1e3
+    value = n * k / (ms_step / 1e3)
+
+    # phase split of one more (untimed) step
+    phases = {}
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    if self_target:
+        sel.set_target(None)
+    else:
+        sel.project_target(Om)
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    idx, obj, ns, st = sel.select(k)
+    tc = time.perf_counter()
+    sel.reconstruction_error(idx[:ns])
+    td = time.perf_counter()
+    phases = {"target_and_initial_scores_ms": round((tb - ta) * 1e3, 3),
+              "selection_loop_ms": round((tc - tb) * 1e3, 3),
+              "reconstruction_error_ms": round((td - tc) * 1e3, 3)}
+
+    # roofline of the fused stream kernel
+    src = open(os.path.join(ROOT, "paper_1312_6838_amd", "csrc", "k_stream.hip"), "rb").read()
+    src_sha = hashlib.sha256(src).hexdigest()
+    per_col = algorithmic_bytes_per_column(m, dtype)
+    bytes_launch = n * per_col
+    avg_ms = prof["stream_ms"] / max(prof["stream_launches"], 1)
+    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    roof = {"bound": "hbm", "kernel": "k_stream (fused A^T[q,z] pass + score update + argmax)",
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": read_traffic(args.workload, dtype, src_sha, bytes_launch),
+            "bytes_per_launch": bytes_launch, "avg_launch_ms": round(avg_ms, 5),
+            "launches_timed": prof["stream_launches"]}
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "score updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+        "data": "synthetic",
+        "config": {"workload": args.workload, "m": m, "n": n, "k": k, "lda": lda,
+                   "target": "B = A" if self_target else f"B = A Omega, r = {r}",
+                   "a_storage": dtype},
+        "roofline": roof,
+        "loop_only": {"score_updates_per_s": n * k / (prof["loop_ms"] / max(prof["selects"], 1) * 1e-3)
+                      if prof["selects"] else None,
+                      "loop_ms": round(prof["loop_ms"] / max(prof["selects"], 1), 3)},
+        "phases": phases,
+        "result": {"n_selected": int(state["ns"]), "objective_first": float(state["obj"][0]),
+                   "objective_last": float(state["obj"][state["ns"]]),
+                   "reconstruction_error": float(state["err"])},
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (FP64 oracle, bounded sample)")
+        out["cpu_baseline"] = cpu_baseline(w, A32, Om, args.cpu_seconds)
+    else:
+        out["cpu_baseline"] = None
+    line = json.dumps(out)
+    print(line, flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(line + "\n")
+
+
+if __name__ == "__main__":
+    main()

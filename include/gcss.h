@@ -87,8 +87,8 @@ gcss_status gcss_workspace_size(const gcss_desc *d, size_t *bytes);
  * HIP device.  workspace: device, >= gcss_workspace_size bytes, 256-byte
  * aligned, borrowed for the context's life.
  * Errors: GCSS_ERR_ARG, GCSS_ERR_WORKSPACE, GCSS_ERR_DEVICE (no gfx950),
- * GCSS_ERR_UNSUPPORTED (m larger than the kernels cover: 8192 for F32,
- * 16384 for BF16, 32768 for FP8).
+ * GCSS_ERR_UNSUPPORTED (m > 8192, the most rows the streaming kernel keeps
+ * in registers).
  */
 gcss_status gcss_create(const gcss_desc *d, void *workspace, size_t ws_bytes, gcss_ctx **out);
 
@@ -126,8 +126,11 @@ gcss_status gcss_project_target(gcss_ctx *h, const float *omega, int64_t r, floa
  * scores, so repeated calls give identical results.
  * idx:        host, k entries: picks in order; -1 for picks not made.
  * objective:  host, k+1 entries (may be NULL): objective[0] = ||B||_F^2,
- *             objective[t] = F(first t picks) by the recursion of Theorems
- *             1 and 3; entries past *n_selected repeat the last value.
+ *             objective[t] = F(first t picks) = objective[t-1] minus the
+ *             decrease of Theorems 1 and 3, ||B^T q_t||^2 for the pick's unit
+ *             residual direction q_t (FP64; for B = A it is recomputed after
+ *             the loop as ||A^T q_t||^2 with FP64 products and sums);
+ *             entries past *n_selected repeat the last value.
  * n_selected: host (may be NULL): number of picks made.
  * Returns GCSS_OK, or GCSS_WARN_EXHAUSTED when fewer than k columns stay
  * candidates (see gcss_desc.tau).  Errors: GCSS_ERR_ARG (k < 1 or k > k_max),
@@ -149,11 +152,12 @@ gcss_status gcss_select_async(gcss_ctx *h, int32_t k, int64_t *d_idx, double *d_
 /*
  * Reconstruction error || B - P_S B ||_F^2 of the current target for the
  * columns S = idx[0..k-1] (host, distinct, in [0, n)), written to *err
- * (host).  P_S comes from an FP64 Gram-Schmidt basis (with one
- * re-orthogonalisation) of A_S.  For an explicit B the residual
+ * (host).  P_S comes from an FP64 Gram-Schmidt basis Q (with one
+ * re-orthogonalisation) of A_S; a column numerically dependent on the
+ * earlier ones adds no direction.  For an explicit B the residual
  * B - Q (Q^T B) is formed and summed in FP64.  For B = A the error is
- * tr(A A^T) - tr(Q^T (A A^T) Q) with FP64 sums over the binary32 Gram
- * matrix.  Errors: GCSS_ERR_ARG, GCSS_ERR_STATE, GCSS_ERR_DEVICE.
+ * ||A||_F^2 - sum_s ||A^T q_s||^2 with FP64 products and sums.
+ * Errors: GCSS_ERR_ARG, GCSS_ERR_STATE, GCSS_ERR_DEVICE.
  */
 gcss_status gcss_reconstruction_error(gcss_ctx *h, const int64_t *idx, int32_t k, double *err);
 
@@ -218,6 +222,23 @@ typedef enum {
  * size, and *copied (may be NULL) receives the bytes written.
  */
 gcss_status gcss_read_state(gcss_ctx *h, int32_t item, void *host, size_t bytes, size_t *copied);
+
+/* Timings collected while profiling is on (HIP events on the context's stream,
+ * recorded by gcss_select only; the graph-replayed gcss_select_async is not
+ * instrumented). */
+typedef struct {
+  int64_t stream_launches;  /* fused streaming passes (step 4 of the loop) timed */
+  double stream_ms;         /* their summed duration, milliseconds                */
+  int64_t selects;          /* gcss_select calls timed                            */
+  double loop_ms;           /* summed duration of their k-step loops, ms          */
+} gcss_profile;
+
+/* Turn event timing of gcss_select on (enable != 0) or off; always clears
+ * the counters.  Errors: GCSS_ERR_ARG, GCSS_ERR_DEVICE. */
+gcss_status gcss_set_profiling(gcss_ctx *h, int32_t enable);
+
+/* Read the counters (host struct).  Errors: GCSS_ERR_ARG. */
+gcss_status gcss_get_profile(gcss_ctx *h, gcss_profile *out);
 
 /* Message for the last non-OK status returned on this thread ("" if none). */
 const char *gcss_last_error(void);

@@ -17,6 +17,7 @@ from ._abi import (  # noqa: F401
     STATE_Q, STATE_Z, WARN_EXHAUSTED, Desc, GcssError, batched_workspace_size, create, destroy,
     last_error, load, make_desc, project_target, quantize, read_state, reconstruction_error,
     select, select_async, select_batched, set_target, version, workspace_size,
+    set_profiling, get_profile,
 )
 
 __all__ = ["Selector", "quantize_tensor", "load", "version", "GcssError"]
@@ -115,6 +116,12 @@ class Selector:
         import numpy as np
         raw = read_state(self.h, item, int(count) * np.dtype(np_dtype).itemsize)
         return np.frombuffer(raw, dtype=np_dtype).copy()
+
+    def profile(self, enable=None):
+        """Turn stream-kernel event timing on/off (clears counters), or read them."""
+        if enable is not None:
+            set_profiling(self.h, enable)
+        return get_profile(self.h)
 
     def close(self):
         if getattr(self, "h", None):

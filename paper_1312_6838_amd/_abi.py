@@ -30,7 +30,7 @@ EXPORTS = [
     "gcss_workspace_size", "gcss_create", "gcss_destroy", "gcss_set_target",
     "gcss_project_target", "gcss_select", "gcss_select_async", "gcss_reconstruction_error",
     "gcss_select_batched", "gcss_batched_workspace_size", "gcss_quantize", "gcss_read_state",
-    "gcss_last_error", "gcss_version",
+    "gcss_last_error", "gcss_version", "gcss_set_profiling", "gcss_get_profile",
 ]
 
 
@@ -47,6 +47,11 @@ class Desc(ctypes.Structure):
         ("k_max", ctypes.c_int32), ("r_max", ctypes.c_int64), ("self_target", ctypes.c_int32),
         ("reserved", ctypes.c_int32), ("tau", ctypes.c_double), ("stream", ctypes.c_void_p),
     ]
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("stream_launches", ctypes.c_int64), ("stream_ms", ctypes.c_double),
+                ("selects", ctypes.c_int64), ("loop_ms", ctypes.c_double)]
 
 
 _lib = None
@@ -87,6 +92,10 @@ def load():
     lib.gcss_quantize.restype = st
     lib.gcss_read_state.argtypes = [_vp, _i32, _vp, _sz, _P(_sz)]
     lib.gcss_read_state.restype = st
+    lib.gcss_set_profiling.argtypes = [_vp, _i32]
+    lib.gcss_set_profiling.restype = st
+    lib.gcss_get_profile.argtypes = [_vp, _P(Profile)]
+    lib.gcss_get_profile.restype = st
     lib.gcss_last_error.argtypes = []
     lib.gcss_last_error.restype = ctypes.c_char_p
     lib.gcss_version.argtypes = []
@@ -192,3 +201,14 @@ def read_state(h: int, item: int, nbytes: int) -> bytes:
     got = _sz(0)
     _check(load().gcss_read_state(h, item, buf, nbytes, ctypes.byref(got)))
     return bytes(buf[: got.value])
+
+
+def set_profiling(h: int, enable: bool) -> None:
+    _check(load().gcss_set_profiling(h, int(bool(enable))))
+
+
+def get_profile(h: int) -> dict:
+    p = Profile()
+    _check(load().gcss_get_profile(h, ctypes.byref(p)))
+    return dict(stream_launches=p.stream_launches, stream_ms=p.stream_ms, selects=p.selects,
+                loop_ms=p.loop_ms)

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -57,8 +58,9 @@ struct Carve {
 // Offsets of every workspace region for a description (sizes only).
 struct Layout {
   size_t f0, g0, f, g, mask0, mask, part, npart, Q, e1, e2, w, q64, q32, z32, c1, c2, c3, ups,
-      st, idx, obj, scal, pick, gram, scratch, total;
+      st, idx, obj, scal, pick, quad, ap64, gram, scratch, total;
   size_t scratch_bytes;
+  size_t qbuf;  // floats in q32 / z32 (covers both stream variants)
   StreamGeo geo;
   int64_t ldq;
 };
@@ -66,8 +68,16 @@ struct Layout {
 bool make_layout(const gcss_desc *d, int num_cu, Layout *L) {
   const int64_t m = d->m, n = d->n, k = d->k_max, r = d->r_max;
   L->ldq = ld_for(m);
-  L->geo = stream_geometry(m, n, d->a_dtype, num_cu);
+  // both stream variants must fit the carve: size q32/z32 and the partials
+  // for the larger, pick the register variant unless told otherwise
+  StreamGeo g_reg = stream_geometry(m, n, d->a_dtype, num_cu, 0);
+  StreamGeo g_lds = stream_geometry(m, n, d->a_dtype, num_cu, 1);
+  const char *ql_env = getenv("GCSS_STREAM_QL");
+  const bool use_lds = (ql_env && atoi(ql_env) != 0) || g_reg.nj == 0;
+  L->geo = use_lds ? g_lds : g_reg;
   if (L->geo.nj == 0) return false;
+  L->geo.grid = std::max(g_reg.grid, g_lds.grid);
+  L->qbuf = (size_t)std::max(g_reg.nj ? g_reg.qlen : 0, g_lds.qlen);
   Carve c;
   L->f0 = c.take<double>(n);
   L->g0 = c.take<double>(n);
@@ -82,7 +92,7 @@ bool make_layout(const gcss_desc *d, int num_cu, Layout *L) {
   L->e2 = c.take<double>(L->ldq);
   L->w = c.take<double>(L->ldq);
   L->q64 = c.take<double>(L->ldq);
-  const size_t qlen = std::max<size_t>(L->geo.qlen, L->ldq);
+  const size_t qlen = std::max<size_t>(L->qbuf, L->ldq);
   L->q32 = c.take<float>(qlen);
   L->z32 = c.take<float>(qlen);
   L->c1 = c.take<double>(k + 8);
@@ -94,6 +104,8 @@ bool make_layout(const gcss_desc *d, int num_cu, Layout *L) {
   L->obj = c.take<double>(k + 8);
   L->scal = c.take<double>(64);
   L->pick = c.take<int64_t>(k + 8);
+  L->quad = c.take<double>(k + 8);
+  L->ap64 = c.take<double>(L->ldq);
   L->gram = d->self_target ? c.take<float>((size_t)L->ldq * m) : 0;
   // transient scratch: split-K partials, or the reconstruction-error buffers
   size_t s = 0;
@@ -102,6 +114,7 @@ bool make_layout(const gcss_desc *d, int num_cu, Layout *L) {
   const size_t err_bytes = up((size_t)std::max<int64_t>(r, 1) * 8, 256) +
                            up((size_t)L->ldq * k * 4, 256) + 3 * up((size_t)(k + 8) * 8, 256);
   s = std::max(s, err_bytes);
+  if (d->self_target) s = std::max(s, qta_scratch_bytes(n, (int)k));
   L->scratch_bytes = s;
   L->scratch = c.take<uint8_t>(s);
   L->total = up(c.off, 256);
@@ -142,6 +155,11 @@ struct gcss_ctx {
   // last completed selection (host copy), for reuse of its basis
   std::vector<int64_t> last_idx;
   bool basis_valid = false;
+  // event timing of the fused stream (gcss_select only)
+  bool profiling = false;
+  std::vector<hipEvent_t> ev;  // pairs around stream launches, then the loop pair
+  size_t ev_used = 0;
+  gcss_profile prof{};
   // captured loop
   hipGraphExec_t graph = nullptr;
   int graph_k = -1;
@@ -187,10 +205,29 @@ hipError_t enqueue_basis_step(gcss_ctx *h, const StepBufs &sb) {
   double *c1 = h->at<double>(h->L.c1), *c2 = h->at<double>(h->L.c2);
   hipStream_t s = h->stream;
   hipError_t e;
-  if ((e = launch_cols(Q, nullptr, ldq, m, 1, 0, kmax, VEC_ACOL, nullptr, h->A, c1, CF_NONE, sb, s))) return e;
-  if ((e = launch_rows(Q, nullptr, ldq, m, 1, 0, VEC_ACOL, nullptr, h->A, c1, e1, nullptr, RF_NONE, sb, s))) return e;
+  // first projection of the pick's column: decoded to FP64 by the previous
+  // stream pass, or (caller's pick list) decoded here
+  const double *ap = h->at<double>(h->L.ap64);
+  const int vs = sb.pick_list ? VEC_ACOL : VEC_F64;
+  if ((e = launch_cols(Q, nullptr, ldq, m, 1, 0, kmax, vs, ap, h->A, c1, CF_NONE, sb, s))) return e;
+  if ((e = launch_rows(Q, nullptr, ldq, m, 1, 0, vs, ap, h->A, c1, e1, nullptr, RF_NONE, sb, s))) return e;
   if ((e = launch_cols(Q, nullptr, ldq, m, 1, 0, kmax, VEC_F64, e1, h->A, c2, CF_NONE, sb, s))) return e;
   return launch_rows(Q, nullptr, ldq, m, 1, 0, VEC_F64, e1, h->A, c2, e2, nullptr, RF_GS2, sb, s);
+}
+
+hipEvent_t next_event(gcss_ctx *h) {
+  if (h->ev_used == h->ev.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    h->ev.push_back(e);
+  }
+  return h->ev[h->ev_used++];
+}
+
+hipError_t record(gcss_ctx *h) {
+  hipEvent_t e = next_event(h);
+  if (!e) return hipErrorOutOfMemory;
+  return hipEventRecord(e, h->stream);
 }
 
 // One greedy step: basis update, target ops, fused stream.
@@ -218,9 +255,25 @@ hipError_t enqueue_step(gcss_ctx *h) {
   }
   // z = w - Q_{t-1} c3 ; record the pick
   if ((e = launch_rows(Q, nullptr, ldq, m, 1, 0, VEC_F64, w, h->A, c3, nullptr, h->at<float>(h->L.z32), RF_Z, sb, s))) return e;
-  return launch_stream(h->L.geo, h->A, h->at<float>(h->L.q32), h->at<float>(h->L.z32),
-                       h->at<double>(h->L.f), h->at<double>(h->L.g), h->at<double>(h->L.g0),
-                       h->at<uint8_t>(h->L.mask), h->at<ArgPart>(h->L.part), sb.st, 0, s);
+  if (h->profiling && (e = record(h))) return e;
+  if ((e = launch_stream(h->L.geo, h->A, h->at<float>(h->L.q32), h->at<float>(h->L.z32),
+                         h->at<double>(h->L.f), h->at<double>(h->L.g), h->at<double>(h->L.g0),
+                         h->at<uint8_t>(h->L.mask), h->at<ArgPart>(h->L.part), sb.st,
+                         h->at<double>(h->L.ap64), 0, s)))
+    return e;
+  if (h->profiling && (e = record(h))) return e;
+  return hipSuccess;
+}
+
+// Gram target: replace the per-step decrements (from the binary32 Gram
+// matrix) by the exact ||A^T q_s||^2 of an FP64 pass over A.
+hipError_t enqueue_exact_objective(gcss_ctx *h) {
+  if (h->target != 2) return hipSuccess;
+  const StepBufs sb = h->bufs();
+  hipError_t e = launch_qta(h->at<double>(h->L.Q), h->L.ldq, h->d.k_max, sb.st, h->A,
+                            h->at<double>(h->L.scratch), h->at<double>(h->L.quad), h->stream);
+  if (e) return e;
+  return launch_obj_from_quad(h->F0(), h->at<double>(h->L.quad), sb.st, sb.obj, h->stream);
 }
 
 hipError_t enqueue_begin(gcss_ctx *h, int k) {
@@ -233,7 +286,8 @@ hipError_t enqueue_begin(gcss_ctx *h, int k) {
   // first argmax over the initial scores
   return launch_stream(h->L.geo, h->A, h->at<float>(h->L.q32), h->at<float>(h->L.z32),
                        h->at<double>(h->L.f), h->at<double>(h->L.g), h->at<double>(h->L.g0),
-                       h->at<uint8_t>(h->L.mask), h->at<ArgPart>(h->L.part), sb.st, 1, h->stream);
+                       h->at<uint8_t>(h->L.mask), h->at<ArgPart>(h->L.part), sb.st,
+                       h->at<double>(h->L.ap64), 1, h->stream);
 }
 
 gcss_status check_ctx(gcss_ctx *h) {
@@ -284,6 +338,18 @@ gcss_status gcss_create(const gcss_desc *d, void *workspace, size_t ws_bytes, gc
   if (ws_bytes < L.total)
     return fail(GCSS_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
 
+  // streaming-pass tunables (see gcss_tune in the docs): column group size
+  // and non-temporal loads; then size the grid from the kernel's occupancy
+  if (const char *v = getenv("GCSS_STREAM_G")) {
+    const int gsz = atoi(v);
+    if (gsz == 16 || gsz == 32 || gsz == 64) L.geo.g = gsz;
+  }
+  if (const char *v = getenv("GCSS_STREAM_NT")) L.geo.nt = atoi(v) != 0;
+  {
+    hipError_t fe = stream_finalize(L.geo, d->n, d->a_dtype, num_cu);
+    if (fe != hipSuccess) return fail(GCSS_ERR_DEVICE, "stream kernel occupancy: %s", hipGetErrorString(fe));
+  }
+
   gcss_ctx *h = new gcss_ctx();
   h->device = dev;
   h->num_cu = num_cu;
@@ -298,7 +364,7 @@ gcss_status gcss_create(const gcss_desc *d, void *workspace, size_t ws_bytes, gc
   h->A.n = d->n;
   h->A.lda = d->lda;
   h->A.dtype = d->a_dtype;
-  const size_t qlen = std::max<size_t>(L.geo.qlen, L.ldq);
+  const size_t qlen = std::max<size_t>(L.qbuf, L.ldq);
   hipError_t e = launch_zero_f32(h->at<float>(L.q32), (int64_t)qlen, h->stream);
   if (!e) e = launch_zero_f32(h->at<float>(L.z32), (int64_t)qlen, h->stream);
   if (e) {
@@ -312,6 +378,7 @@ gcss_status gcss_create(const gcss_desc *d, void *workspace, size_t ws_bytes, gc
 void gcss_destroy(gcss_ctx *h) {
   if (!h) return;
   drop_graph(h);
+  for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   delete h;
 }
@@ -365,6 +432,14 @@ gcss_status gcss_select(gcss_ctx *h, int32_t k, int64_t *idx, double *objective,
   if (!idx) return fail(GCSS_ERR_ARG, "null idx");
   if (k < 1 || k > h->d.k_max) return fail(GCSS_ERR_ARG, "k = %d outside [1, k_max = %d]", k, h->d.k_max);
   if (!h->target) return fail(GCSS_ERR_STATE, "no target set");
+  hipEvent_t loop0 = nullptr, loop1 = nullptr;
+  if (h->profiling) {
+    h->ev_used = 0;
+    loop0 = next_event(h);
+    loop1 = next_event(h);
+    if (!loop0 || !loop1) return fail(GCSS_ERR_DEVICE, "event create failed");
+    HIPCHK(hipEventRecord(loop0, h->stream));
+  }
   HIPCHK(enqueue_begin(h, k));
   DevState hs;
   int slots = k;
@@ -375,6 +450,20 @@ gcss_status gcss_select(gcss_ctx *h, int32_t k, int64_t *idx, double *objective,
     if (hs.done) break;
     slots = k - hs.t;  // picks were rejected: run the missing steps
     if (slots < 1) slots = 1;
+  }
+  HIPCHK(enqueue_exact_objective(h));
+  if (h->profiling) {
+    HIPCHK(hipEventRecord(loop1, h->stream));
+    HIPCHK(hipEventSynchronize(loop1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, loop0, loop1));
+    h->prof.loop_ms += ms;
+    h->prof.selects += 1;
+    for (size_t x = 2; x + 1 < h->ev_used; x += 2) {
+      HIPCHK(hipEventElapsedTime(&ms, h->ev[x], h->ev[x + 1]));
+      h->prof.stream_ms += ms;
+      h->prof.stream_launches += 1;
+    }
   }
   std::vector<int64_t> hidx(k);
   std::vector<double> hobj(k + 1);
@@ -405,14 +494,18 @@ gcss_status gcss_select_async(gcss_ctx *h, int32_t k, int64_t *d_idx, double *d_
     drop_graph(h);
     if (!h->cap_stream) HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
     hipStream_t user = h->stream;
+    const bool prof = h->profiling;
+    h->profiling = false;
     h->stream = h->cap_stream;
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeRelaxed);
     if (!e) e = enqueue_begin(h, k);
     for (int i = 0; !e && i < k + kSpareSlots; ++i) e = enqueue_step(h);
+    if (!e) e = enqueue_exact_objective(h);
     if (!e) e = launch_finish(h->bufs(), k, d_idx, d_obj, d_nsel, h->cap_stream);
     hipError_t e2 = hipStreamEndCapture(h->cap_stream, &g);
     h->stream = user;
+    h->profiling = prof;
     if (e || e2) {
       if (g) (void)hipGraphDestroy(g);
       return fail(GCSS_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e ? e : e2));
@@ -477,17 +570,25 @@ gcss_status gcss_reconstruction_error(gcss_ctx *h, const int64_t *idx, int32_t k
   } else if (kb == 0) {
     HIPCHK(launch_sum_f64(h->F0(), 1, h->err_dev(), s));
   } else {
-    float *Q32 = (float *)scr;
-    double *quad = (double *)(scr + up((size_t)ldq * h->d.k_max * 4, 256));
-    double *gtmp = quad + up((size_t)(h->d.k_max + 8), 32);
-    uint8_t *mtmp = (uint8_t *)(gtmp + up((size_t)(h->d.k_max + 8), 32));
-    HIPCHK(launch_q_to_f32(Q, ldq, m, kb, Q32, ldq, s));
-    AView qv{Q32, nullptr, m, kb, ldq, DT_F32};
-    HIPCHK(launch_init_gram(h->at<float>(h->L.gram), ldq, qv, quad, gtmp, mtmp, s));
+    double *quad = h->at<double>(h->L.quad);
+    HIPCHK(launch_qta(Q, ldq, kb, nullptr, h->A, (double *)scr, quad, s));
     HIPCHK(launch_gram_err(h->F0(), quad, kb, h->err_dev(), s));
   }
   HIPCHK(hipMemcpyAsync(err, h->err_dev(), sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  return GCSS_OK;
+}
+
+gcss_status gcss_set_profiling(gcss_ctx *h, int32_t enable) {
+  if (check_ctx(h)) return GCSS_ERR_ARG;
+  h->profiling = enable != 0;
+  h->prof = gcss_profile{};
+  return GCSS_OK;
+}
+
+gcss_status gcss_get_profile(gcss_ctx *h, gcss_profile *out) {
+  if (check_ctx(h) || !out) return fail(GCSS_ERR_ARG, "null argument");
+  *out = h->prof;
   return GCSS_OK;
 }
 

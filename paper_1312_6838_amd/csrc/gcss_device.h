@@ -60,20 +60,23 @@ __device__ __forceinline__ int64_t load_acquire_i64(const int64_t *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Last-block-done protocol: every workgroup publishes its partial, issues a
-// device-scope release fence and bumps a counter; the workgroup that sees
-// the final count does the cross-workgroup step and re-arms the counter.
-// Must be called by all threads of the block.  Returns true in the last one.
+// Last-block-done protocol: every workgroup publishes its partial results,
+// then one thread releases them at device scope (a single fence per
+// workgroup: on CDNA a device-scope fence writes back the L2, so one per
+// thread would cost far more than the work) and bumps a counter; the
+// workgroup that sees the final count acquires (one fence) and does the
+// cross-workgroup step, then re-arms the counter.  Must be called by all
+// threads of the block.  Returns true in the last one.
 __device__ __forceinline__ bool last_block_arrive(uint32_t *counter) {
   __shared__ int am_last;
-  __threadfence();
-  __syncthreads();
+  __syncthreads();  // this block's stores are complete at workgroup scope
   if (threadIdx.x == 0) {
-    uint32_t prev = atomicAdd(counter, 1u);
+    __threadfence();
+    const uint32_t prev = atomicAdd(counter, 1u);
     am_last = (prev == gridDim.x - 1);
+    if (am_last) __threadfence();
   }
   __syncthreads();
-  if (am_last) __threadfence();
   return am_last != 0;
 }
 

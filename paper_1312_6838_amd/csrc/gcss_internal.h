@@ -60,14 +60,18 @@ struct StreamGeo {
   int g;         // columns per team group
   int grid;      // workgroups
   int qlen;      // padded length of q32/z32
+  int nt;        // 1: non-temporal loads of A
+  int ql;        // 1: q and z held in LDS instead of registers
 };
 
 // ---- launchers (k_stream.hip) ----
-StreamGeo stream_geometry(int64_t m, int64_t n, int dtype, int num_cu);
+StreamGeo stream_geometry(int64_t m, int64_t n, int dtype, int num_cu, int ql);
+// Sets the grid from the occupancy of the chosen kernel (needs the device).
+hipError_t stream_finalize(StreamGeo &geo, int64_t n, int dtype, int num_cu);
 hipError_t launch_stream(const StreamGeo &geo, const AView &A, const float *q32,
                          const float *z32, double *f, double *g, const double *g0,
-                         uint8_t *mask, ArgPart *part, DevState *st, int score_only,
-                         hipStream_t s);
+                         uint8_t *mask, ArgPart *part, DevState *st, double *ap64,
+                         int score_only, hipStream_t s);
 
 // ---- launchers (k_gemv.hip) ----
 // Buffers of one selection problem that the per-step kernels touch.
@@ -140,6 +144,15 @@ hipError_t launch_gram(const AView &A, float *C, int64_t ldc, void *scratch, int
 size_t proj_scratch_bytes(int64_t m, int64_t n, int64_t r, int num_cu);
 hipError_t launch_project(const AView &A, const float *omega, int64_t r, float *B,
                           int64_t ldb, void *scratch, int num_cu, hipStream_t s);
+
+// Exact decrements of the Gram target: quad[s] = ||A^T q_s||^2 for s < nrow,
+// nrow = st->t (st given) or kmax.  scratch >= qta_scratch_bytes(n, kmax).
+size_t qta_scratch_bytes(int64_t n, int kmax);
+hipError_t launch_qta(const double *Q, int64_t ldq, int kmax, const DevState *st,
+                      const AView &A, double *scratch, double *quad, hipStream_t s);
+// obj[s+1] = F0 - sum_{x<=s} quad[x], s < st->t
+hipError_t launch_obj_from_quad(const double *F0, const double *quad, const DevState *st,
+                                double *obj, hipStream_t s);
 
 // ---- launchers (k_quant.hip) ----
 hipError_t launch_quantize(const float *a, int64_t m, int64_t n, int64_t lda, int dtype,

@@ -14,37 +14,58 @@
 
 namespace gcss {
 
+// Two consecutive elements of a column of M as doubles (M is FP64 or FP32).
+template <typename MT>
+__device__ __forceinline__ double2 load2(const MT *p) {
+  if constexpr (sizeof(MT) == 8) {
+    return *(const double2 *)p;
+  } else {
+    const float2 f = *(const float2 *)p;
+    return make_double2((double)f.x, (double)f.y);
+  }
+}
+
+// Column dots: one workgroup per output s; each thread owns pairs of rows
+// (j, j+1) with j = 2*tid + 512*i, so a wave reads 512 contiguous bytes of
+// FP32 or 1 KiB of FP64 per load and every load of a thread is issued before
+// the first is used.
 template <typename MT, int VSRC>
 __global__ __launch_bounds__(256) void k_cols(const MT *__restrict__ M, int64_t ldm, int64_t m,
                                               int ns_from_t, int ns_add,
                                               const double *__restrict__ vec, AView A,
                                               double *__restrict__ out, int final_mode,
                                               StepBufs sb) {
+  __shared__ double red[4];
   DevState *st = sb.st;
   if (st->done || st->skip) return;
   const int t = st->t;
   const int ns = (ns_from_t ? t : 0) + ns_add;
-  int64_t p = 0;
-  double ps = 1.0;
-  if constexpr (VSRC == VEC_ACOL) {
-    p = sb.pick_list ? sb.pick_list[st->pos] : st->p;
-    ps = col_scale(A, p);
-  }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int s = blockIdx.x * 4 + wave;
+  const int s = blockIdx.x;
   if (s < ns) {
     const MT *col = M + (int64_t)s * ldm;
     double acc = 0.0;
-    for (int64_t j = lane; j < m; j += 64) {
-      double v;
-      if constexpr (VSRC == VEC_ACOL)
-        v = ps * (double)load_elem(A, p, j);
-      else
-        v = vec[j];
-      acc = fma((double)col[j], v, acc);
+    if constexpr (VSRC == VEC_ACOL) {
+      const int64_t p = sb.pick_list ? sb.pick_list[st->pos] : st->p;
+      const double ps = col_scale(A, p);
+      for (int64_t j = threadIdx.x; j < m; j += 256)
+        acc = fma((double)col[j], ps * (double)load_elem(A, p, j), acc);
+    } else {
+      const int64_t mp = m & ~(int64_t)1;
+      double a0 = 0.0, a1 = 0.0;
+#pragma unroll 4
+      for (int64_t j = 2 * threadIdx.x; j < mp; j += 512) {
+        const double2 x = load2<MT>(col + j);
+        const double2 y = *(const double2 *)(vec + j);
+        a0 = fma(x.x, y.x, a0);
+        a1 = fma(x.y, y.y, a1);
+      }
+      if ((m & 1) && threadIdx.x == 0) a0 = fma((double)col[m - 1], vec[m - 1], a0);
+      acc = a0 + a1;
     }
     acc = wave_sum(acc);
-    if (lane == 0) out[s] = acc;
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) out[s] = ((red[0] + red[1]) + red[2]) + red[3];
   }
   if (final_mode == CF_NONE) return;
   if (!last_block_arrive(&st->cnt[1])) return;
@@ -63,14 +84,19 @@ __global__ __launch_bounds__(256) void k_cols(const MT *__restrict__ M, int64_t 
   }
 }
 
-// VSRC: -1 no base vector, VEC_F64, VEC_ACOL
+// Row updates: a workgroup owns 128 rows (each lane two consecutive rows) and
+// its 16 waves split the sum over s; partial sums meet in LDS in a fixed
+// order.  VSRC: -1 no base vector, VEC_F64, VEC_ACOL.
+constexpr int kRowsWaves = 16;
+
 template <typename MT, int VSRC>
-__global__ __launch_bounds__(256) void k_rows(const MT *__restrict__ M, int64_t ldm, int64_t m,
-                                              int ns_from_t, int ns_add,
-                                              const double *__restrict__ vec, AView A,
-                                              const double *__restrict__ c, double *out64,
-                                              float *out32, int final_mode, StepBufs sb) {
-  __shared__ double red[4][64];
+__global__ __launch_bounds__(1024) void k_rows(const MT *__restrict__ M, int64_t ldm, int64_t m,
+                                               int ns_from_t, int ns_add,
+                                               const double *__restrict__ vec, AView A,
+                                               const double *__restrict__ c, double *out64,
+                                               float *out32, int final_mode, StepBufs sb) {
+  __shared__ double2 red[kRowsWaves][64];
+  __shared__ double wsq[2];
   __shared__ double nrm;
   __shared__ int ok;
   DevState *st = sb.st;
@@ -84,30 +110,70 @@ __global__ __launch_bounds__(256) void k_rows(const MT *__restrict__ M, int64_t 
     ps = col_scale(A, p);
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t j = (int64_t)blockIdx.x * 64 + lane;
-  double acc = 0.0;
-  if (j < m)
-    for (int s = wave; s < ns; s += 4) acc = fma((double)M[j + (int64_t)s * ldm], c[s], acc);
-  red[wave][lane] = acc;
+  const int64_t j = (int64_t)blockIdx.x * 128 + 2 * lane;  // rows j, j+1
+  const bool full = j + 1 < m;
+  double a0 = 0.0, a1 = 0.0;
+  if (j < m) {
+    const MT *base = M + j;
+    int s = wave;
+    for (; s + 3 * kRowsWaves < ns; s += 4 * kRowsWaves) {
+      double2 x[4];
+      double cc[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t off = (int64_t)(s + u * kRowsWaves) * ldm;
+        x[u] = full ? load2<MT>(base + off) : make_double2((double)base[off], 0.0);
+        cc[u] = c[s + u * kRowsWaves];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a0 = fma(x[u].x, cc[u], a0);
+        a1 = fma(x[u].y, cc[u], a1);
+      }
+    }
+    for (; s < ns; s += kRowsWaves) {
+      const int64_t off = (int64_t)s * ldm;
+      const double2 x = full ? load2<MT>(base + off) : make_double2((double)base[off], 0.0);
+      a0 = fma(x.x, c[s], a0);
+      a1 = fma(x.y, c[s], a1);
+    }
+  }
+  red[wave][lane] = make_double2(a0, a1);
   __syncthreads();
   if (wave == 0) {
-    const double sum = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
-    double o = 0.0;
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int x = 0; x < kRowsWaves; ++x) {
+      s0 += red[x][lane].x;
+      s1 += red[x][lane].y;
+    }
+    double o0 = 0.0, o1 = 0.0;
     if (j < m) {
       if constexpr (VSRC < 0) {
-        o = sum;
+        o0 = s0;
+        o1 = s1;
       } else {
-        double v;
-        if constexpr (VSRC == VEC_ACOL)
-          v = ps * (double)load_elem(A, p, j);
-        else
-          v = vec[j];
-        o = v - sum;
+        double v0, v1 = 0.0;
+        if constexpr (VSRC == VEC_ACOL) {
+          v0 = ps * (double)load_elem(A, p, j);
+          if (full) v1 = ps * (double)load_elem(A, p, j + 1);
+        } else {
+          v0 = vec[j];
+          if (full) v1 = vec[j + 1];
+        }
+        o0 = v0 - s0;
+        o1 = full ? v1 - s1 : 0.0;
       }
-      if (out64) out64[j] = o;
-      if (out32) out32[j] = (float)o;
+      if (out64) {
+        out64[j] = o0;
+        if (full) out64[j + 1] = o1;
+      }
+      if (out32) {
+        out32[j] = (float)o0;
+        if (full) out32[j + 1] = (float)o1;
+      }
     }
-    const double sq = wave_sum(o * o);
+    const double sq = wave_sum(o0 * o0 + o1 * o1);
     if (lane == 0 && final_mode == RF_GS2) sb.part[blockIdx.x] = sq;
   }
   if (final_mode == RF_NONE) return;
@@ -159,6 +225,7 @@ __global__ __launch_bounds__(256) void k_rows(const MT *__restrict__ M, int64_t 
       st->cnt[2] = 0;
     }
   }
+  (void)wsq;
 }
 
 __global__ void k_select_begin(const double *__restrict__ f0, const double *__restrict__ g0,
@@ -309,7 +376,7 @@ template <typename MT>
 static hipError_t cols_t(const MT *M, int64_t ldm, int64_t m, int ns_from_t, int ns_add,
                          int max_ns, int vsrc, const double *vec, const AView &A, double *out,
                          int final_mode, const StepBufs &sb, hipStream_t s) {
-  const unsigned grid = blocks_for(max_ns > 0 ? max_ns : 1, 4);
+  const unsigned grid = (unsigned)(max_ns > 0 ? max_ns : 1);
   if (vsrc == VEC_ACOL)
     hipLaunchKernelGGL((k_cols<MT, VEC_ACOL>), dim3(grid), dim3(256), 0, s, M, ldm, m, ns_from_t,
                        ns_add, vec, A, out, final_mode, sb);
@@ -334,15 +401,15 @@ static hipError_t rows_t(const MT *M, int64_t ldm, int64_t m, int ns_from_t, int
                          int vsrc, const double *vec, const AView &A, const double *c,
                          double *out64, float *out32, int final_mode, const StepBufs &sb,
                          hipStream_t s) {
-  const unsigned grid = blocks_for(m, 64);
+  const unsigned grid = blocks_for(m, 128);
   if (vsrc == VEC_ACOL)
-    hipLaunchKernelGGL((k_rows<MT, VEC_ACOL>), dim3(grid), dim3(256), 0, s, M, ldm, m, ns_from_t,
+    hipLaunchKernelGGL((k_rows<MT, VEC_ACOL>), dim3(grid), dim3(64 * kRowsWaves), 0, s, M, ldm, m, ns_from_t,
                        ns_add, vec, A, c, out64, out32, final_mode, sb);
   else if (vsrc == VEC_F64)
-    hipLaunchKernelGGL((k_rows<MT, VEC_F64>), dim3(grid), dim3(256), 0, s, M, ldm, m, ns_from_t,
+    hipLaunchKernelGGL((k_rows<MT, VEC_F64>), dim3(grid), dim3(64 * kRowsWaves), 0, s, M, ldm, m, ns_from_t,
                        ns_add, vec, A, c, out64, out32, final_mode, sb);
   else
-    hipLaunchKernelGGL((k_rows<MT, -1>), dim3(grid), dim3(256), 0, s, M, ldm, m, ns_from_t,
+    hipLaunchKernelGGL((k_rows<MT, -1>), dim3(grid), dim3(64 * kRowsWaves), 0, s, M, ldm, m, ns_from_t,
                        ns_add, vec, A, c, out64, out32, final_mode, sb);
   return hipGetLastError();
 }

@@ -465,6 +465,198 @@ __global__ void k_proj_reduce(const float *__restrict__ P, int64_t ldp, int64_t 
 }
 
 // ---------------------------------------------------------------------------
+// Exact decrements for the Gram target: quad_s = || A^T q_s ||^2 for the
+// basis vectors q_s (FP64), as row sums of squares of W = Q^T A.  FP64
+// matrix cores (v_mfma_f64_16x16x4_f64: operands laid out as in the FP32
+// form, but lane l, register v of the result holds row (l/16) + 4v);
+// A is decoded to FP64 on the way into LDS, so every product is exact and
+// only FP64 accumulation rounds.  Each workgroup owns 64 columns of A and
+// writes one partial per basis vector; a fixed-order reduce follows.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+constexpr int PIT64 = 18;  // LDS row pitch in doubles (16 k values + pad)
+
+__device__ __forceinline__ f64x4 mfma4d(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <int DT, int RB>
+__global__ __launch_bounds__(256) void k_qta_rowsq(const double *__restrict__ Q, int64_t ldq,
+                                                   int kmax, const DevState *st, AView A,
+                                                   double *__restrict__ part, int kpad) {
+  constexpr int NB = 4, NT = 64, RT = 64 * RB;
+  constexpr int ES = EInfo<DT>::esize, EPC = EInfo<DT>::epc, CPC = ES;
+  __shared__ __align__(16) double Xs[RT * PIT64];
+  __shared__ __align__(16) double Ys[NT * PIT64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t m = A.m, n = A.n;
+  int nrow = st ? st->t : kmax;
+  if (nrow > kmax) nrow = kmax;
+  const int64_t j0 = (int64_t)blockIdx.x * NT;
+  const char *abase = (const char *)A.a;
+  const int64_t colb = A.lda * ES;
+  const int ycol = tid / CPC, ych = tid % CPC;
+  const bool yact = tid < NT * CPC;
+  const bool ycolv = yact && (j0 + ycol) < n;
+  const int64_t ksteps = (m + BK - 1) / BK;
+  double jscale[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    const int64_t j = j0 + 16 * nb + (lane & 15);
+    jscale[nb] = j < n ? col_scale(A, j) : 0.0;
+  }
+
+  for (int r0 = 0; r0 < nrow; r0 += RT) {
+    f64x4 acc[RB][NB];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[rb][nb] = f64x4{0.0, 0.0, 0.0, 0.0};
+    double2 xr[2 * RB];
+    uint4 yr;
+    auto gload = [&](int64_t k0) {
+#pragma unroll
+      for (int u = 0; u < 2 * RB; ++u) {
+        const int q = tid + 256 * u;
+        const int row = q >> 3, c = (q & 7) * 2;
+        const int64_t gr = r0 + row, gk = k0 + c;
+        double2 v = make_double2(0.0, 0.0);
+        if (gr < nrow && gk < m) {
+          v = *(const double2 *)(Q + gr * ldq + gk);
+          if (gk + 1 >= m) v.y = 0.0;
+        }
+        xr[u] = v;
+      }
+      const int64_t gk = k0 + ych * EPC;
+      if (ycolv && gk < m)
+        yr = *(const uint4 *)(abase + (j0 + ycol) * colb + gk * ES);
+      else
+        yr = make_uint4(0u, 0u, 0u, 0u);
+    };
+    auto sstore = [&](int64_t k0) {
+#pragma unroll
+      for (int u = 0; u < 2 * RB; ++u) {
+        const int q = tid + 256 * u;
+        const int row = q >> 3, c = (q & 7) * 2;
+        *(double2 *)(Xs + row * PIT64 + c) = xr[u];
+      }
+      if (yact) {
+        float v[EPC];
+        decode16<DT>(yr, v);
+        const int64_t gk = k0 + ych * EPC;
+#pragma unroll
+        for (int e = 0; e < EPC; e += 2)
+          *(double2 *)(Ys + ycol * PIT64 + ych * EPC + e) =
+              make_double2(gk + e < m ? (double)v[e] : 0.0, gk + e + 1 < m ? (double)v[e + 1] : 0.0);
+      }
+    };
+    gload(0);
+    for (int64_t ks = 0; ks < ksteps; ++ks) {
+      __syncthreads();
+      sstore(ks * BK);
+      __syncthreads();
+      if (ks + 1 < ksteps) gload((ks + 1) * BK);
+      const int r = lane & 15, kq = (lane >> 4) * 4;
+      double xa[RB][4], yb[NB][4];
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        const double *px = Xs + (wave * 16 * RB + 16 * rb + r) * PIT64 + kq;
+        const double2 a0 = *(const double2 *)px, a1 = *(const double2 *)(px + 2);
+        xa[rb][0] = a0.x; xa[rb][1] = a0.y; xa[rb][2] = a1.x; xa[rb][3] = a1.y;
+      }
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const double *py = Ys + (16 * nb + r) * PIT64 + kq;
+        const double2 b0 = *(const double2 *)py, b1 = *(const double2 *)(py + 2);
+        yb[nb][0] = b0.x; yb[nb][1] = b0.y; yb[nb][2] = b1.x; yb[nb][3] = b1.y;
+      }
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+          for (int s = 0; s < 4; ++s) acc[rb][nb] = mfma4d(xa[rb][s], yb[nb][s], acc[rb][nb]);
+    }
+    // row sums of squares over this workgroup's 64 columns
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        double sq = 0.0;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const double d = acc[rb][nb][v] * jscale[nb];
+          sq = fma(d, d, sq);
+        }
+        sq += __shfl_xor(sq, 1, 64);
+        sq += __shfl_xor(sq, 2, 64);
+        sq += __shfl_xor(sq, 4, 64);
+        sq += __shfl_xor(sq, 8, 64);
+        // v_mfma_f64_16x16x4_f64: lane l, register v holds D[(l/16) + 4v][l%16]
+        const int row = r0 + wave * 16 * RB + 16 * rb + (lane >> 4) + 4 * v;
+        if ((lane & 15) == 0 && row < nrow) part[(int64_t)blockIdx.x * kpad + row] = sq;
+      }
+  }
+}
+
+// quad[s] = sum over workgroups of part[wg][s], fixed order.
+__global__ void k_qta_reduce(const double *__restrict__ part, int nwg, int kpad, int kmax,
+                             const DevState *st, double *__restrict__ quad) {
+  int nrow = st ? st->t : kmax;
+  if (nrow > kmax) nrow = kmax;
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nrow) return;
+  double acc = 0.0;
+  for (int w = 0; w < nwg; ++w) acc += part[(int64_t)w * kpad + s];
+  quad[s] = acc;
+}
+
+// obj[s+1] = F0 - sum_{x<=s} quad[x] for s < t (the objective from exact decrements)
+__global__ void k_obj_from_quad(const double *F0, const double *quad, const DevState *st,
+                                double *obj) {
+  if (threadIdx.x != 0) return;
+  const int t = st->t;
+  double F = *F0;
+  for (int s = 0; s < t; ++s) {
+    F -= quad[s];
+    obj[s + 1] = F;
+  }
+}
+
+size_t qta_scratch_bytes(int64_t n, int kmax) {
+  const int64_t nwg = (n + 63) / 64;
+  return (size_t)(nwg * kmax + kmax + 64) * sizeof(double);
+}
+
+hipError_t launch_qta(const double *Q, int64_t ldq, int kmax, const DevState *st,
+                      const AView &A, double *scratch, double *quad, hipStream_t s) {
+  const int nwg = (int)((A.n + 63) / 64);
+  double *part = scratch;
+  switch (A.dtype) {
+    case DT_F32:
+      hipLaunchKernelGGL((k_qta_rowsq<DT_F32, 2>), dim3(nwg), dim3(256), 0, s, Q, ldq, kmax, st, A, part, kmax);
+      break;
+    case DT_BF16:
+      hipLaunchKernelGGL((k_qta_rowsq<DT_BF16, 2>), dim3(nwg), dim3(256), 0, s, Q, ldq, kmax, st, A, part, kmax);
+      break;
+    case DT_FP8:
+      hipLaunchKernelGGL((k_qta_rowsq<DT_FP8, 2>), dim3(nwg), dim3(256), 0, s, Q, ldq, kmax, st, A, part, kmax);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_qta_reduce, dim3((unsigned)((kmax + 255) / 256)), dim3(256), 0, s, part, nwg,
+                     kmax, kmax, st, quad);
+  return hipGetLastError();
+}
+
+hipError_t launch_obj_from_quad(const double *F0, const double *quad, const DevState *st,
+                                double *obj, hipStream_t s) {
+  hipLaunchKernelGGL(k_obj_from_quad, dim3(1), dim3(64), 0, s, F0, quad, st, obj);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 template <int DT, int RB, bool GRAM>
 static hipError_t init_t(const float *X, int64_t ldx, int64_t R, const AView &A, double *f0,
                          double *g0, uint8_t *mask0, hipStream_t s) {

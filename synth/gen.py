@@ -10,9 +10,11 @@ The random-projection matrix Omega (n x r) is held row-major with shape
 paper's projection draws one row of Omega per input column (Section 5.1).
 
 Generators return float64 dense matrices (``*_dense``) or float32 column
-stores.  Values are drawn in float64 and rounded once to the storage type.
-Large workloads are drawn on the GPU with torch (``*_torch``); those are
-only used where the data would not fit a CPU test.
+stores; the numpy generators draw in float64 and round once to the storage
+type.  Large workloads are drawn on the GPU with torch (``*_torch``) using
+float32 matrix products only (the small Cholesky factors of the orthonormal
+factors are taken on the host); those are only used where the data would
+not fit a CPU test.
 """
 from __future__ import annotations
 
@@ -167,13 +169,23 @@ def _torch_gen(seed, device):
     return g
 
 
-def _orthonormal_torch(rows, cols, gen, device):
-    """Random orthonormal columns via two rounds of Cholesky QR in float64."""
+def _orthonormal_torch(rows, cols, gen, device, chunk=65536):
+    """Random orthonormal columns (float32, on `device`): Cholesky QR of a Gaussian,
+    twice.  Only plain float32 matrix products run on the device; the small
+    cols x cols Cholesky factor and its inverse are computed on the host."""
+    import numpy as np
     import torch
-    G = torch.randn(rows, cols, generator=gen, device=device, dtype=torch.float64)
+    G = torch.randn(rows, cols, generator=gen, device=device, dtype=torch.float32)
     for _ in range(2):
-        R = torch.linalg.cholesky(G.T @ G).T  # upper triangular, positive diagonal
-        G = torch.linalg.solve_triangular(R, G, upper=True, left=False)
+        S = torch.zeros(cols, cols, dtype=torch.float64)
+        for i0 in range(0, rows, chunk):
+            Gc = G[i0:i0 + chunk]
+            S += (Gc.T @ Gc).double().cpu()
+        R = np.linalg.cholesky(S.numpy()).T            # upper, S = R^T R
+        Rinv = np.linalg.inv(R)
+        Rinv_d = torch.from_numpy(Rinv.astype(np.float32)).to(device)
+        for i0 in range(0, rows, chunk):
+            G[i0:i0 + chunk] = G[i0:i0 + chunk] @ Rinv_d
     return G
 
 
@@ -184,17 +196,18 @@ def spectral_lowrank_torch(m, n, rank, decay, noise, seed, device="cuda", lda=No
     lda = lda_for(m, 4) if lda is None else lda
     gen = _torch_gen(seed, device)
     U = _orthonormal_torch(m, rank, gen, device)
-    s = torch.arange(1, rank + 1, device=device, dtype=torch.float64) ** (-decay)
+    s = torch.arange(1, rank + 1, device=device, dtype=torch.float32) ** (-decay)
     SUt = (U * s).T.contiguous()                      # rank x m
-    out = torch.zeros(n, lda, device=device, dtype=torch.float32)
+    del U
     V = _orthonormal_torch(n, rank, gen, device)      # n x rank
+    out = torch.zeros(n, lda, device=device, dtype=torch.float32)
     for i0 in range(0, n, chunk):
         i1 = min(n, i0 + chunk)
         blk = V[i0:i1] @ SUt                          # columns i0..i1 of A, transposed
         blk += noise * torch.randn(i1 - i0, m, generator=gen, device=device,
-                                   dtype=torch.float64)
-        out[i0:i1, :m] = blk.to(torch.float32)
-    del V, U
+                                   dtype=torch.float32)
+        out[i0:i1, :m] = blk
+    del V
     return out
 
 
@@ -204,15 +217,15 @@ def gauss_lowrank_torch(m, n, rank, noise, seed, device="cuda", lda=None, scale=
     import torch
     lda = lda_for(m, 4) if lda is None else lda
     gen = _torch_gen(seed, device)
-    Ut = torch.randn(rank, m, generator=gen, device=device, dtype=torch.float64) * scale
+    Ut = torch.randn(rank, m, generator=gen, device=device, dtype=torch.float32) * scale
     out = torch.zeros(n, lda, device=device, dtype=torch.float32)
     for i0 in range(0, n, chunk):
         i1 = min(n, i0 + chunk)
-        V = torch.randn(i1 - i0, rank, generator=gen, device=device, dtype=torch.float64)
+        V = torch.randn(i1 - i0, rank, generator=gen, device=device, dtype=torch.float32)
         blk = V @ Ut
         blk += noise * torch.randn(i1 - i0, m, generator=gen, device=device,
-                                   dtype=torch.float64)
-        out[i0:i1, :m] = blk.to(torch.float32)
+                                   dtype=torch.float32)
+        out[i0:i1, :m] = blk
     return out
 
 

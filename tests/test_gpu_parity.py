@@ -217,8 +217,11 @@ def test_scores_after_steps_follow_the_recursion(gpu):
     g = s.read(gpu.STATE_G, n, np.float64)
     fr, gr = ref["fg"][k - 1]
     f0, g0 = ref["fg"][0]
-    np.testing.assert_allclose(g, gr, rtol=0, atol=1e-5 * g0)
-    np.testing.assert_allclose(f, fr, rtol=0, atol=1e-5 * f0 + 1e-9 * f0.max())
+    dg = np.abs(g - gr) / g0
+    df = np.abs(f - fr) / (f0 + 1e-9 * f0.max())
+    ig, jf = int(np.argmax(dg)), int(np.argmax(df))
+    assert dg[ig] <= 1e-5, f"g: col {ig} gpu {g[ig]!r} oracle {gr[ig]!r} g0 {g0[ig]!r} picked {ig in set(idx)}"
+    assert df[jf] <= 1e-5, f"f: col {jf} gpu {f[jf]!r} oracle {fr[jf]!r} f0 {f0[jf]!r} picked {jf in set(idx)}"
 
 
 # ---------------------------------------------------------------- edges ------
