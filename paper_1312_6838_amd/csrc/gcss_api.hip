@@ -149,7 +149,14 @@ struct gcss_ctx {
   gcss_desc d{};
   Layout L{};
   char *ws = nullptr;
+  size_t ws_bytes = 0;
   int target = 0;  // 0 none, 1 explicit B, 2 Gram (B = A)
+  // batched selection (Algorithm 4): cached group table and captured loop
+  std::vector<GroupEnt> bgroups;
+  std::vector<int64_t> bgfirst;
+  std::vector<int64_t> bcol_off;
+  int bk = -1;
+  hipGraphExec_t bgraph = nullptr;
   const float *B = nullptr;
   int64_t r = 0, ldb = 0;
   // last completed selection (host copy), for reuse of its basis
@@ -358,6 +365,7 @@ gcss_status gcss_create(const gcss_desc *d, void *workspace, size_t ws_bytes, gc
   if (!(h->d.tau > 0.0)) h->d.tau = 1e-4;
   h->L = L;
   h->ws = (char *)workspace;
+  h->ws_bytes = ws_bytes;
   h->A.a = d->a;
   h->A.scale = d->a_scale;
   h->A.m = d->m;
@@ -378,6 +386,7 @@ gcss_status gcss_create(const gcss_desc *d, void *workspace, size_t ws_bytes, gc
 void gcss_destroy(gcss_ctx *h) {
   if (!h) return;
   drop_graph(h);
+  if (h->bgraph) (void)hipGraphExecDestroy(h->bgraph);
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   delete h;
@@ -412,6 +421,8 @@ gcss_status gcss_set_target(gcss_ctx *h, const float *b, int64_t r, int64_t ldb)
   }
   h->basis_valid = false;
   drop_graph(h);
+  if (h->bgraph) (void)hipGraphExecDestroy(h->bgraph);
+  h->bgraph = nullptr;
   return GCSS_OK;
 }
 
@@ -592,29 +603,251 @@ gcss_status gcss_get_profile(gcss_ctx *h, gcss_profile *out) {
   return GCSS_OK;
 }
 
+namespace {
+
+// Per-block buffers of the batched selection, carved after the context's own.
+struct BLayout {
+  size_t st, Q, ap64, e1, e2, w, q64, q32, z32, c1, c2, c3, ups, idx, obj, npart, groups, gfirst,
+      gpart, bcnt, pick, a0, sc0, sub, total;
+  int64_t sQ, sQ32, sIO, sC, sUps, ngroups_max;
+};
+
+gcss_desc sub_desc(const gcss_desc *d, int64_t npool, int32_t k_merge) {
+  gcss_desc s = *d;
+  s.n = npool;
+  s.a = nullptr;
+  s.a_scale = nullptr;
+  s.k_max = k_merge;
+  s.self_target = 0;
+  return s;
+}
+
+bool make_blayout(const gcss_desc *d, const Layout &L, int nblocks, int kb, int km, BLayout *B) {
+  const int64_t m = d->m, n = d->n, r = std::max<int64_t>(d->r_max, 1), ldq = L.ldq;
+  B->sQ = ldq * (kb + 1);
+  B->sQ32 = (int64_t)up(std::max<size_t>(L.qbuf, (size_t)ldq), 64);
+  B->sIO = kb + 8;
+  B->sC = kb + 8;
+  B->sUps = r + 8;
+  B->ngroups_max = n / 16 + nblocks + 1;
+  Carve c;
+  B->st = c.take<DevState>(nblocks);
+  B->Q = c.take<double>((size_t)nblocks * B->sQ);
+  B->ap64 = c.take<double>((size_t)nblocks * ldq);
+  B->e1 = c.take<double>((size_t)nblocks * ldq);
+  B->e2 = c.take<double>((size_t)nblocks * ldq);
+  B->w = c.take<double>((size_t)nblocks * ldq);
+  B->q64 = c.take<double>((size_t)nblocks * ldq);
+  B->q32 = c.take<float>((size_t)nblocks * B->sQ32);
+  B->z32 = c.take<float>((size_t)nblocks * B->sQ32);
+  B->c1 = c.take<double>((size_t)nblocks * B->sC);
+  B->c2 = c.take<double>((size_t)nblocks * B->sC);
+  B->c3 = c.take<double>((size_t)nblocks * B->sC);
+  B->ups = c.take<double>((size_t)nblocks * B->sUps);
+  B->idx = c.take<int64_t>((size_t)nblocks * B->sIO);
+  B->obj = c.take<double>((size_t)nblocks * B->sIO);
+  B->npart = c.take<double>((size_t)nblocks * 128);
+  B->groups = c.take<GroupEnt>(B->ngroups_max);
+  B->gfirst = c.take<int64_t>(nblocks + 1);
+  B->gpart = c.take<ArgPart>(B->ngroups_max);
+  B->bcnt = c.take<uint32_t>(64);
+  const int64_t P = (int64_t)nblocks * kb;
+  B->pick = c.take<int64_t>(P);
+  B->a0 = c.take<uint8_t>((size_t)P * d->lda * dtype_bytes(d->a_dtype));
+  B->sc0 = c.take<float>(P);
+  if (km > P) return false;
+  gcss_desc sd = sub_desc(d, P, km);
+  Layout SL;
+  if (!make_layout(&sd, kPlanCU, &SL)) return false;
+  B->sub = c.take<uint8_t>(SL.total);
+  B->total = up(c.off, 256);
+  return true;
+}
+
+// One lockstep step of all blocks.
+hipError_t enqueue_batched_step(gcss_ctx *h, const BLayout &B, char *base, int nb, int kb,
+                                int grid) {
+  auto at = [&](size_t off) { return base + off; };
+  const int64_t m = h->d.m, ldq = h->L.ldq, r = h->r;
+  double *Q = (double *)at(B.Q), *ap = (double *)at(B.ap64), *e1 = (double *)at(B.e1),
+         *e2 = (double *)at(B.e2), *w = (double *)at(B.w), *q64 = (double *)at(B.q64),
+         *c1 = (double *)at(B.c1), *c2 = (double *)at(B.c2), *c3 = (double *)at(B.c3),
+         *ups = (double *)at(B.ups);
+  float *q32 = (float *)at(B.q32), *z32 = (float *)at(B.z32);
+  StepBufs sb{};
+  sb.st = (DevState *)at(B.st);
+  sb.Q = Q;
+  sb.ldq = ldq;
+  sb.q32 = q32;
+  sb.z32 = z32;
+  sb.q64 = q64;
+  sb.g0 = h->at<double>(h->L.g0);
+  sb.mask = h->at<uint8_t>(h->L.mask);
+  sb.idx = (int64_t *)at(B.idx);
+  sb.obj = (double *)at(B.obj);
+  sb.part = (double *)at(B.npart);
+  BatchStride bs{1, B.sQ, ldq, B.sQ32, B.sIO, 128};
+  hipStream_t s = h->stream;
+  hipError_t e;
+  const AView &A = h->A;
+  if ((e = launch_cols(Q, nullptr, ldq, m, 1, 0, kb, VEC_F64, ap, A, c1, CF_NONE, sb, s, nb, bs, ArgStride{B.sQ, ldq, B.sC, 0}))) return e;
+  if ((e = launch_rows(Q, nullptr, ldq, m, 1, 0, VEC_F64, ap, A, c1, e1, nullptr, RF_NONE, sb, s, nb, bs, ArgStride{B.sQ, ldq, ldq, B.sC}))) return e;
+  if ((e = launch_cols(Q, nullptr, ldq, m, 1, 0, kb, VEC_F64, e1, A, c2, CF_NONE, sb, s, nb, bs, ArgStride{B.sQ, ldq, B.sC, 0}))) return e;
+  if ((e = launch_rows(Q, nullptr, ldq, m, 1, 0, VEC_F64, e1, A, c2, e2, nullptr, RF_GS2, sb, s, nb, bs, ArgStride{B.sQ, ldq, ldq, B.sC}))) return e;
+  if ((e = launch_cols(nullptr, h->B, h->ldb, m, 0, (int)r, (int)r, VEC_F64, q64, A, ups, CF_UPS, sb, s, nb, bs, ArgStride{0, ldq, B.sUps, 0}))) return e;
+  if ((e = launch_rows(nullptr, h->B, h->ldb, m, 0, (int)r, -1, nullptr, A, ups, w, nullptr, RF_NONE, sb, s, nb, bs, ArgStride{0, 0, ldq, B.sUps}))) return e;
+  if ((e = launch_cols(Q, nullptr, ldq, m, 1, 0, kb, VEC_F64, w, A, c3, CF_NONE, sb, s, nb, bs, ArgStride{B.sQ, ldq, B.sC, 0}))) return e;
+  if ((e = launch_rows(Q, nullptr, ldq, m, 1, 0, VEC_F64, w, A, c3, nullptr, z32, RF_Z, sb, s, nb, bs, ArgStride{B.sQ, ldq, 0, B.sC}))) return e;
+  if ((e = launch_stream_batched(h->L.geo, grid, A, (const GroupEnt *)at(B.groups), (int64_t)h->bgroups.size(), q32, z32, B.sQ32,
+                                 h->at<double>(h->L.f), h->at<double>(h->L.g), h->at<double>(h->L.g0), h->at<uint8_t>(h->L.mask),
+                                 (ArgPart *)at(B.gpart), (const DevState *)at(B.st), (uint32_t *)at(B.bcnt), 0, s))) return e;
+  return launch_block_argmax(A, (const ArgPart *)at(B.gpart), (const int64_t *)at(B.gfirst), nb, (DevState *)at(B.st), ap, ldq, s);
+}
+
+}  // namespace
+
 gcss_status gcss_batched_workspace_size(const gcss_desc *d, int32_t nblocks, int32_t k_block,
                                         int32_t k_merge, size_t *bytes) {
-  (void)d;
-  (void)nblocks;
-  (void)k_block;
-  (void)k_merge;
-  (void)bytes;
-  return fail(GCSS_ERR_UNSUPPORTED, "batched selection not built yet");
+  gcss_status st = check_desc(d);
+  if (st != GCSS_OK) return st;
+  if (!bytes || nblocks < 1 || k_block < 1 || k_merge < 1) return fail(GCSS_ERR_ARG, "bad batched sizes");
+  if ((int64_t)nblocks * k_block < k_merge) return fail(GCSS_ERR_ARG, "k_merge exceeds the pool (nblocks * k_block)");
+  Layout L;
+  if (!make_layout(d, kPlanCU, &L)) return fail(GCSS_ERR_UNSUPPORTED, "m too large for the stream kernel");
+  BLayout B;
+  if (!make_blayout(d, L, nblocks, k_block, k_merge, &B)) return fail(GCSS_ERR_UNSUPPORTED, "batched layout");
+  *bytes = B.total + 256;
+  return GCSS_OK;
 }
 
 gcss_status gcss_select_batched(gcss_ctx *h, int32_t nblocks, const int64_t *col_off,
                                 int32_t k_block, int32_t k_merge, int64_t *idx_block,
                                 int64_t *idx_merge, double *obj_merge, int32_t *n_merge) {
-  (void)h;
-  (void)nblocks;
-  (void)col_off;
-  (void)k_block;
-  (void)k_merge;
-  (void)idx_block;
-  (void)idx_merge;
-  (void)obj_merge;
-  (void)n_merge;
-  return fail(GCSS_ERR_UNSUPPORTED, "batched selection not built yet");
+  if (check_ctx(h)) return GCSS_ERR_ARG;
+  if (!col_off || !idx_block || !idx_merge) return fail(GCSS_ERR_ARG, "null argument");
+  if (nblocks < 1 || k_block < 1 || k_merge < 1) return fail(GCSS_ERR_ARG, "bad batched sizes");
+  if ((int64_t)nblocks * k_block < k_merge) return fail(GCSS_ERR_ARG, "k_merge exceeds the pool (nblocks * k_block)");
+  if (h->target != 1) return fail(GCSS_ERR_STATE, "batched selection needs an explicit target B");
+  if (col_off[0] != 0 || col_off[nblocks] != h->d.n) return fail(GCSS_ERR_ARG, "col_off must run from 0 to n");
+  for (int b = 0; b < nblocks; ++b)
+    if (col_off[b + 1] <= col_off[b]) return fail(GCSS_ERR_ARG, "col_off must be strictly increasing");
+  BLayout B;
+  if (!make_blayout(&h->d, h->L, nblocks, k_block, k_merge, &B)) return fail(GCSS_ERR_UNSUPPORTED, "batched layout");
+  char *base = (char *)up((uintptr_t)(h->ws + h->L.total), 256);
+  if ((size_t)(base - h->ws) + B.total > h->ws_bytes)
+    return fail(GCSS_ERR_WORKSPACE, "workspace lacks the batched region (gcss_batched_workspace_size)");
+  hipStream_t s = h->stream;
+
+  // group table: groups of up to G consecutive columns, never across blocks
+  std::vector<int64_t> off(col_off, col_off + nblocks + 1);
+  const bool same = h->bgraph && h->bk == k_block && off == h->bcol_off;
+  if (!same) {
+    const int G = h->L.geo.g;
+    h->bgroups.clear();
+    h->bgfirst.assign(nblocks + 1, 0);
+    for (int b = 0; b < nblocks; ++b) {
+      h->bgfirst[b] = (int64_t)h->bgroups.size();
+      for (int64_t c0 = off[b]; c0 < off[b + 1]; c0 += G)
+        h->bgroups.push_back(GroupEnt{c0, (int32_t)std::min<int64_t>(G, off[b + 1] - c0), b});
+    }
+    h->bgfirst[nblocks] = (int64_t)h->bgroups.size();
+    if ((int64_t)h->bgroups.size() > B.ngroups_max) return fail(GCSS_ERR_UNSUPPORTED, "too many column groups");
+    HIPCHK(hipMemcpyAsync(base + B.groups, h->bgroups.data(), sizeof(GroupEnt) * h->bgroups.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(base + B.gfirst, h->bgfirst.data(), sizeof(int64_t) * h->bgfirst.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (h->bgraph) (void)hipGraphExecDestroy(h->bgraph);
+    h->bgraph = nullptr;
+    h->bcol_off = off;
+    h->bk = k_block;
+  }
+  int grid = 1;
+  HIPCHK(batched_stream_grid(h->L.geo, h->d.a_dtype, h->num_cu, (int64_t)h->bgroups.size(), &grid));
+
+  // lockstep loop of all blocks, captured once and replayed
+  if (!h->bgraph) {
+    if (!h->cap_stream) HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    hipStream_t user = h->stream;
+    h->stream = h->cap_stream;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeRelaxed);
+    if (!e) e = launch_batch_begin(h->at<double>(h->L.f0), h->at<double>(h->L.g0), h->at<uint8_t>(h->L.mask0),
+                                   h->at<double>(h->L.f), h->at<double>(h->L.g), h->at<uint8_t>(h->L.mask), h->d.n,
+                                   (DevState *)(base + B.st), nblocks, k_block, (int64_t *)(base + B.idx),
+                                   (double *)(base + B.obj), B.sIO, h->F0(), h->d.tau, (uint32_t *)(base + B.bcnt),
+                                   h->cap_stream);
+    if (!e) e = launch_stream_batched(h->L.geo, grid, h->A, (const GroupEnt *)(base + B.groups), (int64_t)h->bgroups.size(),
+                                      (const float *)(base + B.q32), (const float *)(base + B.z32), B.sQ32,
+                                      h->at<double>(h->L.f), h->at<double>(h->L.g), h->at<double>(h->L.g0),
+                                      h->at<uint8_t>(h->L.mask), (ArgPart *)(base + B.gpart), (const DevState *)(base + B.st),
+                                      (uint32_t *)(base + B.bcnt), 1, h->cap_stream);
+    if (!e) e = launch_block_argmax(h->A, (const ArgPart *)(base + B.gpart), (const int64_t *)(base + B.gfirst), nblocks,
+                                    (DevState *)(base + B.st), (double *)(base + B.ap64), h->L.ldq, h->cap_stream);
+    for (int i = 0; !e && i < k_block + kSpareSlots; ++i) e = enqueue_batched_step(h, B, base, nblocks, k_block, grid);
+    hipError_t e2 = hipStreamEndCapture(h->cap_stream, &g);
+    h->stream = user;
+    if (e || e2) {
+      if (g) (void)hipGraphDestroy(g);
+      return fail(GCSS_ERR_DEVICE, "batched capture failed: %s", hipGetErrorString(e ? e : e2));
+    }
+    e = hipGraphInstantiate(&h->bgraph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e) {
+      h->bgraph = nullptr;
+      return fail(GCSS_ERR_DEVICE, "batched graph instantiate: %s", hipGetErrorString(e));
+    }
+  }
+  HIPCHK(hipGraphLaunch(h->bgraph, s));
+
+  // per-block picks back to the host
+  std::vector<int64_t> bidx((size_t)nblocks * B.sIO);
+  std::vector<DevState> bst(nblocks);
+  HIPCHK(hipMemcpyAsync(bidx.data(), base + B.idx, sizeof(int64_t) * bidx.size(), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(bst.data(), base + B.st, sizeof(DevState) * nblocks, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  std::vector<int64_t> pool;
+  for (int b = 0; b < nblocks; ++b)
+    for (int j = 0; j < k_block; ++j) {
+      const int64_t v = j < bst[b].t ? bidx[(size_t)b * B.sIO + j] : -1;
+      idx_block[(size_t)b * k_block + j] = v;
+      if (v >= 0) pool.push_back(v);
+    }
+  h->basis_valid = false;
+  for (int j = 0; j < k_merge; ++j) idx_merge[j] = -1;
+  if (pool.empty()) {
+    if (n_merge) *n_merge = 0;
+    return GCSS_WARN_EXHAUSTED;
+  }
+
+  // second phase: selection over the pooled columns against the same B
+  const int64_t P = (int64_t)pool.size();
+  HIPCHK(hipMemcpyAsync(base + B.pick, pool.data(), sizeof(int64_t) * P, hipMemcpyHostToDevice, s));
+  HIPCHK(launch_gather_cols(h->A, (const int64_t *)(base + B.pick), P, base + B.a0, (float *)(base + B.sc0), s));
+  const int32_t km = (int32_t)std::min<int64_t>(k_merge, P);
+  gcss_desc sd = sub_desc(&h->d, P, km);
+  sd.a = base + B.a0;
+  sd.a_scale = h->d.a_dtype == GCSS_FP8_E4M3 ? (const float *)(base + B.sc0) : nullptr;
+  sd.tau = h->d.tau;
+  sd.stream = (void *)s;
+  size_t sub_bytes = 0;
+  gcss_status st = gcss_workspace_size(&sd, &sub_bytes);
+  if (st != GCSS_OK) return st;
+  gcss_ctx *sub = nullptr;
+  st = gcss_create(&sd, base + B.sub, sub_bytes, &sub);
+  if (st != GCSS_OK) return st;
+  st = gcss_set_target(sub, h->B, h->r, h->ldb);
+  std::vector<int64_t> loc(km, -1);
+  std::vector<double> obj(km + 1, 0.0);
+  int32_t ns = 0;
+  if (st == GCSS_OK) st = gcss_select(sub, km, loc.data(), obj.data(), &ns);
+  gcss_destroy(sub);
+  if (st < 0) return st;
+  for (int j = 0; j < km; ++j) idx_merge[j] = loc[j] >= 0 ? pool[loc[j]] : -1;
+  if (obj_merge) {
+    for (int j = 0; j <= km; ++j) obj_merge[j] = obj[j];
+    for (int j = km + 1; j <= k_merge; ++j) obj_merge[j] = obj[km];
+  }
+  if (n_merge) *n_merge = ns;
+  return (ns < k_merge) ? GCSS_WARN_EXHAUSTED : GCSS_OK;
 }
 
 gcss_status gcss_quantize(const float *a, int64_t m, int64_t n, int64_t lda, int32_t dtype,

@@ -90,20 +90,55 @@ struct StepBufs {
   int advance;                 // basis-only mode: the GS2 finish also advances t
 };
 
+// Several independent problems (the column blocks of Algorithm 4) run the
+// same per-step kernels side by side: gridDim.y = number of problems, and
+// problem b finds its buffers at the base pointers plus b times these
+// strides (all zero for a single problem).
+struct BatchStride {
+  int64_t st;    // DevState entries
+  int64_t Q;     // doubles between bases
+  int64_t vec;   // doubles between the m-vectors (ap64, e1, e2, w, q64)
+  int64_t q32;   // floats between q32 (and z32) vectors
+  int64_t io;    // entries between idx / obj arrays
+  int64_t part;  // doubles between norm-partial arrays
+};
+
+__device__ __forceinline__ StepBufs shift_bufs(StepBufs sb, const BatchStride &bs, int b) {
+  sb.st += b * bs.st;
+  sb.Q += b * bs.Q;
+  sb.q32 += b * bs.q32;
+  sb.z32 += b * bs.q32;
+  sb.q64 += b * bs.vec;
+  sb.idx += b * bs.io;
+  sb.obj += b * bs.io;
+  sb.part += b * bs.part;
+  return sb;
+}
+
+// Strides of the vector arguments of one cols / rows launch (per problem).
+struct ArgStride {
+  int64_t m;    // matrix M (0: shared, e.g. the target B)
+  int64_t vec;  // base vector
+  int64_t out;  // output
+  int64_t c;    // coefficients
+};
+
 // Column dots:  out[s] = sum_{j<m} M[j + s*ldm] * v[j],  s < ns,
 //   ns = (ns_from_t ? st->t : 0) + ns_add; v = vec (VEC_F64) or column p of A
 //   (VEC_ACOL).  M is FP64 (Mq) or FP32 (Mf).  final_mode: CF_*.
 hipError_t launch_cols(const double *Mq, const float *Mf, int64_t ldm, int64_t m,
                        int ns_from_t, int ns_add, int max_ns, int vsrc, const double *vec,
                        const AView &A, double *out, int final_mode, const StepBufs &sb,
-                       hipStream_t s);
+                       hipStream_t s, int nprob = 1, BatchStride bs = BatchStride{},
+                       ArgStride as = ArgStride{});
 // Row updates:  out[j] = v[j] - sum_{s<ns} M[j + s*ldm] * c[s]  (v given), or
 //   out[j] = sum_{s<ns} M[j + s*ldm] * c[s]  (vsrc < 0: no v).  Writes out64
 //   and/or out32.  final_mode: RF_*.
 hipError_t launch_rows(const double *Mq, const float *Mf, int64_t ldm, int64_t m,
                        int ns_from_t, int ns_add, int vsrc, const double *vec, const AView &A,
                        const double *c, double *out64, float *out32, int final_mode,
-                       const StepBufs &sb, hipStream_t s);
+                       const StepBufs &sb, hipStream_t s, int nprob = 1,
+                       BatchStride bs = BatchStride{}, ArgStride as = ArgStride{});
 // Start of a selection: f = f0, g = g0, mask = mask0, state reset, outputs cleared.
 hipError_t launch_select_begin(const double *f0, const double *g0, const uint8_t *mask0,
                                double *f, double *g, uint8_t *mask, int64_t n,
@@ -159,6 +194,28 @@ hipError_t launch_quantize(const float *a, int64_t m, int64_t n, int64_t lda, in
                            void *out, int64_t ldo, float *scales, hipStream_t s);
 
 // ---- batched (k_batched.hip) ----
-struct BatchedLayout;
+// One group of consecutive columns inside one block of Algorithm 4.
+struct GroupEnt {
+  int64_t col0;
+  int32_t ncol;
+  int32_t blk;
+};
+hipError_t batched_stream_grid(const StreamGeo &geo, int dtype, int num_cu, int64_t ngroups,
+                               int *grid);
+hipError_t launch_stream_batched(const StreamGeo &geo, int grid, const AView &A,
+                                 const GroupEnt *groups, int64_t ngroups, const float *q32,
+                                 const float *z32, int64_t qstride, double *f, double *g,
+                                 const double *g0, const uint8_t *mask, ArgPart *gpart,
+                                 const DevState *stb, uint32_t *bcnt, int score_only,
+                                 hipStream_t s);
+hipError_t launch_block_argmax(const AView &A, const ArgPart *gpart, const int64_t *gfirst,
+                               int nprob, DevState *stb, double *ap64, int64_t apstride,
+                               hipStream_t s);
+hipError_t launch_batch_begin(const double *f0, const double *g0, const uint8_t *mask0,
+                              double *f, double *g, uint8_t *mask, int64_t n, DevState *stb,
+                              int nprob, int k, int64_t *idx, double *obj, int64_t iostride,
+                              const double *F0, double tau, uint32_t *bcnt, hipStream_t s);
+hipError_t launch_gather_cols(const AView &A, const int64_t *pick, int64_t npick, void *a0,
+                              float *scale0, hipStream_t s);
 
 }  // namespace gcss

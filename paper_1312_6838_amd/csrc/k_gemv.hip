@@ -34,8 +34,15 @@ __global__ __launch_bounds__(256) void k_cols(const MT *__restrict__ M, int64_t 
                                               int ns_from_t, int ns_add,
                                               const double *__restrict__ vec, AView A,
                                               double *__restrict__ out, int final_mode,
-                                              StepBufs sb) {
+                                              StepBufs sb, BatchStride bs, ArgStride as) {
   __shared__ double red[4];
+  {
+    const int b = blockIdx.y;
+    sb = shift_bufs(sb, bs, b);
+    M += b * as.m;
+    if (vec) vec += b * as.vec;
+    out += b * as.out;
+  }
   DevState *st = sb.st;
   if (st->done || st->skip) return;
   const int t = st->t;
@@ -94,11 +101,21 @@ __global__ __launch_bounds__(1024) void k_rows(const MT *__restrict__ M, int64_t
                                                int ns_from_t, int ns_add,
                                                const double *__restrict__ vec, AView A,
                                                const double *__restrict__ c, double *out64,
-                                               float *out32, int final_mode, StepBufs sb) {
+                                               float *out32, int final_mode, StepBufs sb,
+                                               BatchStride bs, ArgStride as) {
   __shared__ double2 red[kRowsWaves][64];
   __shared__ double wsq[2];
   __shared__ double nrm;
   __shared__ int ok;
+  {
+    const int b = blockIdx.y;
+    sb = shift_bufs(sb, bs, b);
+    M += b * as.m;
+    if (vec) vec += b * as.vec;
+    c += b * as.c;
+    if (out64) out64 += b * as.out;
+    if (out32) out32 += b * bs.q32;
+  }
   DevState *st = sb.st;
   if (st->done || st->skip) return;
   const int t = st->t;
@@ -375,53 +392,56 @@ static inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + p
 template <typename MT>
 static hipError_t cols_t(const MT *M, int64_t ldm, int64_t m, int ns_from_t, int ns_add,
                          int max_ns, int vsrc, const double *vec, const AView &A, double *out,
-                         int final_mode, const StepBufs &sb, hipStream_t s) {
-  const unsigned grid = (unsigned)(max_ns > 0 ? max_ns : 1);
+                         int final_mode, const StepBufs &sb, hipStream_t s, int nprob,
+                         BatchStride bs, ArgStride as) {
+  const dim3 grid((unsigned)(max_ns > 0 ? max_ns : 1), (unsigned)nprob);
   if (vsrc == VEC_ACOL)
-    hipLaunchKernelGGL((k_cols<MT, VEC_ACOL>), dim3(grid), dim3(256), 0, s, M, ldm, m, ns_from_t,
-                       ns_add, vec, A, out, final_mode, sb);
+    hipLaunchKernelGGL((k_cols<MT, VEC_ACOL>), grid, dim3(256), 0, s, M, ldm, m, ns_from_t,
+                       ns_add, vec, A, out, final_mode, sb, bs, as);
   else
-    hipLaunchKernelGGL((k_cols<MT, VEC_F64>), dim3(grid), dim3(256), 0, s, M, ldm, m, ns_from_t,
-                       ns_add, vec, A, out, final_mode, sb);
+    hipLaunchKernelGGL((k_cols<MT, VEC_F64>), grid, dim3(256), 0, s, M, ldm, m, ns_from_t,
+                       ns_add, vec, A, out, final_mode, sb, bs, as);
   return hipGetLastError();
 }
 
 hipError_t launch_cols(const double *Mq, const float *Mf, int64_t ldm, int64_t m,
                        int ns_from_t, int ns_add, int max_ns, int vsrc, const double *vec,
                        const AView &A, double *out, int final_mode, const StepBufs &sb,
-                       hipStream_t s) {
+                       hipStream_t s, int nprob, BatchStride bs, ArgStride as) {
   if (Mq) return cols_t<double>(Mq, ldm, m, ns_from_t, ns_add, max_ns, vsrc, vec, A, out,
-                                final_mode, sb, s);
+                                final_mode, sb, s, nprob, bs, as);
   return cols_t<float>(Mf, ldm, m, ns_from_t, ns_add, max_ns, vsrc, vec, A, out, final_mode,
-                       sb, s);
+                       sb, s, nprob, bs, as);
 }
 
 template <typename MT>
 static hipError_t rows_t(const MT *M, int64_t ldm, int64_t m, int ns_from_t, int ns_add,
                          int vsrc, const double *vec, const AView &A, const double *c,
                          double *out64, float *out32, int final_mode, const StepBufs &sb,
-                         hipStream_t s) {
-  const unsigned grid = blocks_for(m, 128);
+                         hipStream_t s, int nprob, BatchStride bs, ArgStride as) {
+  const dim3 grid(blocks_for(m, 128), (unsigned)nprob);
+  const dim3 block(64 * kRowsWaves);
   if (vsrc == VEC_ACOL)
-    hipLaunchKernelGGL((k_rows<MT, VEC_ACOL>), dim3(grid), dim3(64 * kRowsWaves), 0, s, M, ldm, m, ns_from_t,
-                       ns_add, vec, A, c, out64, out32, final_mode, sb);
+    hipLaunchKernelGGL((k_rows<MT, VEC_ACOL>), grid, block, 0, s, M, ldm, m, ns_from_t, ns_add,
+                       vec, A, c, out64, out32, final_mode, sb, bs, as);
   else if (vsrc == VEC_F64)
-    hipLaunchKernelGGL((k_rows<MT, VEC_F64>), dim3(grid), dim3(64 * kRowsWaves), 0, s, M, ldm, m, ns_from_t,
-                       ns_add, vec, A, c, out64, out32, final_mode, sb);
+    hipLaunchKernelGGL((k_rows<MT, VEC_F64>), grid, block, 0, s, M, ldm, m, ns_from_t, ns_add,
+                       vec, A, c, out64, out32, final_mode, sb, bs, as);
   else
-    hipLaunchKernelGGL((k_rows<MT, -1>), dim3(grid), dim3(64 * kRowsWaves), 0, s, M, ldm, m, ns_from_t,
-                       ns_add, vec, A, c, out64, out32, final_mode, sb);
+    hipLaunchKernelGGL((k_rows<MT, -1>), grid, block, 0, s, M, ldm, m, ns_from_t, ns_add, vec, A,
+                       c, out64, out32, final_mode, sb, bs, as);
   return hipGetLastError();
 }
 
 hipError_t launch_rows(const double *Mq, const float *Mf, int64_t ldm, int64_t m,
                        int ns_from_t, int ns_add, int vsrc, const double *vec, const AView &A,
                        const double *c, double *out64, float *out32, int final_mode,
-                       const StepBufs &sb, hipStream_t s) {
+                       const StepBufs &sb, hipStream_t s, int nprob, BatchStride bs,
+                       ArgStride as) {
   if (Mq) return rows_t<double>(Mq, ldm, m, ns_from_t, ns_add, vsrc, vec, A, c, out64, out32,
-                                final_mode, sb, s);
+                                final_mode, sb, s, nprob, bs, as);
   return rows_t<float>(Mf, ldm, m, ns_from_t, ns_add, vsrc, vec, A, c, out64, out32,
-                       final_mode, sb, s);
+                       final_mode, sb, s, nprob, bs, as);
 }
 
 hipError_t launch_select_begin(const double *f0, const double *g0, const uint8_t *mask0,
