@@ -495,8 +495,9 @@ double orc_fp8_decode(uint8_t c) {
 }
 
 /* Nearest E4M3 code to x, ties to the even code, magnitudes above 448
- * saturate to 448, NaN stays NaN.  Found by walking the 127 finite
- * non-negative codes in increasing order. */
+ * saturate to 448, NaN stays NaN.  The 127 finite non-negative codes are
+ * increasing in value; a binary search finds the largest code not above |x|,
+ * then the nearer of it and the next code is taken. */
 uint8_t orc_fp8_encode(float x) {
   uint32_t b;
   memcpy(&b, &x, 4);
@@ -504,18 +505,24 @@ uint8_t orc_fp8_encode(float x) {
   if (isnan(x)) return (uint8_t)(sign | 0x7Fu);
   double ax = fabs((double)x);
   if (ax >= 448.0) return (uint8_t)(sign | 0x7Eu);
-  uint8_t lo = 0;
-  while (lo < 0x7E && orc_fp8_decode((uint8_t)(lo + 1)) <= ax) ++lo;
-  double vlo = orc_fp8_decode(lo);
+  int lo = 0, hi = 0x7E; /* decode(lo) <= ax < decode(hi) */
+  while (hi - lo > 1) {
+    int mid = (lo + hi) / 2;
+    if (orc_fp8_decode((uint8_t)mid) <= ax)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  double vlo = orc_fp8_decode((uint8_t)lo);
   if (vlo == ax) return (uint8_t)(sign | lo);
   double vhi = orc_fp8_decode((uint8_t)(lo + 1));
   uint8_t code;
   if (ax - vlo < vhi - ax)
-    code = lo;
+    code = (uint8_t)lo;
   else if (ax - vlo > vhi - ax)
     code = (uint8_t)(lo + 1);
   else
-    code = (lo & 1u) ? (uint8_t)(lo + 1) : lo;
+    code = (lo & 1) ? (uint8_t)(lo + 1) : (uint8_t)lo;
   return (uint8_t)(sign | code);
 }
 

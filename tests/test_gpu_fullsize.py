@@ -1,0 +1,201 @@
+"""GPU path at the full workload sizes, in the launch configuration bench.py
+times, checked with the oracle on what it can compute one by one (sampled
+projection entries, sampled initial scores, quantizer codes, the greedy
+criterion of sampled candidates given the GPU's prefix, the explicit FP64
+error of the picks) and on properties that hold at any size (distinct
+picks, monotone objective, objective = explicit error)."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import dense
+import synth
+from tests.gpu_util import rel
+
+pytestmark = pytest.mark.gpu
+
+
+def host(A, m, rows=None):
+    """Column store rows (columns of A) on the GPU -> float64 (c, m) numpy."""
+    X = A if rows is None else A[rows]
+    return X[:, :m].double().cpu().numpy()
+
+
+def project_ref(A, m, Om, chunk=32768):
+    """B = A Omega in FP64 on the host (oracle definition), streamed from the GPU."""
+    n, r = Om.shape
+    B = np.zeros((m, r))
+    for i0 in range(0, n, chunk):
+        i1 = min(n, i0 + chunk)
+        B += dense.project(A[i0:i1, :m].double().cpu().numpy(), m,
+                           Om[i0:i1].double().cpu().numpy(), chunk=chunk)
+    return B
+
+
+def check_greedy(A, m, idx, B, steps, rng, ncand=32, tol=1e-5):
+    """The GPU's pick at step t maximises the criterion over sampled candidates."""
+    n = A.shape[0]
+    for t in steps:
+        prefix = [int(x) for x in idx[:t]]
+        cand = [int(x) for x in rng.choice(n, ncand, replace=False) if int(x) not in prefix]
+        cols = cand + [int(idx[t])]
+        AS = host(A, m, prefix).T if prefix else np.zeros((m, 0))
+        sc = dense.scores(AS, host(A, m, cols).T, B)
+        assert sc[-1] >= np.max(sc[:-1]) * (1 - tol), (t, sc[-1], np.max(sc[:-1]))
+
+
+def common_checks(idx, obj, ns, k):
+    assert ns == k
+    assert len(set(int(x) for x in idx)) == k
+    assert np.all(np.diff(obj) <= 0)
+
+
+@pytest.mark.timeout(600)
+def test_full_css_4096x65536_k200(gpu):
+    import torch
+    w = synth.workload("css_4096x65536_k200")
+    m, n, k = w["m"], w["n"], w["k"]
+    A = synth.spectral_lowrank_torch(m, n, w["rank"], w["decay"], w["noise"], 0)
+    sel = gpu.Selector(A, m, k_max=k, self_target=True)
+    sel.set_target(None)
+    idx, obj, ns, st = sel.select(k)
+    err = sel.reconstruction_error(idx)
+    common_checks(idx, obj, ns, k)
+    Ah = host(A, m)                       # (n, m) float64
+    rng = np.random.default_rng(0)
+    samp = np.sort(rng.choice(n, 24, replace=False))
+    f0 = sel.read(gpu.STATE_F0, n, np.float64)[samp]
+    g0 = sel.read(gpu.STATE_G0, n, np.float64)[samp]
+    fr, gr = oracle.init_scores(np.ascontiguousarray(Ah[samp]), m, B=Ah)  # B = A, one by one
+    np.testing.assert_allclose(g0, gr, rtol=1e-12)
+    np.testing.assert_allclose(f0, fr, rtol=1e-4)
+    Bt = Ah.T                             # B = A, m x n
+    e = dense.error(Ah[idx].T, Bt)
+    assert rel(obj[k], e) <= 1e-5 and rel(err, e) <= 1e-5
+    assert rel(obj[k // 2], dense.error(Ah[idx[:k // 2]].T, Bt)) <= 1e-5
+    check_greedy(A, m, idx, Bt, [0, k - 1], rng, ncand=24)
+    del A
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.timeout(600)
+def test_full_gcss_2048x1048576_r256_k100_fp32_and_bf16(gpu):
+    import torch
+    w = synth.workload("gcss_2048x1048576_r256_k100")
+    m, n, k, r = w["m"], w["n"], w["k"], w["r"]
+    A = synth.spectral_lowrank_torch(m, n, w["rank"], w["decay"], w["noise"], 0)
+    Om = synth.omega_gauss_torch(n, r, 1)
+    sel = gpu.Selector(A, m, k_max=k, r_max=r)
+    Bg = sel.project_target(Om)[:, :m].double().cpu().numpy().T
+    idx, obj, ns, st = sel.select(k)
+    err = sel.reconstruction_error(idx)
+    common_checks(idx, obj, ns, k)
+    B = project_ref(A, m, Om)
+    scale = np.sqrt(np.sum(B * B, axis=1, keepdims=True) * np.sum(B * B, axis=0, keepdims=True) / B.shape[1])
+    assert np.max(np.abs(Bg - B) / scale) < 1e-5
+    rng = np.random.default_rng(1)
+    samp = np.sort(rng.choice(n, 32, replace=False))
+    f0 = sel.read(gpu.STATE_F0, n, np.float64)[samp]
+    fr, gr = oracle.init_scores(host(A, m, samp), m, B=np.ascontiguousarray(B.T))
+    np.testing.assert_allclose(f0, fr, rtol=1e-4)
+    e32 = dense.error(host(A, m, idx).T, B)
+    assert rel(obj[k], e32) <= 1e-5 and rel(err, e32) <= 1e-5
+    check_greedy(A, m, idx, B, [0, k // 2, k - 1], rng)
+    # BF16 stream of the same data: stored codes bit-exact with the oracle's,
+    # selection quality within 1e-3 of the FP32 run on the FP32 data
+    A16, _ = gpu.quantize_tensor(A, m, "bf16")
+    cols = np.sort(rng.choice(n, 16, replace=False))
+    ref_codes = oracle.quantize_bf16(A[cols].cpu().numpy(), m, ldo=A16.shape[1])
+    assert np.array_equal(A16[cols].cpu().numpy().view(np.uint16), ref_codes)
+    s16 = gpu.Selector(A16, m, k_max=k, r_max=r)
+    s16.project_target(Om)
+    i16, o16, n16, _ = s16.select(k)
+    common_checks(i16, o16, n16, k)
+    e16 = dense.error(host(A, m, i16).T, B)
+    assert abs(e16 - e32) <= 1e-3 * e32
+    del A, A16, Om
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.timeout(600)
+def test_full_batched_1024_64blocks(gpu):
+    import torch
+    w = synth.workload("batched_1024_64blocks_r128")
+    m, r, kb, km = w["m"], w["r"], w["k_block"], w["k_merge"]
+    widths = synth.block_widths(w["nblocks"], w["wlo"], w["whi"], 0)
+    off = np.concatenate([[0], np.cumsum(widths)]).astype(np.int64)
+    n = int(off[-1])
+    A = synth.gauss_lowrank_torch(m, n, w["rank"], w["noise"], 0, scale=1.0 / np.sqrt(w["rank"]))
+    Om = synth.omega_gauss_torch(n, r, 1)
+    sel = gpu.Selector(A, m, k_max=kb, r_max=r, batched=(len(widths), kb, km))
+    sel.project_target(Om)
+    ib, im, om, nm, st = sel.select_batched(off, kb, km)
+    assert nm == km and st == gpu.OK
+    B = project_ref(A, m, Om)
+    # three blocks (the two narrowest and one wide) against the oracle's Algorithm 3
+    order = np.argsort(widths)
+    for b in [int(order[0]), int(order[1]), int(order[len(order) // 2])]:
+        Ab = host(A, m, np.arange(off[b], off[b + 1]))
+        rb = oracle.select(Ab, m, kb, B=np.ascontiguousarray(B.T))
+        sep = int(np.argmax(rb["gap"] < 1e-4)) if np.any(rb["gap"] < 1e-4) else kb
+        got = [int(x) - int(off[b]) for x in ib[b]]
+        n_same = 0
+        for x, y in zip(got, rb["idx"]):
+            if x != y:
+                break
+            n_same += 1
+        assert n_same >= sep, (b, got, list(rb["idx"]))
+    # merge: objective = explicit error of every prefix, picks greedy within the pool
+    pool = [int(x) for x in ib.ravel() if x >= 0]
+    assert set(int(x) for x in im) <= set(pool) and len(set(int(x) for x in im)) == km
+    for t in (1, km // 2, km):
+        assert rel(om[t], dense.error(host(A, m, im[:t]).T, B)) <= 1e-5
+    P = host(A, m, pool).T
+    for t in (0, km - 1):
+        sc = dense.scores(host(A, m, im[:t]).T if t else np.zeros((m, 0)), P, B)
+        sc[[pool.index(int(x)) for x in im[:t]]] = -np.inf
+        assert sc[pool.index(int(im[t]))] >= np.max(sc) * (1 - 1e-5)
+    del A, Om
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.timeout(600)
+def test_full_gcss_fp8_8192x262144_r512_k500(gpu):
+    import torch
+    w = synth.workload("gcss_fp8_8192x262144_r512_k500")
+    m, n, k, r = w["m"], w["n"], w["k"], w["r"]
+    A = synth.spectral_lowrank_torch(m, n, w["rank"], w["decay"], w["noise"], 0)
+    Om = synth.omega_gauss_torch(n, r, 1)
+    A8, sc8 = gpu.quantize_tensor(A, m, "fp8")
+    # every stored code and scale against the oracle's quantizer; the oracle's
+    # decoded values then give the target of the data the GPU selects on
+    B = np.zeros((m, r))
+    chunk = 16384
+    for i0 in range(0, n, chunk):
+        i1 = min(n, i0 + chunk)
+        codes, scl = oracle.quantize_fp8(A[i0:i1].cpu().numpy(), m, ldo=A8.shape[1])
+        assert np.array_equal(codes, A8[i0:i1].cpu().numpy()), i0
+        assert np.array_equal(scl, sc8[i0:i1].cpu().numpy()), i0
+        Ahat = oracle.decode_columns(codes, m, "fp8", scl)
+        B += dense.project(Ahat, m, Om[i0:i1].double().cpu().numpy(), chunk=chunk)
+    sel = gpu.Selector(A8, m, k_max=k, r_max=r, scales=sc8)
+    sel.project_target(Om)
+    idx, obj, ns, st = sel.select(k)
+    err = sel.reconstruction_error(idx)
+    common_checks(idx, obj, ns, k)
+
+    def ahat(cols):
+        cols = np.asarray(cols, dtype=np.int64)
+        codes, scl = oracle.quantize_fp8(A[cols].cpu().numpy(), m, ldo=A8.shape[1])
+        return oracle.decode_columns(codes, m, "fp8", scl).T
+
+    e8 = dense.error(ahat(idx), B)
+    assert rel(obj[k], e8) <= 1e-5 and rel(err, e8) <= 1e-5
+    rng = np.random.default_rng(2)
+    for t in (0, k // 2, k - 1):
+        prefix = idx[:t]
+        cand = [int(x) for x in rng.choice(n, 32, replace=False) if int(x) not in set(prefix)]
+        sc = dense.scores(ahat(prefix) if t else np.zeros((m, 0)), ahat(cand + [int(idx[t])]), B)
+        assert sc[-1] >= np.max(sc[:-1]) * (1 - 1e-5), t
+    del A, A8, Om
+    torch.cuda.empty_cache()

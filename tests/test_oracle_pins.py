@@ -292,3 +292,30 @@ def test_quantized_columns_decode_within_half_step():
     h = oracle.quantize_bf16(A32, m)
     dh = oracle.decode_columns(h, m, "bf16")
     assert np.all(np.abs(dh - A32[:, :m]) <= np.abs(A32[:, :m]) * 2.0 ** -8 * (1 + 1e-9))
+
+
+# --- the large-input definitions agree with the C oracle and brute force ----
+def test_dense_definitions_match_oracle():
+    from oracle import dense
+    m, n, r = 30, 80, 6
+    A = synth.gauss_lowrank_dense(m, n, 8, 0.1, seed=81)
+    Om = synth.omega_gauss(n, r, seed=82).astype(np.float64)
+    B = dense.project(cs(A), m, Om, chunk=17)
+    np.testing.assert_allclose(B, A @ Om, rtol=1e-12, atol=1e-12)
+    res = oracle.select(cs(A), m, 7, B=cs(B))
+    S = list(res["idx"])
+    for t in (0, 3, 7):
+        assert abs(dense.error(A[:, S[:t]], B) - oracle.error(cs(A), m, S[:t], B=cs(B))) <= 1e-10 * res["obj"][0]
+    # scores given a prefix equal the brute-force objective decrease
+    for t in (0, 4):
+        sc = dense.scores(A[:, S[:t]], A, B)
+        F = brute.objective(A, B, S[:t])
+        for i in range(0, n, 9):
+            if i in S[:t]:
+                continue
+            assert abs(sc[i] - (F - brute.objective(A, B, S[:t] + [i]))) <= 1e-9 * res["obj"][0]
+    # the picks maximise the criterion
+    for t in range(7):
+        sc = dense.scores(A[:, S[:t]], A, B)
+        sc[S[:t]] = -np.inf
+        assert int(np.argmax(sc)) == S[t]
