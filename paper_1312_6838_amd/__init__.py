@@ -44,11 +44,13 @@ class Selector:
     """One selection context over a column store A (n, lda) on the GPU.
 
     Holds references to every tensor the library borrows (A, scales, the
-    workspace, the target) so they outlive the context.
+    workspace, the target) so they outlive the context.  ``workspace`` may be
+    a caller-owned uint8 cuda tensor of at least the required size; by
+    default one is allocated.
     """
 
     def __init__(self, A, m, *, k_max, r_max=0, self_target=False, scales=None, tau=0.0,
-                 stream=None, batched=None):
+                 stream=None, batched=None, workspace=None):
         import torch
         if not A.is_cuda or A.dim() != 2 or not A.is_contiguous():
             raise ValueError("A must be a contiguous 2-D cuda tensor of shape (n, lda)")
@@ -64,7 +66,12 @@ class Selector:
         nbytes = workspace_size(self.desc)
         if batched is not None:
             nbytes += batched_workspace_size(self.desc, *batched)
-        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=A.device)
+        if workspace is None:
+            workspace = torch.empty(nbytes, dtype=torch.uint8, device=A.device)
+        elif (workspace.dtype != torch.uint8 or not workspace.is_cuda
+              or not workspace.is_contiguous() or workspace.numel() < nbytes):
+            raise ValueError(f"workspace must be a contiguous uint8 cuda tensor of >= {nbytes} bytes")
+        self.ws = workspace
         self.ws_bytes = nbytes
         self.h = create(self.desc, self.ws.data_ptr(), nbytes)
         self.B = None

@@ -581,8 +581,10 @@ gcss_status gcss_reconstruction_error(gcss_ctx *h, const int64_t *idx, int32_t k
   } else if (kb == 0) {
     HIPCHK(launch_sum_f64(h->F0(), 1, h->err_dev(), s));
   } else {
+    // ||A||^2 - sum_s ||A^T q_s||^2; the selection that built this basis
+    // already computed the terms exactly (quad), so only a fresh basis needs them
     double *quad = h->at<double>(h->L.quad);
-    HIPCHK(launch_qta(Q, ldq, kb, nullptr, h->A, (double *)scr, quad, s));
+    if (!reuse) HIPCHK(launch_qta(Q, ldq, kb, nullptr, h->A, (double *)scr, quad, s));
     HIPCHK(launch_gram_err(h->F0(), quad, kb, h->err_dev(), s));
   }
   HIPCHK(hipMemcpyAsync(err, h->err_dev(), sizeof(double), hipMemcpyDeviceToHost, s));
@@ -770,6 +772,11 @@ gcss_status gcss_select_batched(gcss_ctx *h, int32_t nblocks, const int64_t *col
     h->stream = h->cap_stream;
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeRelaxed);
+    // the stream kernel reads q and z up to the padded length: the padding
+    // (never written by the step kernels) must hold zeros, whatever the
+    // workspace held before
+    if (!e) e = launch_zero_f32((float *)(base + B.q32), (int64_t)nblocks * B.sQ32, h->cap_stream);
+    if (!e) e = launch_zero_f32((float *)(base + B.z32), (int64_t)nblocks * B.sQ32, h->cap_stream);
     if (!e) e = launch_batch_begin(h->at<double>(h->L.f0), h->at<double>(h->L.g0), h->at<uint8_t>(h->L.mask0),
                                    h->at<double>(h->L.f), h->at<double>(h->L.g), h->at<uint8_t>(h->L.mask), h->d.n,
                                    (DevState *)(base + B.st), nblocks, k_block, (int64_t *)(base + B.idx),

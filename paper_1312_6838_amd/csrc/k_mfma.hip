@@ -1,51 +1,86 @@
 // Dense contractions of the selection, on the CDNA matrix cores
 // (v_mfma_f32_16x16x4_f32, FP32 in / FP32 accumulate):
 //
-//   init scores (Algorithm 3, first line):   f_i = || X^T A_i ||^2,
-//       X = B (m x r), the epilogue sums the squares so the r x n product is
+//   init scores (Algorithm 3, first line):   f_i = || X A_i ||^2,
+//       X = B^T (r x m), the epilogue sums the squares so the r x n product is
 //       never stored; g_i = || A_i ||^2 is accumulated from the same A tiles.
 //   init scores, Gram target (B = A enters only through C = A A^T):
-//       f_i = A_i^T C A_i = || A^T A_i ||^2, epilogue dot with A_i.
+//       f_i = A_i^T C A_i = A_i^T T A_i with T = diag(C) + 2 strictly-upper(C),
+//       so only the tiles of C on or right of the diagonal are multiplied
+//       (half the flops); T is formed from C while its tiles are loaded.
 //   Gram matrix C = A A^T (symmetric rank-n update, upper tiles, split-K).
 //   Projection B = A Omega (Section 5.1), split-K with a fixed-order reduce.
 //
-// All tiles are staged in LDS in "k-major" layout (each row of the tile
-// holds 16 consecutive k values, pitch 20 floats).  A lane feeds the 16x16x4
-// instruction from one 16-byte LDS read per operand: lane l takes rows
-// l%16 and the k quad 4*(l/16)..+3, and the four instructions s = 0..3 use
-// element s of that quad, so the four lane groups cover all 16 k values.
-// Output layout of v_mfma_f32_16x16x4_f32: lane l, register v holds
-// D[4*(l/16) + v][l%16].
+// Two LDS layouts feed the 16x16x4 instruction (lane l supplies row l%16 and
+// k index l/16 of each operand; lane l, register v of the result holds
+// D[4*(l/16) + v][l%16]):
+//  * k-major (operands whose k index is contiguous in memory: rows of X,
+//    columns of A as the right operand): each tile row holds BKT consecutive
+//    k values (pitch BKT + 4).  A lane reads one 16-byte quad of k values per
+//    operand and feeds four instructions with its components, the four lane
+//    groups covering 16 consecutive k.
+//  * MN-major (operands whose row index is contiguous: A as the left operand
+//    of A A^T and A Omega, Omega itself): each LDS row holds one k value and
+//    128 tile rows (pitch 132), written with 16-byte stores.  Tile row
+//    4*rho + b is row rho of the b-th 16-row instruction block, so one 16-byte
+//    read gives a lane its operand for four blocks at one k.
+#include <cstdlib>
+
 #include "gcss_device.h"
 
 namespace gcss {
 
-constexpr int BK = 16;   // k values per LDS stage
-constexpr int PIT = 20;  // LDS row pitch in floats
+constexpr int BK = 16;   // k values per stage of the FP64 kernel
+constexpr int MP = 132;  // MN-major LDS pitch in floats (128 rows + pad)
 
 __device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// acc[rb][nb] += X_rows(rb) * Y_cols(nb) over one BK stage.
-template <int RB, int NB>
-__device__ __forceinline__ void mma_stage(const float *Xs, int xrow0, const float *Ys, int ycol0,
-                                          int lane, f32x4 (&acc)[RB][NB]) {
-  const int r = lane & 15, kq = (lane >> 4) * 4;
-  float4 xa[RB], yb[NB];
+// k-major: acc[rb][nb] += X_rows(rb) * Y_cols(nb) over one stage of BKT k values.
+template <int RB, int NB, int BKT>
+__device__ __forceinline__ void mma_stage_k(const float *Xs, int xrow0, const float *Ys,
+                                            int ycol0, int lane, f32x4 (&acc)[RB][NB]) {
+  constexpr int KP = BKT + 4;
+  const int r = lane & 15, g = lane >> 4;
 #pragma unroll
-  for (int rb = 0; rb < RB; ++rb) xa[rb] = *(const float4 *)(Xs + (xrow0 + 16 * rb + r) * PIT + kq);
+  for (int kk = 0; kk < BKT / 16; ++kk) {
+    const int kq = 16 * kk + 4 * g;
+    float4 xa[RB], yb[NB];
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb) yb[nb] = *(const float4 *)(Ys + (ycol0 + 16 * nb + r) * PIT + kq);
+    for (int rb = 0; rb < RB; ++rb) xa[rb] = *(const float4 *)(Xs + (xrow0 + 16 * rb + r) * KP + kq);
 #pragma unroll
-  for (int rb = 0; rb < RB; ++rb)
+    for (int nb = 0; nb < NB; ++nb) yb[nb] = *(const float4 *)(Ys + (ycol0 + 16 * nb + r) * KP + kq);
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      acc[rb][nb] = mfma4(xa[rb].x, yb[nb].x, acc[rb][nb]);
-      acc[rb][nb] = mfma4(xa[rb].y, yb[nb].y, acc[rb][nb]);
-      acc[rb][nb] = mfma4(xa[rb].z, yb[nb].z, acc[rb][nb]);
-      acc[rb][nb] = mfma4(xa[rb].w, yb[nb].w, acc[rb][nb]);
-    }
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        acc[rb][nb] = mfma4(xa[rb].x, yb[nb].x, acc[rb][nb]);
+        acc[rb][nb] = mfma4(xa[rb].y, yb[nb].y, acc[rb][nb]);
+        acc[rb][nb] = mfma4(xa[rb].z, yb[nb].z, acc[rb][nb]);
+        acc[rb][nb] = mfma4(xa[rb].w, yb[nb].w, acc[rb][nb]);
+      }
+  }
+}
+
+// MN-major: a wave's 64 x 64 block at tile rows xr0.., columns yc0..;
+// acc[rb][nb] row rho <-> tile row xr0 + 4*rho + rb, column c <-> yc0 + 4*c + nb.
+template <int BKT>
+__device__ __forceinline__ void mma_stage_mn(const float *Xs, int xr0, const float *Ys, int yc0,
+                                             int lane, f32x4 (&acc)[4][4]) {
+  const int r = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int s = 0; s < BKT / 4; ++s) {
+    const int k = 4 * s + g;
+    const float4 x = *(const float4 *)(Xs + k * MP + xr0 + 4 * r);
+    const float4 y = *(const float4 *)(Ys + k * MP + yc0 + 4 * r);
+    const float xv[4] = {x.x, x.y, x.z, x.w};
+    const float yv[4] = {y.x, y.y, y.z, y.w};
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) acc[rb][nb] = mfma4(xv[rb], yv[nb], acc[rb][nb]);
+  }
 }
 
 template <int DT>
@@ -104,17 +139,24 @@ __device__ __forceinline__ float4 load4(const void *base, int64_t off) {
 // ---------------------------------------------------------------------------
 // Initial scores.  Workgroup: 4 waves stacked along the rows of X (R), one
 // tile of NT = 16*NB columns of A.  Rows are processed in chunks of
-// RT = 64*RB; the column results are accumulated across chunks.
-template <int DT, int RB, int NB, bool GRAM>
+// RT = 64*RB; the column results are accumulated across chunks.  With TRI,
+// X = C is weighted as T/2 (zero left of the diagonal, so the k loop starts
+// at r0; one half on it) and the sum is doubled.
+template <int DT, int RB, int NB, int BKT, bool TRI>
 __global__ __launch_bounds__(256) void k_init(const float *__restrict__ X, int64_t ldx,
                                               int64_t R, AView A, double *__restrict__ f0,
                                               double *__restrict__ g0,
                                               uint8_t *__restrict__ mask0) {
-  constexpr int RT = 64 * RB, NT = 16 * NB;
+  constexpr int RT = 64 * RB, NT = 16 * NB, KP = BKT + 4;
   constexpr int ES = EInfo<DT>::esize, EPC = EInfo<DT>::epc;
-  constexpr int CPC = ES;  // 16-byte chunks per column per stage (16 k values)
-  __shared__ __align__(16) float Xs[RT * PIT];
-  __shared__ __align__(16) float Ys[NT * PIT];
+  constexpr int XQ = BKT / 4;              // float4 per X row per stage
+  constexpr int XPT = RT * XQ / 256;       // X float4 per thread per stage
+  constexpr int YCC = BKT * ES / 16;       // 16-byte chunks per A column per stage
+  constexpr int YCH = NT * YCC;            // A chunks per stage
+  constexpr int YPT = (YCH + 255) / 256;   // A chunks per thread per stage
+  static_assert(RT % BKT == 0 && YCC >= 1 && YCC <= 16, "tile shape");
+  __shared__ __align__(16) float Xs[RT * KP];
+  __shared__ __align__(16) float Ys[NT * KP];
   __shared__ double red[4][NT];
   __shared__ double gs[NT];
 
@@ -124,18 +166,15 @@ __global__ __launch_bounds__(256) void k_init(const float *__restrict__ X, int64
   const char *abase = (const char *)A.a;
   const int64_t colb = A.lda * ES;
 
-  // Y loader: thread -> (column, chunk)
-  const int ycol = tid / CPC, ych = tid % CPC;
-  const bool yact = tid < NT * CPC;
-  const bool ycolv = yact && (j0 + ycol) < n;
-  double gacc = 0.0;
-
+  double gacc[YPT];
+#pragma unroll
+  for (int u = 0; u < YPT; ++u) gacc[u] = 0.0;
   double colacc[NB];
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) colacc[nb] = 0.0;
 
   const int64_t nchunks = (R + RT - 1) / RT;
-  const int64_t ksteps = (m + BK - 1) / BK;
+  const int64_t ksteps = (m + BKT - 1) / BKT;
   for (int64_t rc = 0; rc < nchunks; ++rc) {
     const int64_t r0 = rc * RT;
     f32x4 acc[RB][NB];
@@ -144,88 +183,115 @@ __global__ __launch_bounds__(256) void k_init(const float *__restrict__ X, int64
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) acc[rb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    float4 xr[RB];
-    uint4 yr = make_uint4(0u, 0u, 0u, 0u);
+    float4 xr[XPT];
+    uint4 yr[YPT];
+    // X loads are unconditional 16-byte loads from clamped (valid) addresses;
+    // only the uniform tail and diagonal stages apply masks
+    const bool rtail = r0 + RT > R;
     auto gload = [&](int64_t k0) {
+      const bool ktail = k0 + BKT > m;
+      const bool diag = TRI && k0 < r0 + RT;
 #pragma unroll
-      for (int u = 0; u < RB; ++u) {
+      for (int u = 0; u < XPT; ++u) {
         const int q = tid + 256 * u;
-        const int row = q >> 2, kq = (q & 3) * 4;
+        const int row = q / XQ, kq = (q % XQ) * 4;
         const int64_t gr = r0 + row, gk = k0 + kq;
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (gr < R && gk < m) {
-          v = *(const float4 *)(X + gr * ldx + gk);
-          if (gk + 4 > m) {
-            if (gk + 1 >= m) v.y = 0.f;
-            if (gk + 2 >= m) v.z = 0.f;
-            if (gk + 3 >= m) v.w = 0.f;
-          }
+        const int64_t grc = gr < R ? gr : R - 1, gkc = gk < m ? gk : 0;
+        float4 v = *(const float4 *)(X + grc * ldx + gkc);
+        if (rtail || ktail) {
+          const bool rok = gr < R;
+          v.x = (rok && gk < m) ? v.x : 0.f;
+          v.y = (rok && gk + 1 < m) ? v.y : 0.f;
+          v.z = (rok && gk + 2 < m) ? v.z : 0.f;
+          v.w = (rok && gk + 3 < m) ? v.w : 0.f;
+        }
+        if (diag) {
+          // rows of T/2: weight 1 right of the diagonal, 1/2 on it, 0 left of it
+          const int d = (int)(gk - gr);
+          v.x *= d > 0 ? 1.f : (d == 0 ? 0.5f : 0.f);
+          v.y *= d + 1 > 0 ? 1.f : (d + 1 == 0 ? 0.5f : 0.f);
+          v.z *= d + 2 > 0 ? 1.f : (d + 2 == 0 ? 0.5f : 0.f);
+          v.w *= d + 3 > 0 ? 1.f : (d + 3 == 0 ? 0.5f : 0.f);
         }
         xr[u] = v;
       }
-      const int64_t gk = k0 + ych * EPC;
-      if (ycolv && gk < m)
-        yr = *(const uint4 *)(abase + (j0 + ycol) * colb + gk * ES);
-      else
-        yr = make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+      for (int u = 0; u < YPT; ++u) {
+        const int q = tid + 256 * u;
+        const int col = q / YCC, ch = q % YCC;
+        const int64_t gk = k0 + ch * EPC;
+        if (q < YCH && j0 + col < n && gk < m)
+          yr[u] = *(const uint4 *)(abase + (j0 + col) * colb + gk * ES);
+        else
+          yr[u] = make_uint4(0u, 0u, 0u, 0u);
+      }
     };
     auto sstore = [&](int64_t k0) {
 #pragma unroll
-      for (int u = 0; u < RB; ++u) {
+      for (int u = 0; u < XPT; ++u) {
         const int q = tid + 256 * u;
-        const int row = q >> 2, kq = (q & 3) * 4;
-        *(float4 *)(Xs + row * PIT + kq) = xr[u];
+        const int row = q / XQ, kq = (q % XQ) * 4;
+        *(float4 *)(Xs + row * KP + kq) = xr[u];
       }
-      if (yact) {
+#pragma unroll
+      for (int u = 0; u < YPT; ++u) {
+        const int q = tid + 256 * u;
+        if (q >= YCH) continue;
+        const int col = q / YCC, ch = q % YCC;
         float v[EPC];
-        decode16<DT>(yr, v);
-        const int64_t gk = k0 + ych * EPC;
+        decode16<DT>(yr[u], v);
+        const int64_t gk = k0 + ch * EPC;
 #pragma unroll
         for (int e = 0; e < EPC; ++e)
           if (gk + e >= m) v[e] = 0.f;
         if (rc == 0) {
 #pragma unroll
-          for (int e = 0; e < EPC; ++e) gacc = fma((double)v[e], (double)v[e], gacc);
+          for (int e = 0; e < EPC; ++e) gacc[u] = fma((double)v[e], (double)v[e], gacc[u]);
         }
 #pragma unroll
         for (int e = 0; e < EPC; e += 4)
-          *(float4 *)(Ys + ycol * PIT + ych * EPC + e) = make_float4(v[e], v[e + 1], v[e + 2], v[e + 3]);
+          *(float4 *)(Ys + col * KP + ch * EPC + e) = make_float4(v[e], v[e + 1], v[e + 2], v[e + 3]);
       }
     };
 
-    gload(0);
-    for (int64_t ks = 0; ks < ksteps; ++ks) {
+    const int64_t ks0 = TRI ? r0 / BKT : 0;
+    gload(ks0 * BKT);
+    for (int64_t ks = ks0; ks < ksteps; ++ks) {
       __syncthreads();
-      sstore(ks * BK);
+      sstore(ks * BKT);
       __syncthreads();
-      if (ks + 1 < ksteps) gload((ks + 1) * BK);
-      mma_stage<RB, NB>(Xs, wave * 16 * RB, Ys, 0, lane, acc);
+      if (ks + 1 < ksteps) gload((ks + 1) * BKT);
+      mma_stage_k<RB, NB, BKT>(Xs, wave * 16 * RB, Ys, 0, lane, acc);
     }
 
-    // epilogue of this row chunk
+    // epilogue of this row chunk, one 16-row block at a time (bounded registers)
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      const int64_t j = j0 + 16 * nb + (lane & 15);
-      double s = 0.0;
+    for (int rb = 0; rb < RB; ++rb) {
+      const int64_t i = r0 + wave * 16 * RB + 16 * rb + 4 * (lane >> 4);
+      if constexpr (TRI) {
+        // branch-free: clamped (always valid) addresses, masked values
+        const int64_t ic = i < m ? i : 0;
+        const float w0 = i < m ? 1.f : 0.f, w1 = i + 1 < m ? 1.f : 0.f;
+        const float w2 = i + 2 < m ? 1.f : 0.f, w3 = i + 3 < m ? 1.f : 0.f;
 #pragma unroll
-      for (int rb = 0; rb < RB; ++rb) {
-        const int64_t i = r0 + wave * 16 * RB + 16 * rb + 4 * (lane >> 4);
-        if constexpr (GRAM) {
-          float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
-          if (j < n && i < m) {
-            a = load4<DT>(A.a, j * A.lda + i);
-            if (i + 1 >= m) a.y = 0.f;
-            if (i + 2 >= m) a.z = 0.f;
-            if (i + 3 >= m) a.w = 0.f;
-          }
-          s += (double)acc[rb][nb][0] * a.x + (double)acc[rb][nb][1] * a.y +
-               (double)acc[rb][nb][2] * a.z + (double)acc[rb][nb][3] * a.w;
-        } else {
+        for (int nb = 0; nb < NB; ++nb) {
+          const int64_t j = j0 + 16 * nb + (lane & 15);
+          const float wj = j < n ? 1.f : 0.f;
+          const float4 a = load4<DT>(A.a, (j < n ? j : 0) * A.lda + ic);
+          const float p = acc[rb][nb][0] * (a.x * w0) + acc[rb][nb][1] * (a.y * w1) +
+                          acc[rb][nb][2] * (a.z * w2) + acc[rb][nb][3] * (a.w * w3);
+          colacc[nb] += (double)(p * wj);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      } else {
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          double s = 0.0;
 #pragma unroll
           for (int v = 0; v < 4; ++v) s += (double)acc[rb][nb][v] * (double)acc[rb][nb][v];
+          colacc[nb] += s;
         }
       }
-      colacc[nb] += s;
     }
   }
 
@@ -237,18 +303,24 @@ __global__ __launch_bounds__(256) void k_init(const float *__restrict__ X, int64
     s += __shfl_xor(s, 32, 64);
     if (lane < 16) red[wave][16 * nb + lane] = s;
   }
-  // g: sum over the CPC threads of a column
-  double gsum = gacc;
-  if constexpr (CPC >= 2) gsum += __shfl_xor(gsum, 1, 64);
-  if constexpr (CPC >= 4) gsum += __shfl_xor(gsum, 2, 64);
-  if (yact && ych == 0) gs[ycol] = gsum;
+  // g: sum over the YCC threads of a column
+#pragma unroll
+  for (int u = 0; u < YPT; ++u) {
+    const int q = tid + 256 * u;
+    double gsum = gacc[u];
+    if constexpr (YCC >= 2) gsum += __shfl_xor(gsum, 1, 64);
+    if constexpr (YCC >= 4) gsum += __shfl_xor(gsum, 2, 64);
+    if constexpr (YCC >= 8) gsum += __shfl_xor(gsum, 4, 64);
+    if constexpr (YCC >= 16) gsum += __shfl_xor(gsum, 8, 64);
+    if (q < YCH && q % YCC == 0) gs[q / YCC] = gsum;
+  }
   __syncthreads();
   if (tid < NT) {
     const int64_t j = j0 + tid;
     if (j < n) {
       const double fv = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
       const double sc = col_scale(A, j);
-      const double f = sc * sc * fv, g = sc * sc * gs[tid];
+      const double f = (TRI ? 2.0 : 1.0) * sc * sc * fv, g = sc * sc * gs[tid];
       f0[j] = f;
       g0[j] = g;
       mask0[j] = (g > 0.0 && isfinite(g) && isfinite(f)) ? 0 : 2;
@@ -257,55 +329,81 @@ __global__ __launch_bounds__(256) void k_init(const float *__restrict__ X, int64
 }
 
 // ---------------------------------------------------------------------------
-// 128 x 128 output tiles, 4 waves in a 2 x 2 arrangement of 64 x 64.
-// X[k][i] = A[i, k]: for each k (a column of A) the tile's rows are
-// consecutive in memory; they are decoded, scaled by the column scale and
-// written transposed into the k-major LDS tile.
-template <int DT>
-__device__ __forceinline__ void load_at_tile(const AView &A, int64_t i0, int64_t k0,
-                                             int64_t kend, int tid, uint4 (&raw)[2],
-                                             int (&kk)[2], int (&ii)[2], bool (&ok)[2]) {
-  constexpr int ES = EInfo<DT>::esize, EPC = EInfo<DT>::epc;
-  constexpr int CPK = 128 / EPC;  // chunks per k (128 rows)
-  const char *abase = (const char *)A.a;
-#pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int q = tid + 256 * u;
-    kk[u] = q / CPK;
-    ii[u] = (q % CPK) * EPC;
-    ok[u] = q < 16 * CPK && (k0 + kk[u]) < kend && (i0 + ii[u]) < A.m;
-    raw[u] = ok[u] ? *(const uint4 *)(abase + ((k0 + kk[u]) * A.lda + i0 + ii[u]) * ES)
-                   : make_uint4(0u, 0u, 0u, 0u);
-  }
-}
+// MN-major operand from A: rows i0..i0+127 of columns k0..k0+BKT-1 (decoded,
+// FP8 columns scaled), staged through registers into Ts[k * MP + i].
+template <int DT, int BKT>
+struct MnTileA {
+  static constexpr int EPC = EInfo<DT>::epc, ES = EInfo<DT>::esize;
+  static constexpr int CPK = 128 / EPC;        // 16-byte chunks per k
+  static constexpr int CH = BKT * CPK;         // chunks per stage
+  static constexpr int PT = (CH + 255) / 256;  // chunks per thread
+  uint4 raw[PT];
+  float sc[PT];
 
-template <int DT>
-__device__ __forceinline__ void store_at_tile(const AView &A, float *Ts, int64_t i0, int64_t k0,
-                                              int tid, const uint4 (&raw)[2], const int (&kk)[2],
-                                              const int (&ii)[2], const bool (&ok)[2]) {
-  constexpr int EPC = EInfo<DT>::epc;
-  constexpr int CPK = 128 / EPC;
+  __device__ __forceinline__ void load(const AView &A, int64_t i0, int64_t k0, int64_t kend,
+                                       int tid) {
+    const char *abase = (const char *)A.a;
 #pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int q = tid + 256 * u;
-    if (q >= 16 * CPK) continue;
-    float v[EPC];
-    decode16<DT>(raw[u], v);
-    float sc = 1.f;
-    if constexpr (DT == DT_FP8) sc = ok[u] ? A.scale[k0 + kk[u]] : 0.f;
+    for (int u = 0; u < PT; ++u) {
+      const int q = tid + 256 * u;
+      const int kk = q / CPK, ii = (q % CPK) * EPC;
+      const bool ok = q < CH && (k0 + kk) < kend && (i0 + ii) < A.m;
+      raw[u] = ok ? *(const uint4 *)(abase + ((k0 + kk) * A.lda + i0 + ii) * ES)
+                  : make_uint4(0u, 0u, 0u, 0u);
+      if constexpr (DT == DT_FP8) sc[u] = ok ? A.scale[k0 + kk] : 0.f;
+    }
+  }
+  __device__ __forceinline__ void store(float *Ts, const AView &A, int64_t i0, int tid) const {
 #pragma unroll
-    for (int e = 0; e < EPC; ++e) {
-      const bool in = ok[u] && (i0 + ii[u] + e) < A.m;
-      Ts[(ii[u] + e) * PIT + kk[u]] = in ? v[e] * sc : 0.f;
+    for (int u = 0; u < PT; ++u) {
+      const int q = tid + 256 * u;
+      if (q >= CH) continue;
+      const int kk = q / CPK, ii = (q % CPK) * EPC;
+      float v[EPC];
+      decode16<DT>(raw[u], v);
+#pragma unroll
+      for (int e = 0; e < EPC; ++e) {
+        if constexpr (DT == DT_FP8) v[e] *= sc[u];
+        if (i0 + ii + e >= A.m) v[e] = 0.f;
+      }
+#pragma unroll
+      for (int e = 0; e < EPC; e += 4)
+        *(float4 *)(Ts + kk * MP + ii + e) = make_float4(v[e], v[e + 1], v[e + 2], v[e + 3]);
+    }
+  }
+};
+
+// Store a wave's 64 x 64 MN-major accumulator block: rows i0.. (contiguous in
+// P), columns j0.. (stride ldp), rows < mrow and columns < ncol.
+__device__ __forceinline__ void store_block_mn(float *P, int64_t ldp, int64_t i0, int64_t j0,
+                                               int64_t mrow, int64_t ncol, int lane,
+                                               const f32x4 (&acc)[4][4]) {
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) {
+    const int64_t j = j0 + 4 * (lane & 15) + nb;
+    if (j >= ncol) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t i = i0 + 16 * (lane >> 4) + 4 * v;
+      const float4 val = make_float4(acc[0][nb][v], acc[1][nb][v], acc[2][nb][v], acc[3][nb][v]);
+      float *dst = P + j * ldp + i;
+      if (i + 3 < mrow) {
+        *(float4 *)dst = val;
+      } else {
+        if (i < mrow) dst[0] = val.x;
+        if (i + 1 < mrow) dst[1] = val.y;
+        if (i + 2 < mrow) dst[2] = val.z;
+      }
     }
   }
 }
 
-template <int DT>
+// 128 x 128 upper tiles of C = A A^T, 4 waves in a 2 x 2 arrangement of 64 x 64.
+template <int DT, int BKT>
 __global__ __launch_bounds__(256) void k_gram(AView A, float *__restrict__ P, int64_t ldp,
                                               int ntile, int64_t kchunk) {
-  __shared__ __align__(16) float Xs[128 * PIT];
-  __shared__ __align__(16) float Ys[128 * PIT];
+  __shared__ __align__(16) float Xs[BKT * MP];
+  __shared__ __align__(16) float Ys[BKT * MP];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t m = A.m, n = A.n;
   // tile id -> (bi, bj), bi <= bj
@@ -324,34 +422,24 @@ __global__ __launch_bounds__(256) void k_gram(AView A, float *__restrict__ P, in
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  uint4 xr[2], yr[2];
-  int xk[2], xi[2], yk[2], yi[2];
-  bool xo[2], yo[2];
+  MnTileA<DT, BKT> xt, yt;
   const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
-  if (kb < ke) load_at_tile<DT>(A, i0, kb, ke, tid, xr, xk, xi, xo);
-  if (kb < ke) load_at_tile<DT>(A, j0, kb, ke, tid, yr, yk, yi, yo);
-  for (int64_t k0 = kb; k0 < ke; k0 += BK) {
-    __syncthreads();
-    store_at_tile<DT>(A, Xs, i0, k0, tid, xr, xk, xi, xo);
-    store_at_tile<DT>(A, Ys, j0, k0, tid, yr, yk, yi, yo);
-    __syncthreads();
-    if (k0 + BK < ke) {
-      load_at_tile<DT>(A, i0, k0 + BK, ke, tid, xr, xk, xi, xo);
-      load_at_tile<DT>(A, j0, k0 + BK, ke, tid, yr, yk, yi, yo);
-    }
-    mma_stage<4, 4>(Xs, wr, Ys, wc, lane, acc);
+  if (kb < ke) {
+    xt.load(A, i0, kb, ke, tid);
+    yt.load(A, j0, kb, ke, tid);
   }
-#pragma unroll
-  for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-    for (int nb = 0; nb < 4; ++nb) {
-      const int64_t i = i0 + wr + 16 * rb + 4 * (lane >> 4);
-      const int64_t j = j0 + wc + 16 * nb + (lane & 15);
-      if (j < m)
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-          if (i + v < m) Pout[j * ldp + i + v] = acc[rb][nb][v];
+  for (int64_t k0 = kb; k0 < ke; k0 += BKT) {
+    __syncthreads();
+    xt.store(Xs, A, i0, tid);
+    yt.store(Ys, A, j0, tid);
+    __syncthreads();
+    if (k0 + BKT < ke) {
+      xt.load(A, i0, k0 + BKT, ke, tid);
+      yt.load(A, j0, k0 + BKT, ke, tid);
     }
+    mma_stage_mn<BKT>(Xs, wr, Ys, wc, lane, acc);
+  }
+  store_block_mn(Pout, ldp, i0 + wr, j0 + wc, m, m, lane, acc);
 }
 
 // C[i,j] = sum_s P_s[min, max] (upper tiles only were computed; exact symmetry)
@@ -366,13 +454,15 @@ __global__ void k_gram_reduce(const float *__restrict__ P, int64_t ldp, int64_t 
   C[j * ldc + i] = s;
 }
 
-// B = A Omega: X[k][i] = A[i, k], Y[k][j] = Omega[k, j] (row-major n x r).
-template <int DT>
+// B = A Omega: left operand A (MN-major), right operand Omega[k][j]
+// (row-major n x r, MN-major as stored).
+template <int DT, int BKT>
 __global__ __launch_bounds__(256) void k_project(AView A, const float *__restrict__ Om,
                                                  int64_t r, float *__restrict__ P, int64_t ldp,
                                                  int ntm, int ntn, int64_t kchunk) {
-  __shared__ __align__(16) float Xs[128 * PIT];
-  __shared__ __align__(16) float Ys[128 * PIT];
+  constexpr int YPT = BKT * 32 / 256;  // Omega float4 per thread per stage
+  __shared__ __align__(16) float Xs[BKT * MP];
+  __shared__ __align__(16) float Ys[BKT * MP];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t n = A.n;
   const int ntile = ntm * ntn;
@@ -389,13 +479,11 @@ __global__ __launch_bounds__(256) void k_project(AView A, const float *__restric
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  uint4 xr[2];
-  int xk[2], xi[2];
-  bool xo[2];
-  float4 yv[2];
+  MnTileA<DT, BKT> xt;
+  float4 yv[YPT];
   auto yload = [&](int64_t k0) {
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
+    for (int u = 0; u < YPT; ++u) {
       const int q = tid + 256 * u;
       const int kk = q >> 5, jj = (q & 31) * 4;
       const int64_t gk = k0 + kk, gj = j0 + jj;
@@ -416,42 +504,29 @@ __global__ __launch_bounds__(256) void k_project(AView A, const float *__restric
   };
   auto ystore = [&]() {
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
+    for (int u = 0; u < YPT; ++u) {
       const int q = tid + 256 * u;
       const int kk = q >> 5, jj = (q & 31) * 4;
-      Ys[(jj + 0) * PIT + kk] = yv[u].x;
-      Ys[(jj + 1) * PIT + kk] = yv[u].y;
-      Ys[(jj + 2) * PIT + kk] = yv[u].z;
-      Ys[(jj + 3) * PIT + kk] = yv[u].w;
+      *(float4 *)(Ys + kk * MP + jj) = yv[u];
     }
   };
   const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
   if (kb < ke) {
-    load_at_tile<DT>(A, i0, kb, ke, tid, xr, xk, xi, xo);
+    xt.load(A, i0, kb, ke, tid);
     yload(kb);
   }
-  for (int64_t k0 = kb; k0 < ke; k0 += BK) {
+  for (int64_t k0 = kb; k0 < ke; k0 += BKT) {
     __syncthreads();
-    store_at_tile<DT>(A, Xs, i0, k0, tid, xr, xk, xi, xo);
+    xt.store(Xs, A, i0, tid);
     ystore();
     __syncthreads();
-    if (k0 + BK < ke) {
-      load_at_tile<DT>(A, i0, k0 + BK, ke, tid, xr, xk, xi, xo);
-      yload(k0 + BK);
+    if (k0 + BKT < ke) {
+      xt.load(A, i0, k0 + BKT, ke, tid);
+      yload(k0 + BKT);
     }
-    mma_stage<4, 4>(Xs, wr, Ys, wc, lane, acc);
+    mma_stage_mn<BKT>(Xs, wr, Ys, wc, lane, acc);
   }
-#pragma unroll
-  for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-    for (int nb = 0; nb < 4; ++nb) {
-      const int64_t i = i0 + wr + 16 * rb + 4 * (lane >> 4);
-      const int64_t j = j0 + wc + 16 * nb + (lane & 15);
-      if (j < r)
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-          if (i + v < A.m) Pout[j * ldp + i + v] = acc[rb][nb][v];
-    }
+  store_block_mn(Pout, ldp, i0 + wr, j0 + wc, A.m, r, lane, acc);
 }
 
 __global__ void k_proj_reduce(const float *__restrict__ P, int64_t ldp, int64_t m, int64_t r,
@@ -657,24 +732,42 @@ hipError_t launch_obj_from_quad(const double *F0, const double *quad, const DevS
 }
 
 // ---------------------------------------------------------------------------
-template <int DT, int RB, bool GRAM>
+// k values per LDS stage of the FP32 contractions: 32 by default; the
+// environment variable GCSS_MFMA_BK=16 selects the shallower stage.
+static int mfma_bk() {
+  static const int bk = [] {
+    const char *e = std::getenv("GCSS_MFMA_BK");
+    return (e && std::atoi(e) == 16) ? 16 : 32;
+  }();
+  return bk;
+}
+constexpr int KC_ALIGN = 32;  // split-K chunks are multiples of every stage depth
+
+template <int DT, int RB, int BKT, bool TRI>
 static hipError_t init_t(const float *X, int64_t ldx, int64_t R, const AView &A, double *f0,
                          double *g0, uint8_t *mask0, hipStream_t s) {
   constexpr int NB = 4;
   const unsigned grid = (unsigned)((A.n + 16 * NB - 1) / (16 * NB));
-  hipLaunchKernelGGL((k_init<DT, RB, NB, GRAM>), dim3(grid), dim3(256), 0, s, X, ldx, R, A, f0,
-                     g0, mask0);
+  hipLaunchKernelGGL((k_init<DT, RB, NB, BKT, TRI>), dim3(grid), dim3(256), 0, s, X, ldx, R, A,
+                     f0, g0, mask0);
   return hipGetLastError();
+}
+
+template <int DT, int BKT>
+static hipError_t init_bk(const float *X, int64_t ldx, int64_t R, const AView &A, double *f0,
+                          double *g0, uint8_t *mask0, bool gram, hipStream_t s) {
+  if (gram) return init_t<DT, 4, BKT, true>(X, ldx, R, A, f0, g0, mask0, s);
+  if (R <= 64) return init_t<DT, 1, BKT, false>(X, ldx, R, A, f0, g0, mask0, s);
+  if (R <= 128) return init_t<DT, 2, BKT, false>(X, ldx, R, A, f0, g0, mask0, s);
+  if (R <= 256) return init_t<DT, 4, BKT, false>(X, ldx, R, A, f0, g0, mask0, s);
+  return init_t<DT, 8, BKT, false>(X, ldx, R, A, f0, g0, mask0, s);
 }
 
 template <int DT>
 static hipError_t init_dt(const float *X, int64_t ldx, int64_t R, const AView &A, double *f0,
                           double *g0, uint8_t *mask0, bool gram, hipStream_t s) {
-  if (gram) return init_t<DT, 4, true>(X, ldx, R, A, f0, g0, mask0, s);
-  if (R <= 64) return init_t<DT, 1, false>(X, ldx, R, A, f0, g0, mask0, s);
-  if (R <= 128) return init_t<DT, 2, false>(X, ldx, R, A, f0, g0, mask0, s);
-  if (R <= 256) return init_t<DT, 4, false>(X, ldx, R, A, f0, g0, mask0, s);
-  return init_t<DT, 8, false>(X, ldx, R, A, f0, g0, mask0, s);
+  if (mfma_bk() == 16) return init_bk<DT, 16>(X, ldx, R, A, f0, g0, mask0, gram, s);
+  return init_bk<DT, 32>(X, ldx, R, A, f0, g0, mask0, gram, s);
 }
 
 hipError_t launch_init_factor(const float *X, int64_t ldx, int64_t R, const AView &A,
@@ -705,7 +798,7 @@ static void gram_plan(int64_t m, int64_t n, int num_cu, int *ntile, int *nsplit,
   if (sp > 8) sp = 8;
   if (sp < 1) sp = 1;
   int64_t kc = (n + sp - 1) / sp;
-  kc = ((kc + BK - 1) / BK) * BK;
+  kc = ((kc + KC_ALIGN - 1) / KC_ALIGN) * KC_ALIGN;
   sp = (n + kc - 1) / kc;
   *ntile = (int)T;
   *nsplit = (int)sp;
@@ -729,10 +822,18 @@ hipError_t launch_gram(const AView &A, float *C, int64_t ldc, void *scratch, int
   const int64_t ldp = ((A.m + 3) / 4) * 4;
   float *P = (float *)scratch;
   const dim3 grid((unsigned)(nt * sp));
+  const bool bk16 = mfma_bk() == 16;
   switch (A.dtype) {
-    case DT_F32: hipLaunchKernelGGL(k_gram<DT_F32>, grid, dim3(256), 0, s, A, P, ldp, nt, kc); break;
-    case DT_BF16: hipLaunchKernelGGL(k_gram<DT_BF16>, grid, dim3(256), 0, s, A, P, ldp, nt, kc); break;
-    case DT_FP8: hipLaunchKernelGGL(k_gram<DT_FP8>, grid, dim3(256), 0, s, A, P, ldp, nt, kc); break;
+#define GCSS_GRAM(DTV)                                                                        \
+  if (bk16)                                                                                   \
+    hipLaunchKernelGGL((k_gram<DTV, 16>), grid, dim3(256), 0, s, A, P, ldp, nt, kc);          \
+  else                                                                                        \
+    hipLaunchKernelGGL((k_gram<DTV, 32>), grid, dim3(256), 0, s, A, P, ldp, nt, kc);          \
+  break;
+    case DT_F32: GCSS_GRAM(DT_F32)
+    case DT_BF16: GCSS_GRAM(DT_BF16)
+    case DT_FP8: GCSS_GRAM(DT_FP8)
+#undef GCSS_GRAM
     default: return hipErrorInvalidValue;
   }
   hipError_t e = hipGetLastError();
@@ -757,7 +858,7 @@ static void proj_plan(int64_t m, int64_t n, int64_t r, int num_cu, int *ntm, int
   if (sp > (n + 255) / 256) sp = (n + 255) / 256;
   if (sp < 1) sp = 1;
   int64_t kc = (n + sp - 1) / sp;
-  kc = ((kc + BK - 1) / BK) * BK;
+  kc = ((kc + KC_ALIGN - 1) / KC_ALIGN) * KC_ALIGN;
   sp = (n + kc - 1) / kc;
   *ntm = (int)tm;
   *ntn = (int)tn;
@@ -781,16 +882,20 @@ hipError_t launch_project(const AView &A, const float *omega, int64_t r, float *
   const int64_t ldp = ((A.m + 3) / 4) * 4;
   float *P = (float *)scratch;
   const dim3 grid((unsigned)(tm * tn * sp));
+  const bool bk16 = mfma_bk() == 16;
   switch (A.dtype) {
-    case DT_F32:
-      hipLaunchKernelGGL(k_project<DT_F32>, grid, dim3(256), 0, s, A, omega, r, P, ldp, tm, tn, kc);
-      break;
-    case DT_BF16:
-      hipLaunchKernelGGL(k_project<DT_BF16>, grid, dim3(256), 0, s, A, omega, r, P, ldp, tm, tn, kc);
-      break;
-    case DT_FP8:
-      hipLaunchKernelGGL(k_project<DT_FP8>, grid, dim3(256), 0, s, A, omega, r, P, ldp, tm, tn, kc);
-      break;
+#define GCSS_PROJ(DTV)                                                                        \
+  if (bk16)                                                                                   \
+    hipLaunchKernelGGL((k_project<DTV, 16>), grid, dim3(256), 0, s, A, omega, r, P, ldp, tm,  \
+                       tn, kc);                                                               \
+  else                                                                                        \
+    hipLaunchKernelGGL((k_project<DTV, 32>), grid, dim3(256), 0, s, A, omega, r, P, ldp, tm,  \
+                       tn, kc);                                                               \
+  break;
+    case DT_F32: GCSS_PROJ(DT_F32)
+    case DT_BF16: GCSS_PROJ(DT_BF16)
+    case DT_FP8: GCSS_PROJ(DT_FP8)
+#undef GCSS_PROJ
     default: return hipErrorInvalidValue;
   }
   hipError_t e = hipGetLastError();

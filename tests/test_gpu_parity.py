@@ -340,6 +340,33 @@ def test_batched_blocks_and_merge_match_oracle(gpu, dt):
     assert nm == km and st == gpu.OK
 
 
+def test_batched_on_dirty_workspace(gpu):
+    """A workspace holding all-ones bytes (NaN as float, -1 as int64) gives
+    the same picks as a zero-filled one: nothing is read before written."""
+    import torch
+    m, r, kb, km = 128, 16, 6, 10
+    widths = [700, 64, 1025, 300]
+    off = np.concatenate([[0], np.cumsum(widths)]).astype(np.int64)
+    n = int(off[-1])
+    A32 = colstore32(synth.gauss_lowrank_dense(m, n, 20, 0.1, seed=14))
+    Bcs = colstore32(stored_dense(A32, m) @ synth.omega_gauss(n, r, seed=15).astype(np.float64))
+    probe = gpu.Selector(dev(A32), m, k_max=kb, r_max=r, batched=(len(widths), kb, km))
+    nbytes = probe.ws_bytes
+    probe.close()
+    res = []
+    for fill in (0x00, 0xFF):
+        ws = torch.full((nbytes,), fill, dtype=torch.uint8, device="cuda")
+        s = gpu.Selector(dev(A32), m, k_max=kb, r_max=r, batched=(len(widths), kb, km), workspace=ws)
+        s.set_target(dev(Bcs))
+        ib, im, om, nm, st = s.select_batched(off, kb, km)
+        assert nm == km and st == gpu.OK and np.all(ib >= 0), (fill, ib)
+        i1, o1, n1, _ = s.select(kb)
+        res.append((ib, im, om, i1, o1))
+        s.close()
+    for a, b in zip(res[0], res[1]):
+        assert np.array_equal(np.asarray(a), np.asarray(b))
+
+
 def test_batched_equals_blockwise_single_runs(gpu):
     m, r, kb, km = 128, 16, 6, 10
     widths = [700, 64, 1025, 300]
