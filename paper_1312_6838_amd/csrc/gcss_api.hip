@@ -345,13 +345,15 @@ gcss_status gcss_create(const gcss_desc *d, void *workspace, size_t ws_bytes, gc
   if (ws_bytes < L.total)
     return fail(GCSS_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
 
-  // streaming-pass tunables (see gcss_tune in the docs): column group size
-  // and non-temporal loads; then size the grid from the kernel's occupancy
+  // streaming-pass tunables: column group size of the batched pass, the
+  // load-group prefetch depth and the work units per workgroup; then size the
+  // grid and the unit from the kernel's occupancy
   if (const char *v = getenv("GCSS_STREAM_G")) {
     const int gsz = atoi(v);
     if (gsz == 16 || gsz == 32 || gsz == 64) L.geo.g = gsz;
   }
-  if (const char *v = getenv("GCSS_STREAM_NT")) L.geo.nt = atoi(v) != 0;
+  if (const char *v = getenv("GCSS_STREAM_PD")) L.geo.pd = atoi(v) >= 2 ? 2 : 1;
+  if (const char *v = getenv("GCSS_STREAM_UPW")) L.geo.upw = std::max(1, atoi(v));
   {
     hipError_t fe = stream_finalize(L.geo, d->n, d->a_dtype, num_cu);
     if (fe != hipSuccess) return fail(GCSS_ERR_DEVICE, "stream kernel occupancy: %s", hipGetErrorString(fe));

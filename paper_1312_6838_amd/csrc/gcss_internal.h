@@ -60,7 +60,10 @@ struct StreamGeo {
   int g;         // columns per team group
   int grid;      // workgroups
   int qlen;      // padded length of q32/z32
-  int nt;        // 1: non-temporal loads of A
+  int pd;        // load groups in flight ahead of the one being reduced (1, 2)
+  int ucol;      // columns per team in one work unit of the queue
+  int upw;       // work units per workgroup the unit size aims at
+  int occ;       // resident workgroups per CU of the chosen kernel
   int ql;        // 1: q and z held in LDS instead of registers
 };
 

@@ -732,14 +732,17 @@ hipError_t launch_obj_from_quad(const double *F0, const double *quad, const DevS
 }
 
 // ---------------------------------------------------------------------------
-// k values per LDS stage of the FP32 contractions: 32 by default; the
-// environment variable GCSS_MFMA_BK=16 selects the shallower stage.
-static int mfma_bk() {
-  static const int bk = [] {
+// k values per LDS stage of the FP32 contractions (measured best: 16 for the
+// triangular Gram init, which is register-bound at 32; 32 elsewhere); the
+// environment variable GCSS_MFMA_BK=16 or 32 forces one depth everywhere.
+static int mfma_bk(bool tri) {
+  static const int forced = [] {
     const char *e = std::getenv("GCSS_MFMA_BK");
-    return (e && std::atoi(e) == 16) ? 16 : 32;
+    const int v = e ? std::atoi(e) : 0;
+    return (v == 16 || v == 32) ? v : 0;
   }();
-  return bk;
+  if (forced) return forced;
+  return tri ? 16 : 32;
 }
 constexpr int KC_ALIGN = 32;  // split-K chunks are multiples of every stage depth
 
@@ -766,7 +769,7 @@ static hipError_t init_bk(const float *X, int64_t ldx, int64_t R, const AView &A
 template <int DT>
 static hipError_t init_dt(const float *X, int64_t ldx, int64_t R, const AView &A, double *f0,
                           double *g0, uint8_t *mask0, bool gram, hipStream_t s) {
-  if (mfma_bk() == 16) return init_bk<DT, 16>(X, ldx, R, A, f0, g0, mask0, gram, s);
+  if (mfma_bk(gram) == 16) return init_bk<DT, 16>(X, ldx, R, A, f0, g0, mask0, gram, s);
   return init_bk<DT, 32>(X, ldx, R, A, f0, g0, mask0, gram, s);
 }
 
@@ -822,7 +825,7 @@ hipError_t launch_gram(const AView &A, float *C, int64_t ldc, void *scratch, int
   const int64_t ldp = ((A.m + 3) / 4) * 4;
   float *P = (float *)scratch;
   const dim3 grid((unsigned)(nt * sp));
-  const bool bk16 = mfma_bk() == 16;
+  const bool bk16 = mfma_bk(false) == 16;
   switch (A.dtype) {
 #define GCSS_GRAM(DTV)                                                                        \
   if (bk16)                                                                                   \
@@ -882,7 +885,7 @@ hipError_t launch_project(const AView &A, const float *omega, int64_t r, float *
   const int64_t ldp = ((A.m + 3) / 4) * 4;
   float *P = (float *)scratch;
   const dim3 grid((unsigned)(tm * tn * sp));
-  const bool bk16 = mfma_bk() == 16;
+  const bool bk16 = mfma_bk(false) == 16;
   switch (A.dtype) {
 #define GCSS_PROJ(DTV)                                                                        \
   if (bk16)                                                                                   \

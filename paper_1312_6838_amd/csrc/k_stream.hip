@@ -64,19 +64,14 @@ __device__ __forceinline__ void decode_chunk(const uint4 &r, float *v) {
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-// 16-byte load of a chunk of A; NT: non-temporal (A is read once per pass).
-template <bool NT>
+// 16-byte non-temporal load of a chunk of A (A is read once per pass).
 __device__ __forceinline__ uint4 load_chunk(const char *p) {
-  u32x4 v;
-  if constexpr (NT)
-    v = __builtin_nontemporal_load((const u32x4 *)p);
-  else
-    v = *(const u32x4 *)p;
+  const u32x4 v = __builtin_nontemporal_load((const u32x4 *)p);
   return make_uint4(v[0], v[1], v[2], v[3]);
 }
 
-template <int DT, int NJ, int W, bool NT, bool QL>
-__global__ __launch_bounds__(256) void k_stream(AView A, int G, const float *__restrict__ q32,
+template <int DT, int NJ, int W, int PD, bool QL>
+__global__ __launch_bounds__(256) void k_stream(AView A, int ucol, const float *__restrict__ q32,
                                                 const float *__restrict__ z32,
                                                 double *__restrict__ f, double *__restrict__ g,
                                                 const double *__restrict__ g0,
@@ -89,7 +84,6 @@ __global__ __launch_bounds__(256) void k_stream(AView A, int G, const float *__r
   __shared__ float red[2][4][64];
   __shared__ double bs[4];
   __shared__ int64_t bi_s[4];
-  __shared__ int64_t sg_s;
 
   if (st->done) return;
   const bool rescore = score_only || st->skip;
@@ -101,8 +95,19 @@ __global__ __launch_bounds__(256) void k_stream(AView A, int G, const float *__r
   const int team = wave / W;
   const int ws = wave % W;
   const int64_t m = A.m, n = A.n;
-  const int64_t ngroups = (n + G - 1) / G;
-  const int64_t nsuper = (ngroups + TEAMS - 1) / TEAMS;
+  // Work units: unit su holds TEAMS * ucol consecutive columns, ucol per team
+  // (ucol <= 64, a multiple of (PD + 1) * U); workgroup b takes the units
+  // b * per .. b * per + per - 1 in order.  A team's loads run ahead across
+  // unit boundaries, so one unit's loads are in flight while the previous
+  // one is reduced.  (Shared queues of units balanced the workgroups better
+  // but cost more in waits and atomics than the imbalance.)
+  const int64_t nsu = (n + (int64_t)TEAMS * ucol - 1) / ((int64_t)TEAMS * ucol);
+  const int64_t per = (nsu + gridDim.x - 1) / gridDim.x;
+  auto unit_of = [&](int64_t kth) -> int64_t {
+    const int64_t su = (int64_t)blockIdx.x * per + kth;
+    return (kth < per && su < nsu) ? su : nsu;
+  };
+  const int gpu = ucol / U;  // load groups per unit
   const char *abase = (const char *)A.a;
   const int64_t col_bytes = A.lda * Elem<DT>::esize;
 
@@ -144,87 +149,120 @@ __global__ __launch_bounds__(256) void k_stream(AView A, int G, const float *__r
       }
     }
   }
+  // Every load is issued unconditionally (no branches around loads, so the
+  // waits for a load group are exact): chunks past the end of a column read
+  // its last chunk, and load groups past the end of the range read q (both
+  // cache hits); their values are masked or unused.
+  const int64_t nchunk = (m + EPC - 1) / EPC;
   const char *lane_off[NJ];
 #pragma unroll
-  for (int j = 0; j < NJ; ++j)
-    lane_off[j] = abase + ((int64_t)ws * 64 * NJ + j * 64 + lane) * 16;
+  for (int j = 0; j < NJ; ++j) {
+    const int64_t ci = (int64_t)ws * 64 * NJ + j * 64 + lane;
+    lane_off[j] = abase + (ci < nchunk ? ci : nchunk - 1) * 16;
+  }
 
   double best = -INFINITY;
   int64_t besti = kNoIdx;
+  // loads past the last column read q (resident in L2); unused
+  const char *dummy = (const char *)q32 + lane * 16;
 
-  for (;;) {
-    // next super-group of TEAMS * G columns from the work queue
-    if (threadIdx.x == 0) sg_s = (int64_t)atomicAdd(&st->cnt[3], 1u);
-    __syncthreads();
-    const int64_t sg = sg_s;
-    __syncthreads();
-    if (sg >= nsuper) break;
-    const int64_t grp = sg * TEAMS + team;
-    const int64_t col0 = grp * G;
-    const int ncol = grp < ngroups ? (int)((n - col0) < G ? (n - col0) : G) : 0;
-    float mw = 0.f, mz = 0.f;
-    if (!rescore && ncol > 0) {
-      uint4 cur[U][NJ], nxt[U][NJ];
-      auto fetch = [&](int c0, uint4 (&buf)[U][NJ]) {
+  int64_t kth = 0;
+  int64_t su_cur = unit_of(0), su_nxt = unit_of(1);
+
+  // ring of PD + 1 load groups of U columns: PD groups stay in flight while
+  // one is reduced, across unit boundaries
+  uint4 buf[PD + 1][U][NJ];
+  auto fetch = [&](int64_t su, int x, uint4 (&b)[U][NJ]) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const bool cv = (c0 + u) < ncol;
-          const int64_t cb = (col0 + c0 + u) * col_bytes;
+    for (int u = 0; u < U; ++u) {
+      const int64_t col = (su * TEAMS + team) * ucol + x * U + u;
+      const bool ok = su < nsu && col < n;
+      const int64_t cb = col * col_bytes;
 #pragma unroll
-          for (int j = 0; j < NJ; ++j)
-            buf[u][j] = (cv && valid[j] > 0) ? load_chunk<NT>(lane_off[j] + cb)
-                                             : make_uint4(0u, 0u, 0u, 0u);
+      for (int j = 0; j < NJ; ++j) b[u][j] = load_chunk(ok ? lane_off[j] + cb : dummy);
+    }
+  };
+  float mw = 0.f, mz = 0.f;
+  auto consume = [&](int x, const uint4 (&b)[U][NJ]) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      float dq = 0.f, dz = 0.f;
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        float v[EPC];
+        decode_chunk<DT>(b[u][j], v);
+        if (valid[j] < EPC) {
+#pragma unroll
+          for (int e = 0; e < EPC; ++e)
+            if (e >= valid[j]) v[e] = 0.f;
         }
-      };
-      fetch(0, cur);
-      for (int c0 = 0; c0 < ncol; c0 += U) {
-        if (c0 + U < ncol) fetch(c0 + U, nxt);  // in flight while this group reduces
+        if constexpr (QL) {
+          const int64_t e0 = ((int64_t)ws * 64 * NJ + j * 64 + lane) * EPC;
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          float dq = 0.f, dz = 0.f;
-#pragma unroll
-          for (int j = 0; j < NJ; ++j) {
-            float v[EPC];
-            decode_chunk<DT>(cur[u][j], v);
-            if (valid[j] < EPC) {
-#pragma unroll
-              for (int e = 0; e < EPC; ++e)
-                if (e >= valid[j]) v[e] = 0.f;
-            }
-            if constexpr (QL) {
-              const int64_t e0 = ((int64_t)ws * 64 * NJ + j * 64 + lane) * EPC;
-#pragma unroll
-              for (int e = 0; e < EPC; e += 4) {
-                const float4 a = *(const float4 *)(qz_lds + e0 + e);
-                const float4 b = *(const float4 *)(qz_lds + qlen + e0 + e);
-                dq = fmaf(v[e], a.x, dq);
-                dq = fmaf(v[e + 1], a.y, dq);
-                dq = fmaf(v[e + 2], a.z, dq);
-                dq = fmaf(v[e + 3], a.w, dq);
-                dz = fmaf(v[e], b.x, dz);
-                dz = fmaf(v[e + 1], b.y, dz);
-                dz = fmaf(v[e + 2], b.z, dz);
-                dz = fmaf(v[e + 3], b.w, dz);
-              }
-            } else {
-#pragma unroll
-              for (int e = 0; e < EPC; ++e) {
-                dq = fmaf(v[e], qv[j][e], dq);
-                dz = fmaf(v[e], zv[j][e], dz);
-              }
-            }
+          for (int e = 0; e < EPC; e += 4) {
+            const float4 a = *(const float4 *)(qz_lds + e0 + e);
+            const float4 bz = *(const float4 *)(qz_lds + qlen + e0 + e);
+            dq = fmaf(v[e], a.x, dq);
+            dq = fmaf(v[e + 1], a.y, dq);
+            dq = fmaf(v[e + 2], a.z, dq);
+            dq = fmaf(v[e + 3], a.w, dq);
+            dz = fmaf(v[e], bz.x, dz);
+            dz = fmaf(v[e + 1], bz.y, dz);
+            dz = fmaf(v[e + 2], bz.z, dz);
+            dz = fmaf(v[e + 3], bz.w, dz);
           }
-          dq = wave_sum(dq);
-          dz = wave_sum(dz);
-          if (lane == c0 + u) {
-            mw = dq;
-            mz = dz;
+        } else {
+#pragma unroll
+          for (int e = 0; e < EPC; ++e) {
+            dq = fmaf(v[e], qv[j][e], dq);
+            dz = fmaf(v[e], zv[j][e], dz);
           }
         }
+      }
+      dq = wave_sum(dq);
+      dz = wave_sum(dz);
+      if (lane == x * U + u) {
+        mw = dq;
+        mz = dz;
+      }
+    }
+  };
+  if (!rescore) {
 #pragma unroll
-        for (int u = 0; u < U; ++u)
+    for (int d = 0; d < PD; ++d) fetch(su_cur, d, buf[d]);
+  }
+
+  while (su_cur < nsu) {
+    const int64_t c0 = (su_cur * TEAMS + team) * ucol;  // this team's first column
+    const int ncol = (int)(c0 < n ? ((n - c0) < ucol ? (n - c0) : ucol) : 0);
+    // this unit's scores and state, loaded before its stream loads so that
+    // using them does not wait for loads issued later
+    // (unconditional loads from a clamped column: no branch, so no copies of
+    // in-flight registers at a join)
+    const bool mine = ws == 0 && lane < ncol;
+    const int64_t col = c0 + (lane < ncol ? lane : 0);
+    const int64_t colc = col < n ? col : n - 1;
+    double fv = f[colc], gv = g[colc];
+    const double g0v = g0[colc];
+    const int mk = mask[colc];
+    float sc = 1.f;
+    if constexpr (DT == DT_FP8) sc = A.scale[colc];
+    mw = 0.f;
+    mz = 0.f;
+    if (!rescore) {
+      for (int x0 = 0; x0 < gpu; x0 += PD + 1) {
 #pragma unroll
-          for (int j = 0; j < NJ; ++j) cur[u][j] = nxt[u][j];
+        for (int d = 0; d <= PD; ++d) {
+          // x0 is a multiple of PD + 1, so load group x0 + d sits in slot d;
+          // the group PD ahead may belong to the next unit
+          const int xt = x0 + d + PD;
+          const bool nx = xt >= gpu;
+          fetch(nx ? su_nxt : su_cur, nx ? xt - gpu : xt, buf[(d + PD) % (PD + 1)]);
+          consume(x0 + d, buf[d]);
+          // keeps the scheduler from hoisting later loads into renamed
+          // registers, which would force a full drain at the loop head
+          __builtin_amdgcn_sched_barrier(0);
+        }
       }
     }
     if constexpr (W > 1) {
@@ -241,27 +279,29 @@ __global__ __launch_bounds__(256) void k_stream(AView A, int G, const float *__r
         mw = sw;
         mz = sz;
       }
-      __syncthreads();
     }
-    if (ws == 0 && lane < ncol) {
-      const int64_t col = col0 + lane;
-      double fv = f[col], gv = g[col];
-      if (!rescore) {
-        const double s = (DT == DT_FP8) ? (double)A.scale[col] : 1.0;
-        const double w = s * (double)mw, y = s * (double)mz;
-        fv = fv - 2.0 * w * y + u2 * w * w;
-        gv = gv - w * w;
-        f[col] = fv;
-        g[col] = gv;
-      }
-      if (mask[col] == 0 && gv > tau * g0[col] && isfinite(fv) && isfinite(gv)) {
-        const double sc = fv / gv;
-        if (better(sc, col, best, besti)) {
-          best = sc;
-          besti = col;
-        }
-      }
+    // scores of this unit's columns; the preloaded values are used on every
+    // path (only the stores are predicated), so their waits stay exact
+    if (!rescore) {
+      const double s = (double)sc;
+      const double ww = s * (double)mw, y = s * (double)mz;
+      fv = fv - 2.0 * ww * y + u2 * ww * ww;
+      gv = gv - ww * ww;
     }
+    const bool elig = mine && mk == 0 && gv > tau * g0v && isfinite(fv) && isfinite(gv);
+    const double scv = fv / gv;
+    if (mine && !rescore) {
+      f[col] = fv;
+      g[col] = gv;
+    }
+    if (elig && better(scv, col, best, besti)) {
+      best = scv;
+      besti = col;
+    }
+    ++kth;
+    su_cur = su_nxt;
+    su_nxt = unit_of(kth + 1);
+    if constexpr (W > 1) __syncthreads();  // red[] is rewritten by the next unit
   }
 
   // workgroup winner
@@ -324,10 +364,31 @@ __global__ __launch_bounds__(256) void k_stream(AView A, int G, const float *__r
   }
   __syncthreads();
   // the next pick's column, decoded to FP64, for the next Gram-Schmidt step
+  // (16-byte chunks, four loads per thread in flight before any is used)
   const int64_t pn = bi_s[0];
   if (pn != kNoIdx) {
     const double sp = col_scale(A, pn);
-    for (int64_t j = threadIdx.x; j < m; j += blockDim.x) ap64[j] = sp * (double)load_elem(A, pn, j);
+    const char *colp = abase + pn * col_bytes;
+    constexpr int UNR = 4;
+    for (int64_t c0 = threadIdx.x; c0 < nchunk; c0 += 256 * UNR) {
+      uint4 r[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int64_t c = c0 + 256 * u;
+        r[u] = c < nchunk ? *(const uint4 *)(colp + c * 16) : make_uint4(0u, 0u, 0u, 0u);
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int64_t c = c0 + 256 * u;
+        if (c < nchunk) {
+          float v[EPC];
+          decode_chunk<DT>(r[u], v);
+#pragma unroll
+          for (int e = 0; e < EPC; ++e)
+            if (c * EPC + e < m) ap64[c * EPC + e] = sp * (double)v[e];
+        }
+      }
+    }
   }
 }
 
@@ -342,16 +403,16 @@ typedef void (*StreamFn)(AView, int, const float *, const float *, double *, dou
                          const double *, const uint8_t *, ArgPart *, DevState *, double *, int);
 
 template <int DT, int NJ, int W, bool QL>
-static StreamFn pick_nt(bool nt) {
-  return nt ? (StreamFn)k_stream<DT, NJ, W, true, QL> : (StreamFn)k_stream<DT, NJ, W, false, QL>;
+static StreamFn pick_pd(int pd) {
+  return pd >= 2 ? (StreamFn)k_stream<DT, NJ, W, 2, QL> : (StreamFn)k_stream<DT, NJ, W, 1, QL>;
 }
 
 template <int DT, int NJ, bool QL>
-static StreamFn pick_w(int w, bool nt) {
+static StreamFn pick_w(int w, int pd) {
   switch (w) {
-    case 1: return pick_nt<DT, NJ, 1, QL>(nt);
-    case 2: return pick_nt<DT, NJ, 2, QL>(nt);
-    case 4: return pick_nt<DT, NJ, 4, QL>(nt);
+    case 1: return pick_pd<DT, NJ, 1, QL>(pd);
+    case 2: return pick_pd<DT, NJ, 2, QL>(pd);
+    case 4: return pick_pd<DT, NJ, 4, QL>(pd);
   }
   return nullptr;
 }
@@ -359,31 +420,31 @@ static StreamFn pick_w(int w, bool nt) {
 // Register-resident q, z: at most 32 floats each per lane.  LDS-resident:
 // up to 16 chunks per lane per column.
 template <int DT, bool QL>
-static StreamFn pick_nj(int nj, int w, bool nt) {
+static StreamFn pick_nj(int nj, int w, int pd) {
   constexpr int NJMAX = QL ? 16 : 32 / Elem<DT>::epc;
   switch (nj) {
-    case 1: return pick_w<DT, 1, QL>(w, nt);
+    case 1: return pick_w<DT, 1, QL>(w, pd);
     case 2:
-      if constexpr (NJMAX >= 2) return pick_w<DT, 2, QL>(w, nt);
+      if constexpr (NJMAX >= 2) return pick_w<DT, 2, QL>(w, pd);
       break;
     case 4:
-      if constexpr (NJMAX >= 4) return pick_w<DT, 4, QL>(w, nt);
+      if constexpr (NJMAX >= 4) return pick_w<DT, 4, QL>(w, pd);
       break;
     case 8:
-      if constexpr (NJMAX >= 8) return pick_w<DT, 8, QL>(w, nt);
+      if constexpr (NJMAX >= 8) return pick_w<DT, 8, QL>(w, pd);
       break;
     case 16:
-      if constexpr (NJMAX >= 16) return pick_w<DT, 16, QL>(w, nt);
+      if constexpr (NJMAX >= 16) return pick_w<DT, 16, QL>(w, pd);
       break;
   }
   return nullptr;
 }
 
-static StreamFn pick_kernel(int dtype, int nj, int w, bool nt, bool ql) {
+static StreamFn pick_kernel(int dtype, int nj, int w, int pd, bool ql) {
   switch (dtype) {
-    case DT_F32: return ql ? pick_nj<DT_F32, true>(nj, w, nt) : pick_nj<DT_F32, false>(nj, w, nt);
-    case DT_BF16: return ql ? pick_nj<DT_BF16, true>(nj, w, nt) : pick_nj<DT_BF16, false>(nj, w, nt);
-    case DT_FP8: return ql ? pick_nj<DT_FP8, true>(nj, w, nt) : pick_nj<DT_FP8, false>(nj, w, nt);
+    case DT_F32: return ql ? pick_nj<DT_F32, true>(nj, w, pd) : pick_nj<DT_F32, false>(nj, w, pd);
+    case DT_BF16: return ql ? pick_nj<DT_BF16, true>(nj, w, pd) : pick_nj<DT_BF16, false>(nj, w, pd);
+    case DT_FP8: return ql ? pick_nj<DT_FP8, true>(nj, w, pd) : pick_nj<DT_FP8, false>(nj, w, pd);
   }
   return nullptr;
 }
@@ -392,11 +453,12 @@ static size_t stream_lds(const StreamGeo &geo) {
   return geo.ql ? (size_t)2 * geo.qlen * sizeof(float) : 0;
 }
 
-// Shape of the streaming pass: rows per lane, waves per column, column group
-// size, and a persistent grid of as many workgroups as fit on the chip at
-// once (work is handed out through an atomic queue, so uneven column counts
-// do not leave a partial last round).  The grid is an upper bound until
-// stream_finalize() knows the occupancy of the chosen kernel.
+// Shape of the streaming pass: rows per lane, waves per column, and a grid of
+// as many workgroups as fit on the chip at once; every team streams one
+// contiguous range of ceil(n / teams) columns, so the work is balanced by
+// construction and each team's loads run ahead across its whole range.  The
+// grid is an upper bound until stream_finalize() knows the occupancy of the
+// chosen kernel.
 StreamGeo stream_geometry(int64_t m, int64_t n, int dtype, int num_cu, int ql) {
   StreamGeo geo{};
   const int epc = 16 / dtype_bytes(dtype);
@@ -414,30 +476,43 @@ StreamGeo stream_geometry(int64_t m, int64_t n, int dtype, int num_cu, int ql) {
   geo.w = w;
   geo.ql = ql;
   geo.qlen = w * 64 * nj * epc;
-  geo.g = 64;
-  geo.nt = 1;  // measured faster: A is read once per pass
+  geo.g = 64;  // column groups of the batched pass
+  geo.pd = 1;
+  geo.upw = 4;
   const int teams = 4 / w;
-  const int64_t nsuper = (((n + geo.g - 1) / geo.g) + teams - 1) / teams;
+  const int64_t need = (n + teams - 1) / teams;
   const int64_t cap = 8LL * num_cu;  // upper bound: 8 workgroups (32 waves) per CU
-  geo.grid = (int)(nsuper < cap ? nsuper : cap);
+  geo.grid = (int)(need < cap ? need : cap);
   if (geo.grid < 1) geo.grid = 1;
   return geo;
 }
 
 hipError_t stream_finalize(StreamGeo &geo, int64_t n, int dtype, int num_cu) {
-  StreamFn fn = pick_kernel(dtype, geo.nj, geo.w, geo.nt != 0, geo.ql != 0);
+  StreamFn fn = pick_kernel(dtype, geo.nj, geo.w, geo.pd, geo.ql != 0);
   if (!fn) return hipErrorInvalidValue;
   int per_cu = 0;
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)fn, 256,
                                                               stream_lds(geo));
   if (e != hipSuccess) return e;
   if (per_cu < 1) per_cu = 1;
+  geo.occ = per_cu;
   const int teams = 4 / geo.w;
-  const int64_t nsuper = (((n + geo.g - 1) / geo.g) + teams - 1) / teams;
+  const int64_t need = (n + teams - 1) / teams;
   int64_t want = (int64_t)per_cu * num_cu;
-  if (want > nsuper) want = nsuper;
+  if (want > need) want = need;
   if (want > geo.grid) want = geo.grid;  // never above the workspace's partial count
   geo.grid = (int)(want < 1 ? 1 : want);
+  // unit size: about upw units per workgroup (the last unit of a workgroup
+  // bounds the imbalance at the end of the pass), a multiple of the ring
+  const int U = geo.nj >= 8 ? 1 : 8 / geo.nj;
+  const int quantum = (geo.pd + 1) * U;
+  const int64_t per = (int64_t)geo.grid * teams * (geo.upw > 0 ? geo.upw : 1);
+  int64_t uc = (n + per - 1) / per;
+  uc = ((uc + quantum - 1) / quantum) * quantum;
+  const int64_t ucmax = (64 / quantum) * quantum;
+  if (uc > ucmax) uc = ucmax;
+  if (uc < quantum) uc = quantum;
+  geo.ucol = (int)uc;
   return hipSuccess;
 }
 
@@ -445,10 +520,10 @@ hipError_t launch_stream(const StreamGeo &geo, const AView &A, const float *q32,
                          const float *z32, double *f, double *g, const double *g0,
                          uint8_t *mask, ArgPart *part, DevState *st, double *ap64,
                          int score_only, hipStream_t s) {
-  StreamFn fn = pick_kernel(A.dtype, geo.nj, geo.w, geo.nt != 0, geo.ql != 0);
+  StreamFn fn = pick_kernel(A.dtype, geo.nj, geo.w, geo.pd, geo.ql != 0);
   if (!fn) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(fn, dim3(geo.grid), dim3(256), stream_lds(geo), s, A, geo.g, q32, z32, f, g, g0, mask,
-                     part, st, ap64, score_only);
+  hipLaunchKernelGGL(fn, dim3(geo.grid), dim3(256), stream_lds(geo), s, A, geo.ucol, q32, z32, f, g, g0,
+                     mask, part, st, ap64, score_only);
   return hipGetLastError();
 }
 
