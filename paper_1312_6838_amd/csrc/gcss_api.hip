@@ -57,10 +57,10 @@ struct Carve {
 
 // Offsets of every workspace region for a description (sizes only).
 struct Layout {
-  size_t f0, g0, f, g, mask0, mask, part, npart, Q, e1, e2, w, q64, q32, z32, c1, c2, c3, ups,
+  size_t f0, g0, f, g, mask0, mask, part, qpart, npart, Q, e1, e2, w, q64, q32, z32, c1, c2, c3, ups,
       st, idx, obj, scal, pick, quad, ap64, gram, scratch, total;
   size_t scratch_bytes;
-  size_t qbuf;  // floats in q32 / z32 (covers both stream variants)
+  size_t qbuf;  // padded stream length of q32 / z32 / q64
   StreamGeo geo;
   int64_t ldq;
 };
@@ -68,16 +68,9 @@ struct Layout {
 bool make_layout(const gcss_desc *d, int num_cu, Layout *L) {
   const int64_t m = d->m, n = d->n, k = d->k_max, r = d->r_max;
   L->ldq = ld_for(m);
-  // both stream variants must fit the carve: size q32/z32 and the partials
-  // for the larger, pick the register variant unless told otherwise
-  StreamGeo g_reg = stream_geometry(m, n, d->a_dtype, num_cu, 0);
-  StreamGeo g_lds = stream_geometry(m, n, d->a_dtype, num_cu, 1);
-  const char *ql_env = getenv("GCSS_STREAM_QL");
-  const bool use_lds = (ql_env && atoi(ql_env) != 0) || g_reg.nj == 0;
-  L->geo = use_lds ? g_lds : g_reg;
+  L->geo = stream_geometry(m, n, d->a_dtype, num_cu);
   if (L->geo.nj == 0) return false;
-  L->geo.grid = std::max(g_reg.grid, g_lds.grid);
-  L->qbuf = (size_t)std::max(g_reg.nj ? g_reg.qlen : 0, g_lds.qlen);
+  L->qbuf = (size_t)L->geo.qlen;
   Carve c;
   L->f0 = c.take<double>(n);
   L->g0 = c.take<double>(n);
@@ -86,13 +79,14 @@ bool make_layout(const gcss_desc *d, int num_cu, Layout *L) {
   L->mask0 = c.take<uint8_t>(n);
   L->mask = c.take<uint8_t>(n);
   L->part = c.take<ArgPart>(std::max(L->geo.grid, 1));
+  L->qpart = c.take<double>(std::max(L->geo.grid, 1));
   L->npart = c.take<double>(1024);
   L->Q = c.take<double>((size_t)L->ldq * (k + 1));
   L->e1 = c.take<double>(L->ldq);
   L->e2 = c.take<double>(L->ldq);
   L->w = c.take<double>(L->ldq);
-  L->q64 = c.take<double>(L->ldq);
   const size_t qlen = std::max<size_t>(L->qbuf, L->ldq);
+  L->q64 = c.take<double>(qlen);
   L->q32 = c.take<float>(qlen);
   L->z32 = c.take<float>(qlen);
   L->c1 = c.take<double>(k + 8);
@@ -263,23 +257,25 @@ hipError_t enqueue_step(gcss_ctx *h) {
   // z = w - Q_{t-1} c3 ; record the pick
   if ((e = launch_rows(Q, nullptr, ldq, m, 1, 0, VEC_F64, w, h->A, c3, nullptr, h->at<float>(h->L.z32), RF_Z, sb, s))) return e;
   if (h->profiling && (e = record(h))) return e;
-  if ((e = launch_stream(h->L.geo, h->A, h->at<float>(h->L.q32), h->at<float>(h->L.z32),
-                         h->at<double>(h->L.f), h->at<double>(h->L.g), h->at<double>(h->L.g0),
-                         h->at<uint8_t>(h->L.mask), h->at<ArgPart>(h->L.part), sb.st,
-                         h->at<double>(h->L.ap64), 0, s)))
+  // Gram target: the pass also returns the exact decrease ||A^T q||^2
+  const bool ex = h->target == 2;
+  if ((e = launch_stream(h->L.geo, h->A, h->at<float>(h->L.q32), h->at<double>(h->L.q64),
+                         h->at<float>(h->L.z32), h->at<double>(h->L.f), h->at<double>(h->L.g),
+                         h->at<double>(h->L.g0), h->at<uint8_t>(h->L.mask),
+                         h->at<ArgPart>(h->L.part), sb.st, h->at<double>(h->L.ap64), 0,
+                         ex ? h->at<double>(h->L.qpart) : nullptr,
+                         ex ? h->at<double>(h->L.quad) : nullptr, s)))
     return e;
   if (h->profiling && (e = record(h))) return e;
   return hipSuccess;
 }
 
-// Gram target: replace the per-step decrements (from the binary32 Gram
-// matrix) by the exact ||A^T q_s||^2 of an FP64 pass over A.
+// Gram target: the objective from the exact decrements ||A^T q_s||^2 that
+// the streaming passes returned (the per-step decrements use the binary32
+// Gram matrix).
 hipError_t enqueue_exact_objective(gcss_ctx *h) {
   if (h->target != 2) return hipSuccess;
   const StepBufs sb = h->bufs();
-  hipError_t e = launch_qta(h->at<double>(h->L.Q), h->L.ldq, h->d.k_max, sb.st, h->A,
-                            h->at<double>(h->L.scratch), h->at<double>(h->L.quad), h->stream);
-  if (e) return e;
   return launch_obj_from_quad(h->F0(), h->at<double>(h->L.quad), sb.st, sb.obj, h->stream);
 }
 
@@ -291,10 +287,11 @@ hipError_t enqueue_begin(gcss_ctx *h, int k) {
                                      k, h->d.k_max, h->F0(), h->d.tau, h->stream);
   if (e) return e;
   // first argmax over the initial scores
-  return launch_stream(h->L.geo, h->A, h->at<float>(h->L.q32), h->at<float>(h->L.z32),
-                       h->at<double>(h->L.f), h->at<double>(h->L.g), h->at<double>(h->L.g0),
-                       h->at<uint8_t>(h->L.mask), h->at<ArgPart>(h->L.part), sb.st,
-                       h->at<double>(h->L.ap64), 1, h->stream);
+  return launch_stream(h->L.geo, h->A, h->at<float>(h->L.q32), h->at<double>(h->L.q64),
+                       h->at<float>(h->L.z32), h->at<double>(h->L.f), h->at<double>(h->L.g),
+                       h->at<double>(h->L.g0), h->at<uint8_t>(h->L.mask),
+                       h->at<ArgPart>(h->L.part), sb.st, h->at<double>(h->L.ap64), 1, nullptr,
+                       nullptr, h->stream);
 }
 
 gcss_status check_ctx(gcss_ctx *h) {
@@ -377,6 +374,7 @@ gcss_status gcss_create(const gcss_desc *d, void *workspace, size_t ws_bytes, gc
   const size_t qlen = std::max<size_t>(L.qbuf, L.ldq);
   hipError_t e = launch_zero_f32(h->at<float>(L.q32), (int64_t)qlen, h->stream);
   if (!e) e = launch_zero_f32(h->at<float>(L.z32), (int64_t)qlen, h->stream);
+  if (!e) e = launch_zero_f32(h->at<float>(L.q64), 2 * (int64_t)qlen, h->stream);
   if (e) {
     delete h;
     return fail(GCSS_ERR_DEVICE, "init: %s", hipGetErrorString(e));

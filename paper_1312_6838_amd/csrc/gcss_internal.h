@@ -23,7 +23,7 @@ struct alignas(256) DevState {
   int32_t skip;       // 1: the current pick was rejected; the step only rescores
   int32_t n_reject;   // number of rejected picks
   int32_t pos;        // position in a caller's pick list (basis-only mode)
-  int32_t pad1;
+  int32_t dec_pending;  // 1: a pick was recorded whose exact decrease is not yet known
   int64_t p;          // current pick (-1 none)
   double F;           // objective after the last completed pick
   double u2;          // ||upsilon||^2 of the current step
@@ -59,22 +59,26 @@ struct StreamGeo {
   int w;         // waves per team (column slice count)
   int g;         // columns per team group
   int grid;      // workgroups
+  int grid_ex;   // workgroups of the exact-decrease variant (Gram target)
+  int ucol_ex;   // its unit size
   int qlen;      // padded length of q32/z32
   int pd;        // load groups in flight ahead of the one being reduced (1, 2)
   int ucol;      // columns per team in one work unit of the queue
   int upw;       // work units per workgroup the unit size aims at
   int occ;       // resident workgroups per CU of the chosen kernel
-  int ql;        // 1: q and z held in LDS instead of registers
 };
 
 // ---- launchers (k_stream.hip) ----
-StreamGeo stream_geometry(int64_t m, int64_t n, int dtype, int num_cu, int ql);
+StreamGeo stream_geometry(int64_t m, int64_t n, int dtype, int num_cu);
 // Sets the grid from the occupancy of the chosen kernel (needs the device).
 hipError_t stream_finalize(StreamGeo &geo, int64_t n, int dtype, int num_cu);
+// qpart/quad non-null: the exact-decrease variant (Gram target), which reads
+// q64 and writes sum_i (A_i . q)^2 to quad[t - 1].
 hipError_t launch_stream(const StreamGeo &geo, const AView &A, const float *q32,
-                         const float *z32, double *f, double *g, const double *g0,
-                         uint8_t *mask, ArgPart *part, DevState *st, double *ap64,
-                         int score_only, hipStream_t s);
+                         const double *q64, const float *z32, double *f, double *g,
+                         const double *g0, uint8_t *mask, ArgPart *part, DevState *st,
+                         double *ap64, int score_only, double *qpart, double *quad,
+                         hipStream_t s);
 
 // ---- launchers (k_gemv.hip) ----
 // Buffers of one selection problem that the per-step kernels touch.

@@ -302,7 +302,7 @@ __global__ void k_batch_begin(const double *__restrict__ f0, const double *__res
     st->skip = 0;
     st->n_reject = 0;
     st->pos = 0;
-    st->pad1 = 0;
+    st->dec_pending = 0;
     st->p = -1;
     st->F = *F0;
     st->u2 = 0.0;

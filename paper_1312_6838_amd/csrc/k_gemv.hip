@@ -59,7 +59,7 @@ __global__ __launch_bounds__(256) void k_cols(const MT *__restrict__ M, int64_t 
     } else {
       const int64_t mp = m & ~(int64_t)1;
       double a0 = 0.0, a1 = 0.0;
-#pragma unroll 4
+#pragma unroll 8
       for (int64_t j = 2 * threadIdx.x; j < mp; j += 512) {
         const double2 x = load2<MT>(col + j);
         const double2 y = *(const double2 *)(vec + j);
@@ -76,16 +76,23 @@ __global__ __launch_bounds__(256) void k_cols(const MT *__restrict__ M, int64_t 
   }
   if (final_mode == CF_NONE) return;
   if (!last_block_arrive(&st->cnt[1])) return;
-  if (threadIdx.x == 0) {
-    double u2 = 0.0;
-    if (final_mode == CF_UPS) {
-      for (int x = 0; x < ns; ++x) {
-        const double v = load_acquire_f64(&out[x]);
-        u2 += v * v;
-      }
-    } else {  // CF_GRAM_U2: the last coefficient is q . (C q)
-      u2 = load_acquire_f64(&out[t]);
+  // Last workgroup: the other workgroups' outputs are visible after the fence
+  // and barrier of last_block_arrive; all threads read them (fixed-order sum).
+  double u2;
+  if (final_mode == CF_UPS) {
+    double a = 0.0;
+    for (int x = threadIdx.x; x < ns; x += blockDim.x) {
+      const double v = out[x];
+      a = fma(v, v, a);
     }
+    a = wave_sum(a);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+    __syncthreads();
+    u2 = ((red[0] + red[1]) + red[2]) + red[3];
+  } else {  // CF_GRAM_U2: the last coefficient is q . (C q)
+    u2 = out[t];
+  }
+  if (threadIdx.x == 0) {
     st->u2 = u2;
     st->cnt[1] = 0;
   }
@@ -95,6 +102,7 @@ __global__ __launch_bounds__(256) void k_cols(const MT *__restrict__ M, int64_t 
 // its 16 waves split the sum over s; partial sums meet in LDS in a fixed
 // order.  VSRC: -1 no base vector, VEC_F64, VEC_ACOL.
 constexpr int kRowsWaves = 16;
+constexpr int kRowsUnroll = 8;
 
 template <typename MT, int VSRC>
 __global__ __launch_bounds__(1024) void k_rows(const MT *__restrict__ M, int64_t ldm, int64_t m,
@@ -133,17 +141,18 @@ __global__ __launch_bounds__(1024) void k_rows(const MT *__restrict__ M, int64_t
   if (j < m) {
     const MT *base = M + j;
     int s = wave;
-    for (; s + 3 * kRowsWaves < ns; s += 4 * kRowsWaves) {
-      double2 x[4];
-      double cc[4];
+    // kRowsUnroll loads per lane in flight before the first is used
+    for (; s + (kRowsUnroll - 1) * kRowsWaves < ns; s += kRowsUnroll * kRowsWaves) {
+      double2 x[kRowsUnroll];
+      double cc[kRowsUnroll];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < kRowsUnroll; ++u) {
         const int64_t off = (int64_t)(s + u * kRowsWaves) * ldm;
         x[u] = full ? load2<MT>(base + off) : make_double2((double)base[off], 0.0);
         cc[u] = c[s + u * kRowsWaves];
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < kRowsUnroll; ++u) {
         a0 = fma(x[u].x, cc[u], a0);
         a1 = fma(x[u].y, cc[u], a1);
       }
@@ -198,9 +207,16 @@ __global__ __launch_bounds__(1024) void k_rows(const MT *__restrict__ M, int64_t
 
   if (final_mode == RF_GS2) {
     // ||e||^2, basis check, q = e / ||e||
+    // (the other workgroups' partials are visible after the fence and barrier
+    // of last_block_arrive; fixed-order sum over all threads)
+    double a = 0.0;
+    for (int x = threadIdx.x; x < (int)gridDim.x; x += blockDim.x) a += sb.part[x];
+    a = wave_sum(a);
+    if (lane == 0) red[wave][0].x = a;
+    __syncthreads();
     if (threadIdx.x == 0) {
       double s2 = 0.0;
-      for (int x = 0; x < (int)gridDim.x; ++x) s2 += load_acquire_f64(&sb.part[x]);
+      for (int x = 0; x < kRowsWaves; ++x) s2 += red[x][0].x;
       const int64_t pp = sb.pick_list ? sb.pick_list[st->pos] : st->p;
       const int good = isfinite(s2) && s2 > st->tau * sb.g0[pp];
       nrm = s2;
@@ -217,7 +233,7 @@ __global__ __launch_bounds__(1024) void k_rows(const MT *__restrict__ M, int64_t
     if (ok) {
       const double inv = 1.0 / sqrt(nrm);
       for (int64_t jj = threadIdx.x; jj < m; jj += blockDim.x) {
-        const double qv = load_acquire_f64(&out64[jj]) * inv;
+        const double qv = out64[jj] * inv;
         sb.Q[(int64_t)t * sb.ldq + jj] = qv;
         sb.q64[jj] = qv;
         sb.q32[jj] = (float)qv;
@@ -238,6 +254,7 @@ __global__ __launch_bounds__(1024) void k_rows(const MT *__restrict__ M, int64_t
       sb.idx[t] = pp;
       sb.mask[pp] = 1;
       st->t = t + 1;
+      st->dec_pending = 1;
       if (t + 1 >= st->k) st->done = 1;
       st->cnt[2] = 0;
     }
@@ -268,7 +285,7 @@ __global__ void k_select_begin(const double *__restrict__ f0, const double *__re
       st->skip = 0;
       st->n_reject = 0;
       st->pos = 0;
-      st->pad1 = 0;
+      st->dec_pending = 0;
       st->p = -1;
       st->F = F;
       st->u2 = 0.0;

@@ -18,6 +18,8 @@
 //   * after each column the two partial dots are summed across the wave,
 //     and lane c keeps the result of column c of the group;
 //   * the FP64 epilogue runs with one column per lane.
+#include <type_traits>
+
 #include "gcss_device.h"
 
 namespace gcss {
@@ -70,22 +72,35 @@ __device__ __forceinline__ uint4 load_chunk(const char *p) {
   return make_uint4(v[0], v[1], v[2], v[3]);
 }
 
-template <int DT, int NJ, int W, int PD, bool QL>
+// EX (Gram target B = A): omega_i = A_i . q is formed in FP64 from the FP64
+// basis vector (every product of a decoded element and q is exact before the
+// FP64 accumulation), and the pass also returns sum_i omega_i^2 = ||A^T q||^2,
+// the exact decrease of the objective, in quad[t - 1].
+template <int DT, int NJ, int W, int PD, bool EX>
 __global__ __launch_bounds__(256) void k_stream(AView A, int ucol, const float *__restrict__ q32,
+                                                const double *__restrict__ q64,
                                                 const float *__restrict__ z32,
                                                 double *__restrict__ f, double *__restrict__ g,
                                                 const double *__restrict__ g0,
                                                 const uint8_t *__restrict__ mask,
                                                 ArgPart *__restrict__ part, DevState *st,
-                                                double *__restrict__ ap64, int score_only) {
+                                                double *__restrict__ ap64, int score_only,
+                                                double *__restrict__ qpart,
+                                                double *__restrict__ quad) {
   constexpr int EPC = Elem<DT>::epc;
   constexpr int TEAMS = 4 / W;
   constexpr int U = (8 / NJ) > 0 ? (8 / NJ) : 1;  // columns per load group
-  __shared__ float red[2][4][64];
+  typedef typename std::conditional<EX, double, float>::type QT;  // q and omega type
+  __shared__ QT redq[4][64];
+  __shared__ float redz[4][64];
   __shared__ double bs[4];
   __shared__ int64_t bi_s[4];
+  __shared__ double qs[4];
 
-  if (st->done) return;
+  // after the last pick (done) the exact-decrease variant still makes one
+  // pass for that pick's decrease, without scores or a next pick
+  const bool qonly = EX && st->done && st->dec_pending;
+  if (st->done && !qonly) return;
   const bool rescore = score_only || st->skip;
   const double u2 = st->u2;
   const double tau = st->tau;
@@ -111,11 +126,10 @@ __global__ __launch_bounds__(256) void k_stream(AView A, int ucol, const float *
   const char *abase = (const char *)A.a;
   const int64_t col_bytes = A.lda * Elem<DT>::esize;
 
-  // q, z for this lane's rows; chunk j of the lane is ci(j) = ws*64*NJ + 64*j + lane.
-  // Registers (QL = false) or LDS (QL = true, for long columns).
-  extern __shared__ float qz_lds[];
-  constexpr int NR = QL ? 1 : NJ;
-  float qv[NR][EPC], zv[NR][EPC];
+  // q, z for this lane's rows (registers); chunk j of the lane is
+  // ci(j) = ws*64*NJ + 64*j + lane.
+  QT qv[NJ][EPC];
+  float zv[NJ][EPC];
   int valid[NJ];
 #pragma unroll
   for (int j = 0; j < NJ; ++j) {
@@ -123,30 +137,30 @@ __global__ __launch_bounds__(256) void k_stream(AView A, int ucol, const float *
     const int64_t e0 = ci * EPC;
     valid[j] = (int)(e0 < m ? (m - e0 < EPC ? m - e0 : EPC) : 0);
   }
-  const int qlen = W * 64 * NJ * EPC;
-  if constexpr (QL) {
-    for (int x = threadIdx.x * 4; x < qlen; x += 256 * 4) {
-      *(float4 *)(qz_lds + x) = *(const float4 *)(q32 + x);
-      *(float4 *)(qz_lds + qlen + x) = *(const float4 *)(z32 + x);
-    }
-    __syncthreads();
-  } else {
 #pragma unroll
-    for (int j = 0; j < NR; ++j) {
-      const int64_t e0 = ((int64_t)ws * 64 * NJ + j * 64 + lane) * EPC;
+  for (int j = 0; j < NJ; ++j) {
+    const int64_t e0 = ((int64_t)ws * 64 * NJ + j * 64 + lane) * EPC;
 #pragma unroll
-      for (int e = 0; e < EPC; e += 4) {
-        float4 a = *(const float4 *)(q32 + e0 + e);
-        float4 b = *(const float4 *)(z32 + e0 + e);
+    for (int e = 0; e < EPC; e += 4) {
+      if constexpr (EX) {
+        const double2 a0 = *(const double2 *)(q64 + e0 + e);
+        const double2 a1 = *(const double2 *)(q64 + e0 + e + 2);
+        qv[j][e] = a0.x;
+        qv[j][e + 1] = a0.y;
+        qv[j][e + 2] = a1.x;
+        qv[j][e + 3] = a1.y;
+      } else {
+        const float4 a = *(const float4 *)(q32 + e0 + e);
         qv[j][e] = a.x;
         qv[j][e + 1] = a.y;
         qv[j][e + 2] = a.z;
         qv[j][e + 3] = a.w;
-        zv[j][e] = b.x;
-        zv[j][e + 1] = b.y;
-        zv[j][e + 2] = b.z;
-        zv[j][e + 3] = b.w;
       }
+      const float4 b = *(const float4 *)(z32 + e0 + e);
+      zv[j][e] = b.x;
+      zv[j][e + 1] = b.y;
+      zv[j][e + 2] = b.z;
+      zv[j][e + 3] = b.w;
     }
   }
   // Every load is issued unconditionally (no branches around loads, so the
@@ -182,11 +196,14 @@ __global__ __launch_bounds__(256) void k_stream(AView A, int ucol, const float *
       for (int j = 0; j < NJ; ++j) b[u][j] = load_chunk(ok ? lane_off[j] + cb : dummy);
     }
   };
-  float mw = 0.f, mz = 0.f;
+  QT mw = 0;
+  float mz = 0.f;
+  double qacc = 0.0;  // EX: sum of omega^2 over this lane's columns
   auto consume = [&](int x, const uint4 (&b)[U][NJ]) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      float dq = 0.f, dz = 0.f;
+      QT dq = 0;
+      float dz = 0.f;
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
         float v[EPC];
@@ -196,27 +213,10 @@ __global__ __launch_bounds__(256) void k_stream(AView A, int ucol, const float *
           for (int e = 0; e < EPC; ++e)
             if (e >= valid[j]) v[e] = 0.f;
         }
-        if constexpr (QL) {
-          const int64_t e0 = ((int64_t)ws * 64 * NJ + j * 64 + lane) * EPC;
 #pragma unroll
-          for (int e = 0; e < EPC; e += 4) {
-            const float4 a = *(const float4 *)(qz_lds + e0 + e);
-            const float4 bz = *(const float4 *)(qz_lds + qlen + e0 + e);
-            dq = fmaf(v[e], a.x, dq);
-            dq = fmaf(v[e + 1], a.y, dq);
-            dq = fmaf(v[e + 2], a.z, dq);
-            dq = fmaf(v[e + 3], a.w, dq);
-            dz = fmaf(v[e], bz.x, dz);
-            dz = fmaf(v[e + 1], bz.y, dz);
-            dz = fmaf(v[e + 2], bz.z, dz);
-            dz = fmaf(v[e + 3], bz.w, dz);
-          }
-        } else {
-#pragma unroll
-          for (int e = 0; e < EPC; ++e) {
-            dq = fmaf(v[e], qv[j][e], dq);
-            dz = fmaf(v[e], zv[j][e], dz);
-          }
+        for (int e = 0; e < EPC; ++e) {
+          dq = fma((QT)v[e], qv[j][e], dq);
+          dz = fmaf(v[e], zv[j][e], dz);
         }
       }
       dq = wave_sum(dq);
@@ -247,7 +247,7 @@ __global__ __launch_bounds__(256) void k_stream(AView A, int ucol, const float *
     const int mk = mask[colc];
     float sc = 1.f;
     if constexpr (DT == DT_FP8) sc = A.scale[colc];
-    mw = 0.f;
+    mw = 0;
     mz = 0.f;
     if (!rescore) {
       for (int x0 = 0; x0 < gpu; x0 += PD + 1) {
@@ -266,15 +266,16 @@ __global__ __launch_bounds__(256) void k_stream(AView A, int ucol, const float *
       }
     }
     if constexpr (W > 1) {
-      red[0][wave][lane] = mw;
-      red[1][wave][lane] = mz;
+      redq[wave][lane] = mw;
+      redz[wave][lane] = mz;
       __syncthreads();
       if (ws == 0) {
-        float sw = 0.f, sz = 0.f;
+        QT sw = 0;
+        float sz = 0.f;
 #pragma unroll
         for (int x = 0; x < W; ++x) {
-          sw += red[0][wave + x][lane];
-          sz += red[1][wave + x][lane];
+          sw += redq[wave + x][lane];
+          sz += redz[wave + x][lane];
         }
         mw = sw;
         mz = sz;
@@ -287,10 +288,11 @@ __global__ __launch_bounds__(256) void k_stream(AView A, int ucol, const float *
       const double ww = s * (double)mw, y = s * (double)mz;
       fv = fv - 2.0 * ww * y + u2 * ww * ww;
       gv = gv - ww * ww;
+      if constexpr (EX) qacc += mine ? ww * ww : 0.0;
     }
     const bool elig = mine && mk == 0 && gv > tau * g0v && isfinite(fv) && isfinite(gv);
     const double scv = fv / gv;
-    if (mine && !rescore) {
+    if (mine && !rescore && !qonly) {
       f[col] = fv;
       g[col] = gv;
     }
@@ -301,14 +303,16 @@ __global__ __launch_bounds__(256) void k_stream(AView A, int ucol, const float *
     ++kth;
     su_cur = su_nxt;
     su_nxt = unit_of(kth + 1);
-    if constexpr (W > 1) __syncthreads();  // red[] is rewritten by the next unit
+    if constexpr (W > 1) __syncthreads();  // redq/redz are rewritten by the next unit
   }
 
-  // workgroup winner
+  // workgroup winner (and, EX, the workgroup's sum of omega^2, fixed order)
   wave_argmax(best, besti);
+  if constexpr (EX) qacc = wave_sum(qacc);
   if (lane == 0) {
     bs[wave] = best;
     bi_s[wave] = besti;
+    if constexpr (EX) qs[wave] = qacc;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -321,15 +325,34 @@ __global__ __launch_bounds__(256) void k_stream(AView A, int ucol, const float *
       }
     part[blockIdx.x].score = b;
     part[blockIdx.x].idx = bi;
+    if constexpr (EX) qpart[blockIdx.x] = ((qs[0] + qs[1]) + qs[2]) + qs[3];
   }
   if (!last_block_arrive(&st->cnt[0])) return;
 
-  // last workgroup: winner over all workgroups -> next pick
+  // last workgroup: the exact decrease of this step (EX) ...
+  if constexpr (EX) {
+    if (!rescore) {
+      double a = 0.0;
+      for (int x = threadIdx.x; x < (int)gridDim.x; x += blockDim.x) a += qpart[x];
+      a = wave_sum(a);
+      if (lane == 0) qs[wave] = a;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        quad[st->t - 1] = ((qs[0] + qs[1]) + qs[2]) + qs[3];
+        st->dec_pending = 0;
+      }
+    }
+    if (qonly) {
+      if (threadIdx.x == 0) st->cnt[0] = 0;
+      return;
+    }
+  }
+  // ... and the winner over all workgroups -> next pick
   best = -INFINITY;
   besti = kNoIdx;
   for (int x = threadIdx.x; x < (int)gridDim.x; x += blockDim.x) {
-    const double s = load_acquire_f64(&part[x].score);
-    const int64_t i = load_acquire_i64(&part[x].idx);
+    const double s = part[x].score;  // visible after last_block_arrive
+    const int64_t i = part[x].idx;
     if (better(s, i, best, besti)) {
       best = s;
       besti = i;
@@ -399,70 +422,61 @@ static int pow2_at_least(int64_t x) {
   return p;
 }
 
-typedef void (*StreamFn)(AView, int, const float *, const float *, double *, double *,
-                         const double *, const uint8_t *, ArgPart *, DevState *, double *, int);
+typedef void (*StreamFn)(AView, int, const float *, const double *, const float *, double *,
+                         double *, const double *, const uint8_t *, ArgPart *, DevState *, double *,
+                         int, double *, double *);
 
-template <int DT, int NJ, int W, bool QL>
+template <int DT, int NJ, int W, bool EX>
 static StreamFn pick_pd(int pd) {
-  return pd >= 2 ? (StreamFn)k_stream<DT, NJ, W, 2, QL> : (StreamFn)k_stream<DT, NJ, W, 1, QL>;
+  return pd >= 2 ? (StreamFn)k_stream<DT, NJ, W, 2, EX> : (StreamFn)k_stream<DT, NJ, W, 1, EX>;
 }
 
-template <int DT, int NJ, bool QL>
+template <int DT, int NJ, bool EX>
 static StreamFn pick_w(int w, int pd) {
   switch (w) {
-    case 1: return pick_pd<DT, NJ, 1, QL>(pd);
-    case 2: return pick_pd<DT, NJ, 2, QL>(pd);
-    case 4: return pick_pd<DT, NJ, 4, QL>(pd);
+    case 1: return pick_pd<DT, NJ, 1, EX>(pd);
+    case 2: return pick_pd<DT, NJ, 2, EX>(pd);
+    case 4: return pick_pd<DT, NJ, 4, EX>(pd);
   }
   return nullptr;
 }
 
-// Register-resident q, z: at most 32 floats each per lane.  LDS-resident:
-// up to 16 chunks per lane per column.
-template <int DT, bool QL>
+// q and z live in registers: at most 32 elements each per lane.
+template <int DT, bool EX>
 static StreamFn pick_nj(int nj, int w, int pd) {
-  constexpr int NJMAX = QL ? 16 : 32 / Elem<DT>::epc;
+  constexpr int NJMAX = 32 / Elem<DT>::epc;
   switch (nj) {
-    case 1: return pick_w<DT, 1, QL>(w, pd);
+    case 1: return pick_w<DT, 1, EX>(w, pd);
     case 2:
-      if constexpr (NJMAX >= 2) return pick_w<DT, 2, QL>(w, pd);
+      if constexpr (NJMAX >= 2) return pick_w<DT, 2, EX>(w, pd);
       break;
     case 4:
-      if constexpr (NJMAX >= 4) return pick_w<DT, 4, QL>(w, pd);
+      if constexpr (NJMAX >= 4) return pick_w<DT, 4, EX>(w, pd);
       break;
     case 8:
-      if constexpr (NJMAX >= 8) return pick_w<DT, 8, QL>(w, pd);
-      break;
-    case 16:
-      if constexpr (NJMAX >= 16) return pick_w<DT, 16, QL>(w, pd);
+      if constexpr (NJMAX >= 8) return pick_w<DT, 8, EX>(w, pd);
       break;
   }
   return nullptr;
 }
 
-static StreamFn pick_kernel(int dtype, int nj, int w, int pd, bool ql) {
+static StreamFn pick_kernel(int dtype, int nj, int w, int pd, bool ex) {
   switch (dtype) {
-    case DT_F32: return ql ? pick_nj<DT_F32, true>(nj, w, pd) : pick_nj<DT_F32, false>(nj, w, pd);
-    case DT_BF16: return ql ? pick_nj<DT_BF16, true>(nj, w, pd) : pick_nj<DT_BF16, false>(nj, w, pd);
-    case DT_FP8: return ql ? pick_nj<DT_FP8, true>(nj, w, pd) : pick_nj<DT_FP8, false>(nj, w, pd);
+    case DT_F32: return ex ? pick_nj<DT_F32, true>(nj, w, pd) : pick_nj<DT_F32, false>(nj, w, pd);
+    case DT_BF16: return ex ? pick_nj<DT_BF16, true>(nj, w, pd) : pick_nj<DT_BF16, false>(nj, w, pd);
+    case DT_FP8: return ex ? pick_nj<DT_FP8, true>(nj, w, pd) : pick_nj<DT_FP8, false>(nj, w, pd);
   }
   return nullptr;
-}
-
-static size_t stream_lds(const StreamGeo &geo) {
-  return geo.ql ? (size_t)2 * geo.qlen * sizeof(float) : 0;
 }
 
 // Shape of the streaming pass: rows per lane, waves per column, and a grid of
-// as many workgroups as fit on the chip at once; every team streams one
-// contiguous range of ceil(n / teams) columns, so the work is balanced by
-// construction and each team's loads run ahead across its whole range.  The
-// grid is an upper bound until stream_finalize() knows the occupancy of the
-// chosen kernel.
-StreamGeo stream_geometry(int64_t m, int64_t n, int dtype, int num_cu, int ql) {
+// as many workgroups as fit on the chip at once; workgroup b streams its own
+// consecutive work units (about upw of them).  The grid is an upper bound
+// until stream_finalize() knows the occupancy of the chosen kernels.
+StreamGeo stream_geometry(int64_t m, int64_t n, int dtype, int num_cu) {
   StreamGeo geo{};
   const int epc = 16 / dtype_bytes(dtype);
-  const int nj_max = ql ? 16 : 32 / epc;  // registers: q and z at most 32 floats each per lane
+  const int nj_max = 32 / epc;  // registers: q and z at most 32 elements each per lane
   const int64_t chunks = (m + epc - 1) / epc;
   int w = 1;
   while (w < 4 && chunks > (int64_t)64 * w * nj_max) w <<= 1;
@@ -474,7 +488,6 @@ StreamGeo stream_geometry(int64_t m, int64_t n, int dtype, int num_cu, int ql) {
   if (nj < 1) nj = 1;
   geo.nj = nj;
   geo.w = w;
-  geo.ql = ql;
   geo.qlen = w * 64 * nj * epc;
   geo.g = 64;  // column groups of the batched pass
   geo.pd = 1;
@@ -484,46 +497,55 @@ StreamGeo stream_geometry(int64_t m, int64_t n, int dtype, int num_cu, int ql) {
   const int64_t cap = 8LL * num_cu;  // upper bound: 8 workgroups (32 waves) per CU
   geo.grid = (int)(need < cap ? need : cap);
   if (geo.grid < 1) geo.grid = 1;
+  geo.grid_ex = geo.grid;
   return geo;
 }
 
-hipError_t stream_finalize(StreamGeo &geo, int64_t n, int dtype, int num_cu) {
-  StreamFn fn = pick_kernel(dtype, geo.nj, geo.w, geo.pd, geo.ql != 0);
+// grid = occupancy x CUs (at most the partial count of the workspace), and
+// the unit size for about upw units per workgroup, a multiple of the ring
+static hipError_t finalize_one(const StreamGeo &geo, int64_t n, int dtype, int num_cu, bool ex,
+                               int *grid, int *ucol) {
+  StreamFn fn = pick_kernel(dtype, geo.nj, geo.w, geo.pd, ex);
   if (!fn) return hipErrorInvalidValue;
   int per_cu = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)fn, 256,
-                                                              stream_lds(geo));
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)fn, 256, 0);
   if (e != hipSuccess) return e;
   if (per_cu < 1) per_cu = 1;
-  geo.occ = per_cu;
   const int teams = 4 / geo.w;
   const int64_t need = (n + teams - 1) / teams;
   int64_t want = (int64_t)per_cu * num_cu;
   if (want > need) want = need;
-  if (want > geo.grid) want = geo.grid;  // never above the workspace's partial count
-  geo.grid = (int)(want < 1 ? 1 : want);
-  // unit size: about upw units per workgroup (the last unit of a workgroup
-  // bounds the imbalance at the end of the pass), a multiple of the ring
+  if (want > *grid) want = *grid;
+  *grid = (int)(want < 1 ? 1 : want);
   const int U = geo.nj >= 8 ? 1 : 8 / geo.nj;
   const int quantum = (geo.pd + 1) * U;
-  const int64_t per = (int64_t)geo.grid * teams * (geo.upw > 0 ? geo.upw : 1);
+  const int64_t per = (int64_t)*grid * teams * (geo.upw > 0 ? geo.upw : 1);
   int64_t uc = (n + per - 1) / per;
   uc = ((uc + quantum - 1) / quantum) * quantum;
   const int64_t ucmax = (64 / quantum) * quantum;
   if (uc > ucmax) uc = ucmax;
   if (uc < quantum) uc = quantum;
-  geo.ucol = (int)uc;
+  *ucol = (int)uc;
   return hipSuccess;
 }
 
+hipError_t stream_finalize(StreamGeo &geo, int64_t n, int dtype, int num_cu) {
+  hipError_t e = finalize_one(geo, n, dtype, num_cu, false, &geo.grid, &geo.ucol);
+  if (!e) e = finalize_one(geo, n, dtype, num_cu, true, &geo.grid_ex, &geo.ucol_ex);
+  return e;
+}
+
 hipError_t launch_stream(const StreamGeo &geo, const AView &A, const float *q32,
-                         const float *z32, double *f, double *g, const double *g0,
-                         uint8_t *mask, ArgPart *part, DevState *st, double *ap64,
-                         int score_only, hipStream_t s) {
-  StreamFn fn = pick_kernel(A.dtype, geo.nj, geo.w, geo.pd, geo.ql != 0);
+                         const double *q64, const float *z32, double *f, double *g,
+                         const double *g0, uint8_t *mask, ArgPart *part, DevState *st,
+                         double *ap64, int score_only, double *qpart, double *quad,
+                         hipStream_t s) {
+  const bool ex = qpart != nullptr;
+  StreamFn fn = pick_kernel(A.dtype, geo.nj, geo.w, geo.pd, ex);
   if (!fn) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(fn, dim3(geo.grid), dim3(256), stream_lds(geo), s, A, geo.ucol, q32, z32, f, g, g0,
-                     mask, part, st, ap64, score_only);
+  hipLaunchKernelGGL(fn, dim3(ex ? geo.grid_ex : geo.grid), dim3(256), 0, s, A,
+                     ex ? geo.ucol_ex : geo.ucol, q32, q64, z32, f, g, g0, mask, part, st, ap64,
+                     score_only, qpart, quad);
   return hipGetLastError();
 }
 
