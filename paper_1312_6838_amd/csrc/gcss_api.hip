@@ -401,7 +401,7 @@ gcss_status gcss_set_target(gcss_ctx *h, const float *b, int64_t r, int64_t ldb)
     HIPCHK(launch_gram(h->A, C, h->L.ldq, h->at<void>(h->L.scratch), h->num_cu, h->stream));
     HIPCHK(launch_init_gram(C, h->L.ldq, h->A, h->at<double>(h->L.f0), h->at<double>(h->L.g0),
                             h->at<uint8_t>(h->L.mask0), h->stream));
-    HIPCHK(launch_sum_f64(h->at<double>(h->L.g0), h->d.n, h->F0(), h->stream));
+    HIPCHK(launch_sum_f64(h->at<double>(h->L.g0), h->d.n, h->F0(), h->at<double>(h->L.npart), 1024, h->stream));
     h->target = 2;
     h->B = nullptr;
     h->r = 0;
@@ -577,9 +577,9 @@ gcss_status gcss_reconstruction_error(gcss_ctx *h, const int64_t *idx, int32_t k
   if (h->target == 1) {
     double *colerr = (double *)scr;
     HIPCHK(launch_err_factor(Q, ldq, m, kb, h->B, h->ldb, h->r, colerr, s));
-    HIPCHK(launch_sum_f64(colerr, h->r, h->err_dev(), s));
+    HIPCHK(launch_sum_f64(colerr, h->r, h->err_dev(), nullptr, 0, s));
   } else if (kb == 0) {
-    HIPCHK(launch_sum_f64(h->F0(), 1, h->err_dev(), s));
+    HIPCHK(launch_sum_f64(h->F0(), 1, h->err_dev(), nullptr, 0, s));
   } else {
     // ||A||^2 - sum_s ||A^T q_s||^2; the selection that built this basis
     // already computed the terms exactly (quad), so only a fresh basis needs them

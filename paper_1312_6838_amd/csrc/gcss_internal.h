@@ -155,7 +155,9 @@ hipError_t launch_select_begin(const double *f0, const double *g0, const uint8_t
 hipError_t launch_finish(const StepBufs &sb, int k, int64_t *idx_out, double *obj_out,
                          int32_t *nsel_out, hipStream_t s);
 // out[0] = sum of x[0..n) (fixed order), FP64
-hipError_t launch_sum_f64(const double *x, int64_t n, double *out, hipStream_t s);
+// Fixed-order FP64 sum; part (npart doubles of scratch) serves long inputs.
+hipError_t launch_sum_f64(const double *x, int64_t n, double *out, double *part, int npart,
+                          hipStream_t s);
 // out[0] = sum of squares of an m x r FP32 column-major matrix
 hipError_t launch_sumsq_f32(const float *B, int64_t m, int64_t r, int64_t ldb, double *out,
                             hipStream_t s);

@@ -324,6 +324,23 @@ __global__ __launch_bounds__(256) void k_sum_f64(const double *__restrict__ x, i
   if (threadIdx.x == 0) *out = red[0];
 }
 
+// part[b] = fixed-order sum of x[b * chunk .. (b + 1) * chunk)
+__global__ __launch_bounds__(256) void k_sum_chunks(const double *__restrict__ x, int64_t n,
+                                                    int64_t chunk, double *__restrict__ part) {
+  __shared__ double red[256];
+  const int64_t b0 = (int64_t)blockIdx.x * chunk;
+  const int64_t b1 = (b0 + chunk) < n ? (b0 + chunk) : n;
+  double s = 0.0;
+  for (int64_t i = b0 + threadIdx.x; i < b1; i += 256) s += x[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
 __global__ __launch_bounds__(256) void k_sumsq_f32(const float *__restrict__ B, int64_t m,
                                                    int64_t r, int64_t ldb, double *out) {
   __shared__ double red[256];
@@ -476,8 +493,19 @@ hipError_t launch_finish(const StepBufs &sb, int k, int64_t *idx_out, double *ob
   return hipGetLastError();
 }
 
-hipError_t launch_sum_f64(const double *x, int64_t n, double *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(256), 0, s, x, n, out);
+// Long sums in two fixed-order levels: contiguous chunks, then the chunk sums.
+hipError_t launch_sum_f64(const double *x, int64_t n, double *out, double *part, int npart,
+                          hipStream_t s) {
+  const int64_t chunk = 8192;
+  const int64_t nb = (n + chunk - 1) / chunk;
+  if (nb <= 1 || part == nullptr || nb > npart) {
+    hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(256), 0, s, x, n, out);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_sum_chunks, dim3((unsigned)nb), dim3(256), 0, s, x, n, chunk, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(256), 0, s, part, nb, out);
   return hipGetLastError();
 }
 

@@ -9,14 +9,15 @@
 // The last workgroup to finish reduces the per-workgroup winners and writes
 // the next pick into the device state.
 //
-// Work mapping (CDNA4, 64-lane wavefronts, 256-thread workgroups):
-//   * a "team" of W wavefronts owns a group of G consecutive columns; wave
-//     w of the team reads rows [w*S, (w+1)*S) of each column, S = 64*NJ
-//     16-byte chunks, so every load instruction of a wave covers 1 KiB of
-//     one column, fully coalesced;
-//   * q and z for those rows live in registers (NJ * EPC floats each);
+// Work mapping (CDNA4, 64-lane wavefronts, 512-thread workgroups, one per CU):
+//   * a "team" of W wavefronts streams a sequence of work units of ucol
+//     consecutive columns; wave w of the team reads rows [w*S, (w+1)*S) of
+//     each column, S = 64*NJ 16-byte chunks, so every load instruction of a
+//     wave covers 1 KiB of one column, fully coalesced;
+//   * q and z for those rows live in registers (NJ * EPC elements each);
+//   * loads run ahead of the reduction through a ring of load groups;
 //   * after each column the two partial dots are summed across the wave,
-//     and lane c keeps the result of column c of the group;
+//     and lane c keeps the result of column c of the unit;
 //   * the FP64 epilogue runs with one column per lane.
 #include <type_traits>
 
@@ -72,12 +73,25 @@ __device__ __forceinline__ uint4 load_chunk(const char *p) {
   return make_uint4(v[0], v[1], v[2], v[3]);
 }
 
+// One workgroup of 8 waves per CU (at the kernel's occupancy of two waves per
+// SIMD): two 4-wave workgroups on one CU split its bandwidth unevenly (the
+// older one's loads win), which left the younger finishing alone.
+constexpr int kStreamWaves = 8;
+constexpr int kStreamThreads = 64 * kStreamWaves;
+
+__device__ __forceinline__ double sum_waves(const double (&v)[kStreamWaves]) {
+  double s = 0.0;
+#pragma unroll
+  for (int x = 0; x < kStreamWaves; ++x) s += v[x];
+  return s;
+}
+
 // EX (Gram target B = A): omega_i = A_i . q is formed in FP64 from the FP64
 // basis vector (every product of a decoded element and q is exact before the
 // FP64 accumulation), and the pass also returns sum_i omega_i^2 = ||A^T q||^2,
 // the exact decrease of the objective, in quad[t - 1].
 template <int DT, int NJ, int W, int PD, bool EX>
-__global__ __launch_bounds__(256) void k_stream(AView A, int ucol, const float *__restrict__ q32,
+__global__ __launch_bounds__(512) void k_stream(AView A, int ucol, const float *__restrict__ q32,
                                                 const double *__restrict__ q64,
                                                 const float *__restrict__ z32,
                                                 double *__restrict__ f, double *__restrict__ g,
@@ -88,14 +102,14 @@ __global__ __launch_bounds__(256) void k_stream(AView A, int ucol, const float *
                                                 double *__restrict__ qpart,
                                                 double *__restrict__ quad) {
   constexpr int EPC = Elem<DT>::epc;
-  constexpr int TEAMS = 4 / W;
+  constexpr int TEAMS = kStreamWaves / W;
   constexpr int U = (8 / NJ) > 0 ? (8 / NJ) : 1;  // columns per load group
   typedef typename std::conditional<EX, double, float>::type QT;  // q and omega type
-  __shared__ QT redq[4][64];
-  __shared__ float redz[4][64];
-  __shared__ double bs[4];
-  __shared__ int64_t bi_s[4];
-  __shared__ double qs[4];
+  __shared__ QT redq[kStreamWaves][64];
+  __shared__ float redz[kStreamWaves][64];
+  __shared__ double bs[kStreamWaves];
+  __shared__ int64_t bi_s[kStreamWaves];
+  __shared__ double qs[kStreamWaves];
 
   // after the last pick (done) the exact-decrease variant still makes one
   // pass for that pick's decrease, without scores or a next pick
@@ -318,14 +332,14 @@ __global__ __launch_bounds__(256) void k_stream(AView A, int ucol, const float *
   if (threadIdx.x == 0) {
     double b = bs[0];
     int64_t bi = bi_s[0];
-    for (int x = 1; x < 4; ++x)
+    for (int x = 1; x < kStreamWaves; ++x)
       if (better(bs[x], bi_s[x], b, bi)) {
         b = bs[x];
         bi = bi_s[x];
       }
     part[blockIdx.x].score = b;
     part[blockIdx.x].idx = bi;
-    if constexpr (EX) qpart[blockIdx.x] = ((qs[0] + qs[1]) + qs[2]) + qs[3];
+    if constexpr (EX) qpart[blockIdx.x] = sum_waves(qs);
   }
   if (!last_block_arrive(&st->cnt[0])) return;
 
@@ -338,7 +352,7 @@ __global__ __launch_bounds__(256) void k_stream(AView A, int ucol, const float *
       if (lane == 0) qs[wave] = a;
       __syncthreads();
       if (threadIdx.x == 0) {
-        quad[st->t - 1] = ((qs[0] + qs[1]) + qs[2]) + qs[3];
+        quad[st->t - 1] = sum_waves(qs);
         st->dec_pending = 0;
       }
     }
@@ -368,7 +382,7 @@ __global__ __launch_bounds__(256) void k_stream(AView A, int ucol, const float *
   if (threadIdx.x == 0) {
     double b = bs[0];
     int64_t bi = bi_s[0];
-    for (int x = 1; x < 4; ++x)
+    for (int x = 1; x < kStreamWaves; ++x)
       if (better(bs[x], bi_s[x], b, bi)) {
         b = bs[x];
         bi = bi_s[x];
@@ -393,16 +407,16 @@ __global__ __launch_bounds__(256) void k_stream(AView A, int ucol, const float *
     const double sp = col_scale(A, pn);
     const char *colp = abase + pn * col_bytes;
     constexpr int UNR = 4;
-    for (int64_t c0 = threadIdx.x; c0 < nchunk; c0 += 256 * UNR) {
+    for (int64_t c0 = threadIdx.x; c0 < nchunk; c0 += kStreamThreads * UNR) {
       uint4 r[UNR];
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
-        const int64_t c = c0 + 256 * u;
+        const int64_t c = c0 + kStreamThreads * u;
         r[u] = c < nchunk ? *(const uint4 *)(colp + c * 16) : make_uint4(0u, 0u, 0u, 0u);
       }
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
-        const int64_t c = c0 + 256 * u;
+        const int64_t c = c0 + kStreamThreads * u;
         if (c < nchunk) {
           float v[EPC];
           decode_chunk<DT>(r[u], v);
@@ -508,10 +522,10 @@ static hipError_t finalize_one(const StreamGeo &geo, int64_t n, int dtype, int n
   StreamFn fn = pick_kernel(dtype, geo.nj, geo.w, geo.pd, ex);
   if (!fn) return hipErrorInvalidValue;
   int per_cu = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)fn, 256, 0);
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)fn, kStreamThreads, 0);
   if (e != hipSuccess) return e;
   if (per_cu < 1) per_cu = 1;
-  const int teams = 4 / geo.w;
+  const int teams = kStreamWaves / geo.w;
   const int64_t need = (n + teams - 1) / teams;
   int64_t want = (int64_t)per_cu * num_cu;
   if (want > need) want = need;
@@ -543,7 +557,7 @@ hipError_t launch_stream(const StreamGeo &geo, const AView &A, const float *q32,
   const bool ex = qpart != nullptr;
   StreamFn fn = pick_kernel(A.dtype, geo.nj, geo.w, geo.pd, ex);
   if (!fn) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(fn, dim3(ex ? geo.grid_ex : geo.grid), dim3(256), 0, s, A,
+  hipLaunchKernelGGL(fn, dim3(ex ? geo.grid_ex : geo.grid), dim3(kStreamThreads), 0, s, A,
                      ex ? geo.ucol_ex : geo.ucol, q32, q64, z32, f, g, g0, mask, part, st, ap64,
                      score_only, qpart, quad);
   return hipGetLastError();
