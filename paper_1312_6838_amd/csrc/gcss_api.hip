@@ -413,7 +413,8 @@ gcss_status gcss_set_target(gcss_ctx *h, const float *b, int64_t r, int64_t ldb)
     if (((uintptr_t)b) % 16) return fail(GCSS_ERR_ARG, "B must be 16-byte aligned");
     HIPCHK(launch_init_factor(b, ldb, r, h->A, h->at<double>(h->L.f0), h->at<double>(h->L.g0),
                               h->at<uint8_t>(h->L.mask0), h->stream));
-    HIPCHK(launch_sumsq_f32(b, m, r, ldb, h->F0(), h->stream));
+    // (the step buffer for upsilon, r_max + 8 doubles, is free here)
+    HIPCHK(launch_sumsq_f32(b, m, r, ldb, h->F0(), h->at<double>(h->L.ups), h->stream));
     h->target = 1;
     h->B = b;
     h->r = r;

@@ -158,9 +158,9 @@ hipError_t launch_finish(const StepBufs &sb, int k, int64_t *idx_out, double *ob
 // Fixed-order FP64 sum; part (npart doubles of scratch) serves long inputs.
 hipError_t launch_sum_f64(const double *x, int64_t n, double *out, double *part, int npart,
                           hipStream_t s);
-// out[0] = sum of squares of an m x r FP32 column-major matrix
+// out[0] = sum of squares of an m x r FP32 column-major matrix (part: r doubles)
 hipError_t launch_sumsq_f32(const float *B, int64_t m, int64_t r, int64_t ldb, double *out,
-                            hipStream_t s);
+                            double *part, hipStream_t s);
 // Residual of an explicit target on basis Q (k columns):
 //   colerr[c] = || B_c - Q (Q^T B_c) ||^2, FP64
 hipError_t launch_err_factor(const double *Q, int64_t ldq, int64_t m, int k, const float *B,

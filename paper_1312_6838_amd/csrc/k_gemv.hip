@@ -341,22 +341,23 @@ __global__ __launch_bounds__(256) void k_sum_chunks(const double *__restrict__ x
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-__global__ __launch_bounds__(256) void k_sumsq_f32(const float *__restrict__ B, int64_t m,
-                                                   int64_t r, int64_t ldb, double *out) {
+// part[c] = fixed-order sum of squares of column c of B (m x r, ld ldb)
+__global__ __launch_bounds__(256) void k_sumsq_cols(const float *__restrict__ B, int64_t m,
+                                                    int64_t ldb, double *__restrict__ part) {
   __shared__ double red[256];
+  const float *col = B + (int64_t)blockIdx.x * ldb;
   double s = 0.0;
-  for (int64_t c = 0; c < r; ++c)
-    for (int64_t j = threadIdx.x; j < m; j += 256) {
-      const double v = B[c * ldb + j];
-      s += v * v;
-    }
+  for (int64_t j = threadIdx.x; j < m; j += 256) {
+    const double v = col[j];
+    s += v * v;
+  }
   red[threadIdx.x] = s;
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
     if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *out = red[0];
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
 // One workgroup per target column c: colerr[c] = || B_c - Q (Q^T B_c) ||^2.
@@ -509,9 +510,13 @@ hipError_t launch_sum_f64(const double *x, int64_t n, double *out, double *part,
   return hipGetLastError();
 }
 
+// ||B||_F^2: one workgroup per column, then the column sums in order
 hipError_t launch_sumsq_f32(const float *B, int64_t m, int64_t r, int64_t ldb, double *out,
-                            hipStream_t s) {
-  hipLaunchKernelGGL(k_sumsq_f32, dim3(1), dim3(256), 0, s, B, m, r, ldb, out);
+                            double *part, hipStream_t s) {
+  hipLaunchKernelGGL(k_sumsq_cols, dim3((unsigned)r), dim3(256), 0, s, B, m, ldb, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(256), 0, s, part, r, out);
   return hipGetLastError();
 }
 

@@ -25,10 +25,16 @@
 //    4*rho + b is row rho of the b-th 16-row instruction block, so one 16-byte
 //    read gives a lane its operand for four blocks at one k.
 #include <cstdlib>
+#include <type_traits>
 
 #include "gcss_device.h"
 
 namespace gcss {
+
+// MFMA/LDS interleaving strategy of the compiler for the stage loops
+#ifndef GCSS_IGLP
+#define GCSS_IGLP 1
+#endif
 
 constexpr int BK = 16;   // k values per stage of the FP64 kernel
 constexpr int MP = 132;  // MN-major LDS pitch in floats (128 rows + pad)
@@ -61,19 +67,30 @@ __device__ __forceinline__ void mma_stage_k(const float *Xs, int xrow0, const fl
         acc[rb][nb] = mfma4(xa[rb].w, yb[nb].w, acc[rb][nb]);
       }
   }
+  __builtin_amdgcn_iglp_opt(GCSS_IGLP);
 }
 
 // MN-major: a wave's 64 x 64 block at tile rows xr0.., columns yc0..;
 // acc[rb][nb] row rho <-> tile row xr0 + 4*rho + rb, column c <-> yc0 + 4*c + nb.
+// The operands of step s + 1 are read from LDS before the 16 instructions of
+// step s are issued (the compiler's MFMA/LDS interleaving strategy keeps that
+// order), so the LDS latency overlaps matrix work instead of stalling the
+// pipe between steps.
 template <int BKT>
 __device__ __forceinline__ void mma_stage_mn(const float *Xs, int xr0, const float *Ys, int yc0,
                                              int lane, f32x4 (&acc)[4][4]) {
   const int r = lane & 15, g = lane >> 4;
+  constexpr int NS = BKT / 4;
+  float4 xb = *(const float4 *)(Xs + g * MP + xr0 + 4 * r);
+  float4 yb = *(const float4 *)(Ys + g * MP + yc0 + 4 * r);
 #pragma unroll
-  for (int s = 0; s < BKT / 4; ++s) {
-    const int k = 4 * s + g;
-    const float4 x = *(const float4 *)(Xs + k * MP + xr0 + 4 * r);
-    const float4 y = *(const float4 *)(Ys + k * MP + yc0 + 4 * r);
+  for (int s = 0; s < NS; ++s) {
+    const float4 x = xb, y = yb;
+    if (s + 1 < NS) {
+      const int k = 4 * (s + 1) + g;
+      xb = *(const float4 *)(Xs + k * MP + xr0 + 4 * r);
+      yb = *(const float4 *)(Ys + k * MP + yc0 + 4 * r);
+    }
     const float xv[4] = {x.x, x.y, x.z, x.w};
     const float yv[4] = {y.x, y.y, y.z, y.w};
 #pragma unroll
@@ -81,6 +98,7 @@ __device__ __forceinline__ void mma_stage_mn(const float *Xs, int xr0, const flo
 #pragma unroll
       for (int nb = 0; nb < 4; ++nb) acc[rb][nb] = mfma4(xv[rb], yv[nb], acc[rb][nb]);
   }
+  __builtin_amdgcn_iglp_opt(GCSS_IGLP);
 }
 
 template <int DT>
@@ -142,7 +160,7 @@ __device__ __forceinline__ float4 load4(const void *base, int64_t off) {
 // RT = 64*RB; the column results are accumulated across chunks.  With TRI,
 // X = C is weighted as T/2 (zero left of the diagonal, so the k loop starts
 // at r0; one half on it) and the sum is doubled.
-template <int DT, int RB, int NB, int BKT, bool TRI>
+template <int DT, int RB, int NB, int BKT, bool TRI, bool DB>
 __global__ __launch_bounds__(256) void k_init(const float *__restrict__ X, int64_t ldx,
                                               int64_t R, AView A, double *__restrict__ f0,
                                               double *__restrict__ g0,
@@ -155,8 +173,9 @@ __global__ __launch_bounds__(256) void k_init(const float *__restrict__ X, int64
   constexpr int YCH = NT * YCC;            // A chunks per stage
   constexpr int YPT = (YCH + 255) / 256;   // A chunks per thread per stage
   static_assert(RT % BKT == 0 && YCC >= 1 && YCC <= 16, "tile shape");
-  __shared__ __align__(16) float Xs[RT * KP];
-  __shared__ __align__(16) float Ys[NT * KP];
+  constexpr int NBUF = DB ? 2 : 1;
+  __shared__ __align__(16) float Xsb[NBUF][RT * KP];
+  __shared__ __align__(16) float Ysb[NBUF][NT * KP];
   __shared__ double red[4][NT];
   __shared__ double gs[NT];
 
@@ -226,7 +245,9 @@ __global__ __launch_bounds__(256) void k_init(const float *__restrict__ X, int64
           yr[u] = make_uint4(0u, 0u, 0u, 0u);
       }
     };
-    auto sstore = [&](int64_t k0) {
+    auto sstore = [&](int64_t k0, int bsel) {
+      float *Xs = Xsb[bsel];
+      float *Ys = Ysb[bsel];
 #pragma unroll
       for (int u = 0; u < XPT; ++u) {
         const int q = tid + 256 * u;
@@ -256,12 +277,27 @@ __global__ __launch_bounds__(256) void k_init(const float *__restrict__ X, int64
 
     const int64_t ks0 = TRI ? r0 / BKT : 0;
     gload(ks0 * BKT);
-    for (int64_t ks = ks0; ks < ksteps; ++ks) {
+    if constexpr (DB) {
+      __syncthreads();  // the previous row chunk's last stage is done with both buffers
+      sstore(ks0 * BKT, 0);
       __syncthreads();
-      sstore(ks * BKT);
-      __syncthreads();
-      if (ks + 1 < ksteps) gload((ks + 1) * BKT);
-      mma_stage_k<RB, NB, BKT>(Xs, wave * 16 * RB, Ys, 0, lane, acc);
+      int cur = 0;
+      for (int64_t ks = ks0; ks < ksteps; ++ks) {
+        const bool more = ks + 1 < ksteps;
+        if (more) gload((ks + 1) * BKT);
+        mma_stage_k<RB, NB, BKT>(Xsb[cur], wave * 16 * RB, Ysb[cur], 0, lane, acc);
+        if (more) sstore((ks + 1) * BKT, cur ^ 1);
+        __syncthreads();
+        cur ^= 1;
+      }
+    } else {
+      for (int64_t ks = ks0; ks < ksteps; ++ks) {
+        __syncthreads();
+        sstore(ks * BKT, 0);
+        __syncthreads();
+        if (ks + 1 < ksteps) gload((ks + 1) * BKT);
+        mma_stage_k<RB, NB, BKT>(Xsb[0], wave * 16 * RB, Ysb[0], 0, lane, acc);
+      }
     }
 
     // epilogue of this row chunk, one 16-row block at a time (bounded registers)
@@ -319,6 +355,230 @@ __global__ __launch_bounds__(256) void k_init(const float *__restrict__ X, int64
     const int64_t j = j0 + tid;
     if (j < n) {
       const double fv = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
+      const double sc = col_scale(A, j);
+      const double f = (TRI ? 2.0 : 1.0) * sc * sc * fv, g = sc * sc * gs[tid];
+      f0[j] = f;
+      g0[j] = g;
+      mask0[j] = (g > 0.0 && isfinite(g) && isfinite(f)) ? 0 : 2;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Initial scores with 256 x 256 workgroup tiles (rows of X x columns of A),
+// 8 waves of 128 x 64 (8 x 4 instruction blocks, two waves per SIMD),
+// k-major LDS stages of 16 k values, two buffers.  Same arithmetic as k_init:
+// per row chunk of 256 rows the product is reduced into per-column sums
+// (sum of squares, or the dot with A for TRI), and g_i comes from the A
+// tiles of the first chunk.
+constexpr int kI2Threads = 512;
+
+template <int DT, bool TRI>
+__global__ __launch_bounds__(kI2Threads, 1) void k_init256(const float *__restrict__ X,
+                                                          int64_t ldx, int64_t R, AView A,
+                                                          double *__restrict__ f0,
+                                                          double *__restrict__ g0,
+                                                          uint8_t *__restrict__ mask0) {
+  constexpr int BKT = 16, KP = BKT + 4, RT = 256, NT = 256;
+  constexpr int ES = EInfo<DT>::esize, EPC = EInfo<DT>::epc;
+  constexpr int XQ = BKT / 4;                                  // float4 per X row per stage
+  constexpr int XPT = RT * XQ / kI2Threads;                    // 2
+  constexpr int YCC = BKT * ES / 16;                           // 16-byte chunks per column
+  constexpr int YCH = NT * YCC;                                // chunks per stage
+  constexpr int YPT = (YCH + kI2Threads - 1) / kI2Threads;     // chunks per thread
+  __shared__ __align__(16) float Xsb[2][RT * KP];
+  __shared__ __align__(16) float Ysb[2][NT * KP];
+  __shared__ double red[2][NT];
+  __shared__ double gs[NT];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave >> 2) * 128, wc = (wave & 3) * 64;
+  const int64_t m = A.m, n = A.n;
+  const int64_t j0 = (int64_t)blockIdx.x * NT;
+  const char *abase = (const char *)A.a;
+  const int64_t colb = A.lda * ES;
+
+  double gacc[YPT];
+#pragma unroll
+  for (int u = 0; u < YPT; ++u) gacc[u] = 0.0;
+  double colacc[4] = {0.0, 0.0, 0.0, 0.0};
+
+  const int64_t nchunks = (R + RT - 1) / RT;
+  const int64_t ksteps = (m + BKT - 1) / BKT;
+  for (int64_t rc = 0; rc < nchunks; ++rc) {
+    const int64_t r0 = rc * RT;
+    f32x4 acc[8][4];
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    float4 xr[XPT];
+    uint4 yr[YPT];
+    const bool rtail = r0 + RT > R;
+    auto gload = [&](int64_t k0) {
+      const bool ktail = k0 + BKT > m;
+      const bool diag = TRI && k0 < r0 + RT;
+#pragma unroll
+      for (int u = 0; u < XPT; ++u) {
+        const int q = tid + kI2Threads * u;
+        const int row = q / XQ, kq = (q % XQ) * 4;
+        const int64_t gr = r0 + row, gk = k0 + kq;
+        const int64_t grc = gr < R ? gr : R - 1, gkc = gk < m ? gk : 0;
+        float4 v = *(const float4 *)(X + grc * ldx + gkc);
+        if (rtail || ktail) {
+          const bool rok = gr < R;
+          v.x = (rok && gk < m) ? v.x : 0.f;
+          v.y = (rok && gk + 1 < m) ? v.y : 0.f;
+          v.z = (rok && gk + 2 < m) ? v.z : 0.f;
+          v.w = (rok && gk + 3 < m) ? v.w : 0.f;
+        }
+        if (diag) {
+          const int d = (int)(gk - gr);
+          v.x *= d > 0 ? 1.f : (d == 0 ? 0.5f : 0.f);
+          v.y *= d + 1 > 0 ? 1.f : (d + 1 == 0 ? 0.5f : 0.f);
+          v.z *= d + 2 > 0 ? 1.f : (d + 2 == 0 ? 0.5f : 0.f);
+          v.w *= d + 3 > 0 ? 1.f : (d + 3 == 0 ? 0.5f : 0.f);
+        }
+        xr[u] = v;
+      }
+#pragma unroll
+      for (int u = 0; u < YPT; ++u) {
+        const int q = tid + kI2Threads * u;
+        const int col = q / YCC, ch = q % YCC;
+        const int64_t gk = k0 + ch * EPC;
+        if (q < YCH && j0 + col < n && gk < m)
+          yr[u] = *(const uint4 *)(abase + (j0 + col) * colb + gk * ES);
+        else
+          yr[u] = make_uint4(0u, 0u, 0u, 0u);
+      }
+    };
+    auto sstore = [&](int64_t k0, int bsel) {
+      float *Xs = Xsb[bsel];
+      float *Ys = Ysb[bsel];
+#pragma unroll
+      for (int u = 0; u < XPT; ++u) {
+        const int q = tid + kI2Threads * u;
+        const int row = q / XQ, kq = (q % XQ) * 4;
+        *(float4 *)(Xs + row * KP + kq) = xr[u];
+      }
+#pragma unroll
+      for (int u = 0; u < YPT; ++u) {
+        const int q = tid + kI2Threads * u;
+        if (q >= YCH) continue;
+        const int col = q / YCC, ch = q % YCC;
+        float v[EPC];
+        decode16<DT>(yr[u], v);
+        const int64_t gk = k0 + ch * EPC;
+#pragma unroll
+        for (int e = 0; e < EPC; ++e)
+          if (gk + e >= m) v[e] = 0.f;
+        if (rc == 0) {
+#pragma unroll
+          for (int e = 0; e < EPC; ++e) gacc[u] = fma((double)v[e], (double)v[e], gacc[u]);
+        }
+#pragma unroll
+        for (int e = 0; e < EPC; e += 4)
+          *(float4 *)(Ys + col * KP + ch * EPC + e) = make_float4(v[e], v[e + 1], v[e + 2], v[e + 3]);
+      }
+    };
+
+    const int64_t ks0 = TRI ? r0 / BKT : 0;
+    gload(ks0 * BKT);
+    __syncthreads();  // the previous chunk's last stage is done with both buffers
+    sstore(ks0 * BKT, 0);
+    __syncthreads();
+    int cur = 0;
+    for (int64_t ks = ks0; ks < ksteps; ++ks) {
+      const bool more = ks + 1 < ksteps;
+      if (more) gload((ks + 1) * BKT);
+      {
+        const float *Xs = Xsb[cur];
+        const float *Ys = Ysb[cur];
+        const int r = lane & 15, g = lane >> 4;
+#pragma unroll
+        for (int kk = 0; kk < BKT / 16; ++kk) {
+          const int kq = 16 * kk + 4 * g;
+          float4 yb[4];
+#pragma unroll
+          for (int nb = 0; nb < 4; ++nb) yb[nb] = *(const float4 *)(Ys + (wc + 16 * nb + r) * KP + kq);
+          // row fragments in two halves of four (fewer operand registers live)
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            float4 xa[4];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) xa[b] = *(const float4 *)(Xs + (wr + 16 * (4 * h + b) + r) * KP + kq);
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+              for (int nb = 0; nb < 4; ++nb) {
+                f32x4 &c = acc[4 * h + b][nb];
+                c = mfma4(xa[b].x, yb[nb].x, c);
+                c = mfma4(xa[b].y, yb[nb].y, c);
+                c = mfma4(xa[b].z, yb[nb].z, c);
+                c = mfma4(xa[b].w, yb[nb].w, c);
+              }
+          }
+        }
+      }
+      if (more) sstore((ks + 1) * BKT, cur ^ 1);
+      __syncthreads();
+      cur ^= 1;
+    }
+
+    // epilogue of this row chunk, one 16-row block at a time (bounded registers)
+#pragma unroll
+    for (int rb = 0; rb < 8; ++rb) {
+      const int64_t i = r0 + wr + 16 * rb + 4 * (lane >> 4);
+      if constexpr (TRI) {
+        const int64_t ic = i < m ? i : 0;
+        const float w0 = i < m ? 1.f : 0.f, w1 = i + 1 < m ? 1.f : 0.f;
+        const float w2 = i + 2 < m ? 1.f : 0.f, w3 = i + 3 < m ? 1.f : 0.f;
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) {
+          const int64_t j = j0 + wc + 16 * nb + (lane & 15);
+          const float wj = j < n ? 1.f : 0.f;
+          const float4 a = load4<DT>(A.a, (j < n ? j : 0) * A.lda + ic);
+          const float p = acc[rb][nb][0] * (a.x * w0) + acc[rb][nb][1] * (a.y * w1) +
+                          acc[rb][nb][2] * (a.z * w2) + acc[rb][nb][3] * (a.w * w3);
+          colacc[nb] += (double)(p * wj);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      } else {
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) {
+          double sq = 0.0;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) sq += (double)acc[rb][nb][v] * (double)acc[rb][nb][v];
+          colacc[nb] += sq;
+        }
+      }
+    }
+  }
+
+  // columns: sum over the 4 lane groups, then over the 2 row-waves (fixed order)
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) {
+    double s = colacc[nb];
+    s += __shfl_xor(s, 16, 64);
+    s += __shfl_xor(s, 32, 64);
+    if (lane < 16) red[wave >> 2][wc + 16 * nb + lane] = s;
+  }
+  // g: sum over the YCC threads of a column
+#pragma unroll
+  for (int u = 0; u < YPT; ++u) {
+    const int q = tid + kI2Threads * u;
+    double gsum = gacc[u];
+    if constexpr (YCC >= 2) gsum += __shfl_xor(gsum, 1, 64);
+    if constexpr (YCC >= 4) gsum += __shfl_xor(gsum, 2, 64);
+    if constexpr (YCC >= 8) gsum += __shfl_xor(gsum, 4, 64);
+    if (q < YCH && q % YCC == 0) gs[q / YCC] = gsum;
+  }
+  __syncthreads();
+  if (tid < NT) {
+    const int64_t j = j0 + tid;
+    if (j < n) {
+      const double fv = red[0][tid] + red[1][tid];
       const double sc = col_scale(A, j);
       const double f = (TRI ? 2.0 : 1.0) * sc * sc * fv, g = sc * sc * gs[tid];
       f0[j] = f;
@@ -399,11 +659,14 @@ __device__ __forceinline__ void store_block_mn(float *P, int64_t ldp, int64_t i0
 }
 
 // 128 x 128 upper tiles of C = A A^T, 4 waves in a 2 x 2 arrangement of 64 x 64.
-template <int DT, int BKT>
+// DB: two LDS buffers, one barrier per stage (the next stage's global loads
+// are in flight while this stage multiplies, then land in the other buffer).
+template <int DT, int BKT, bool DB>
 __global__ __launch_bounds__(256) void k_gram(AView A, float *__restrict__ P, int64_t ldp,
                                               int ntile, int64_t kchunk) {
-  __shared__ __align__(16) float Xs[BKT * MP];
-  __shared__ __align__(16) float Ys[BKT * MP];
+  constexpr int NBUF = DB ? 2 : 1;
+  __shared__ __align__(16) float Xs[NBUF][BKT * MP];
+  __shared__ __align__(16) float Ys[NBUF][BKT * MP];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t m = A.m, n = A.n;
   // tile id -> (bi, bj), bi <= bj
@@ -428,18 +691,257 @@ __global__ __launch_bounds__(256) void k_gram(AView A, float *__restrict__ P, in
     xt.load(A, i0, kb, ke, tid);
     yt.load(A, j0, kb, ke, tid);
   }
-  for (int64_t k0 = kb; k0 < ke; k0 += BKT) {
-    __syncthreads();
-    xt.store(Xs, A, i0, tid);
-    yt.store(Ys, A, j0, tid);
-    __syncthreads();
-    if (k0 + BKT < ke) {
-      xt.load(A, i0, k0 + BKT, ke, tid);
-      yt.load(A, j0, k0 + BKT, ke, tid);
+  if constexpr (DB) {
+    if (kb < ke) {
+      xt.store(Xs[0], A, i0, tid);
+      yt.store(Ys[0], A, j0, tid);
     }
-    mma_stage_mn<BKT>(Xs, wr, Ys, wc, lane, acc);
+    __syncthreads();
+    int cur = 0;
+    for (int64_t k0 = kb; k0 < ke; k0 += BKT) {
+      const bool more = k0 + BKT < ke;
+      if (more) {
+        xt.load(A, i0, k0 + BKT, ke, tid);
+        yt.load(A, j0, k0 + BKT, ke, tid);
+      }
+      mma_stage_mn<BKT>(Xs[cur], wr, Ys[cur], wc, lane, acc);
+      if (more) {
+        xt.store(Xs[cur ^ 1], A, i0, tid);
+        yt.store(Ys[cur ^ 1], A, j0, tid);
+      }
+      __syncthreads();
+      cur ^= 1;
+    }
+  } else {
+    for (int64_t k0 = kb; k0 < ke; k0 += BKT) {
+      __syncthreads();
+      xt.store(Xs[0], A, i0, tid);
+      yt.store(Ys[0], A, j0, tid);
+      __syncthreads();
+      if (k0 + BKT < ke) {
+        xt.load(A, i0, k0 + BKT, ke, tid);
+        yt.load(A, j0, k0 + BKT, ke, tid);
+      }
+      mma_stage_mn<BKT>(Xs[0], wr, Ys[0], wc, lane, acc);
+    }
   }
   store_block_mn(Pout, ldp, i0 + wr, j0 + wc, m, m, lane, acc);
+}
+
+// ---------------------------------------------------------------------------
+// Large-tile MN-major product P = X Y^T over a k range, 256 x 256 per
+// workgroup: 8 waves (2 along the rows x 4 along the columns) of 128 x 64,
+// 8 x 4 instruction blocks each, two waves per SIMD.  X is always A (rows
+// i0.., columns of A as k); Y is A (Gram) or Omega (projection, row-major
+// n x r).  Per 4-k step a lane reads 3 x 16 B of operands and issues 32
+// MFMAs.  Tile row of block rb, instruction row rho: 4*rho + rb (rb < 4) or
+// 64 + 4*rho + (rb - 4) within the wave's 128 rows; column of block nb,
+// instruction column c: 4*c + nb within the wave's 64 columns.
+constexpr int MP2 = 260;  // LDS pitch (256 rows + pad) of the large tiles
+constexpr int kG2Threads = 512;
+
+template <int DT, int BKT>
+struct MnTile256 {
+  static constexpr int EPC = EInfo<DT>::epc, ES = EInfo<DT>::esize;
+  static constexpr int CPK = 256 / EPC;  // 16-byte chunks per k
+  static constexpr int CH = BKT * CPK;   // chunks per stage
+  static constexpr int PT = (CH + kG2Threads - 1) / kG2Threads;
+  uint4 raw[PT];
+  float sc[PT];
+
+  __device__ __forceinline__ void load(const AView &A, int64_t i0, int64_t k0, int64_t kend,
+                                       int tid) {
+    const char *abase = (const char *)A.a;
+#pragma unroll
+    for (int u = 0; u < PT; ++u) {
+      const int q = tid + kG2Threads * u;
+      const int kk = q / CPK, ii = (q % CPK) * EPC;
+      const bool ok = q < CH && (k0 + kk) < kend && (i0 + ii) < A.m;
+      raw[u] = ok ? *(const uint4 *)(abase + ((k0 + kk) * A.lda + i0 + ii) * ES)
+                  : make_uint4(0u, 0u, 0u, 0u);
+      if constexpr (DT == DT_FP8) sc[u] = ok ? A.scale[k0 + kk] : 0.f;
+    }
+  }
+  __device__ __forceinline__ void store(float *Ts, const AView &A, int64_t i0, int tid) const {
+#pragma unroll
+    for (int u = 0; u < PT; ++u) {
+      const int q = tid + kG2Threads * u;
+      if (q >= CH) continue;
+      const int kk = q / CPK, ii = (q % CPK) * EPC;
+      float v[EPC];
+      decode16<DT>(raw[u], v);
+#pragma unroll
+      for (int e = 0; e < EPC; ++e) {
+        if constexpr (DT == DT_FP8) v[e] *= sc[u];
+        if (i0 + ii + e >= A.m) v[e] = 0.f;
+      }
+#pragma unroll
+      for (int e = 0; e < EPC; e += 4)
+        *(float4 *)(Ts + kk * MP2 + ii + e) = make_float4(v[e], v[e + 1], v[e + 2], v[e + 3]);
+    }
+  }
+};
+
+// Omega rows k0.. (row-major n x r), columns j0..j0+255, into Ts[k * MP2 + j].
+template <int BKT>
+struct OmTile256 {
+  static constexpr int PT = (BKT * 64 + kG2Threads - 1) / kG2Threads;  // float4 per thread
+  float4 v[PT];
+  __device__ __forceinline__ void load(const float *Om, int64_t r, int64_t j0, int64_t k0,
+                                       int64_t kend, int tid) {
+    const bool vec4 = (r % 4) == 0;
+#pragma unroll
+    for (int u = 0; u < PT; ++u) {
+      const int q = tid + kG2Threads * u;
+      const int kk = q >> 6, jj = (q & 63) * 4;
+      const int64_t gk = k0 + kk, gj = j0 + jj;
+      float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (kk < BKT && gk < kend && gj < r) {
+        const float *src = Om + gk * r + gj;
+        if (vec4) {
+          x = *(const float4 *)src;
+        } else {
+          x.x = src[0];
+          if (gj + 1 < r) x.y = src[1];
+          if (gj + 2 < r) x.z = src[2];
+          if (gj + 3 < r) x.w = src[3];
+        }
+      }
+      v[u] = x;
+    }
+  }
+  __device__ __forceinline__ void store(float *Ts, int tid) const {
+#pragma unroll
+    for (int u = 0; u < PT; ++u) {
+      const int q = tid + kG2Threads * u;
+      const int kk = q >> 6, jj = (q & 63) * 4;
+      if (kk < BKT) *(float4 *)(Ts + kk * MP2 + jj) = v[u];
+    }
+  }
+};
+
+template <int BKT>
+__device__ __forceinline__ void mma_stage_mn256(const float *Xs, int xr0, const float *Ys, int yc0,
+                                                int lane, f32x4 (&acc)[8][4]) {
+  const int r = lane & 15, g = lane >> 4;
+  constexpr int NS = BKT / 4;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int k = 4 * s + g;
+    const float4 x0 = *(const float4 *)(Xs + k * MP2 + xr0 + 4 * r);
+    const float4 x1 = *(const float4 *)(Xs + k * MP2 + xr0 + 64 + 4 * r);
+    const float4 y0 = *(const float4 *)(Ys + k * MP2 + yc0 + 4 * r);
+    const float xv[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+    const float yv[4] = {y0.x, y0.y, y0.z, y0.w};
+#pragma unroll
+    for (int rb = 0; rb < 8; ++rb)
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) acc[rb][nb] = mfma4(xv[rb], yv[nb], acc[rb][nb]);
+  }
+  __builtin_amdgcn_iglp_opt(GCSS_IGLP);
+}
+
+// Store a wave's 128 x 64 block (rows i0.. contiguous in P, columns j0..
+// with stride ldp), rows < mrow and columns < ncol; one column block at a
+// time so few accumulators are copied out at once.
+__device__ __forceinline__ void store_block_mn256(float *P, int64_t ldp, int64_t i0, int64_t j0,
+                                                  int64_t mrow, int64_t ncol, int lane,
+                                                  const f32x4 (&acc)[8][4]) {
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) {
+    const int64_t j = j0 + 4 * (lane & 15) + nb;
+    if (j < ncol) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t i = i0 + 64 * h + 16 * (lane >> 4) + 4 * v;
+          const float4 val = make_float4(acc[4 * h + 0][nb][v], acc[4 * h + 1][nb][v],
+                                         acc[4 * h + 2][nb][v], acc[4 * h + 3][nb][v]);
+          float *dst = P + j * ldp + i;
+          if (i + 3 < mrow) {
+            *(float4 *)dst = val;
+          } else {
+            if (i < mrow) dst[0] = val.x;
+            if (i + 1 < mrow) dst[1] = val.y;
+            if (i + 2 < mrow) dst[2] = val.z;
+          }
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// PROJ = false: upper 256-tiles of C = A A^T; true: tiles of B = A Omega.
+template <int DT, int BKT, bool PROJ>
+__global__ __launch_bounds__(kG2Threads, 1) void k_gemm256(AView A, const float *__restrict__ Om,
+                                                           int64_t r, float *__restrict__ P,
+                                                           int64_t ldp, int ntm, int ntile,
+                                                           int64_t kchunk) {
+  __shared__ __align__(16) float Xs[2][BKT * MP2];
+  __shared__ __align__(16) float Ys[2][BKT * MP2];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t m = A.m, n = A.n;
+  const int64_t tile = blockIdx.x % ntile, split = blockIdx.x / ntile;
+  int64_t i0, j0;
+  if constexpr (PROJ) {
+    i0 = (tile % ntm) * 256;
+    j0 = (tile / ntm) * 256;
+  } else {
+    int64_t bj = 0;
+    while ((bj + 1) * (bj + 2) / 2 <= tile) ++bj;
+    i0 = (tile - bj * (bj + 1) / 2) * 256;
+    j0 = bj * 256;
+  }
+  const int64_t ncol = PROJ ? r : m;
+  const int64_t kb = split * kchunk;
+  const int64_t ke = (kb + kchunk) < n ? (kb + kchunk) : n;
+  float *Pout = P + split * ldp * ncol;
+
+  f32x4 acc[8][4];
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  MnTile256<DT, BKT> xt;
+  typename std::conditional<PROJ, OmTile256<BKT>, MnTile256<DT, BKT>>::type yt;
+  auto yload = [&](int64_t k0) {
+    if constexpr (PROJ)
+      yt.load(Om, r, j0, k0, ke, tid);
+    else
+      yt.load(A, j0, k0, ke, tid);
+  };
+  auto ystore = [&](float *Ts) {
+    if constexpr (PROJ)
+      yt.store(Ts, tid);
+    else
+      yt.store(Ts, A, j0, tid);
+  };
+  const int wr = (wave >> 2) * 128, wc = (wave & 3) * 64;
+  if (kb < ke) {
+    xt.load(A, i0, kb, ke, tid);
+    yload(kb);
+    xt.store(Xs[0], A, i0, tid);
+    ystore(Ys[0]);
+  }
+  __syncthreads();
+  int cur = 0;
+  for (int64_t k0 = kb; k0 < ke; k0 += BKT) {
+    const bool more = k0 + BKT < ke;
+    if (more) {
+      xt.load(A, i0, k0 + BKT, ke, tid);
+      yload(k0 + BKT);
+    }
+    mma_stage_mn256<BKT>(Xs[cur], wr, Ys[cur], wc, lane, acc);
+    if (more) {
+      xt.store(Xs[cur ^ 1], A, i0, tid);
+      ystore(Ys[cur ^ 1]);
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+  store_block_mn256(Pout, ldp, i0 + wr, j0 + wc, m, ncol, lane, acc);
 }
 
 // C[i,j] = sum_s P_s[min, max] (upper tiles only were computed; exact symmetry)
@@ -456,13 +958,14 @@ __global__ void k_gram_reduce(const float *__restrict__ P, int64_t ldp, int64_t 
 
 // B = A Omega: left operand A (MN-major), right operand Omega[k][j]
 // (row-major n x r, MN-major as stored).
-template <int DT, int BKT>
+template <int DT, int BKT, bool DB>
 __global__ __launch_bounds__(256) void k_project(AView A, const float *__restrict__ Om,
                                                  int64_t r, float *__restrict__ P, int64_t ldp,
                                                  int ntm, int ntn, int64_t kchunk) {
   constexpr int YPT = BKT * 32 / 256;  // Omega float4 per thread per stage
-  __shared__ __align__(16) float Xs[BKT * MP];
-  __shared__ __align__(16) float Ys[BKT * MP];
+  constexpr int NBUF = DB ? 2 : 1;
+  __shared__ __align__(16) float Xs[NBUF][BKT * MP];
+  __shared__ __align__(16) float Ys[NBUF][BKT * MP];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t n = A.n;
   const int ntile = ntm * ntn;
@@ -502,12 +1005,12 @@ __global__ __launch_bounds__(256) void k_project(AView A, const float *__restric
       yv[u] = v;
     }
   };
-  auto ystore = [&]() {
+  auto ystore = [&](float *Yb) {
 #pragma unroll
     for (int u = 0; u < YPT; ++u) {
       const int q = tid + 256 * u;
       const int kk = q >> 5, jj = (q & 31) * 4;
-      *(float4 *)(Ys + kk * MP + jj) = yv[u];
+      *(float4 *)(Yb + kk * MP + jj) = yv[u];
     }
   };
   const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
@@ -515,16 +1018,39 @@ __global__ __launch_bounds__(256) void k_project(AView A, const float *__restric
     xt.load(A, i0, kb, ke, tid);
     yload(kb);
   }
-  for (int64_t k0 = kb; k0 < ke; k0 += BKT) {
-    __syncthreads();
-    xt.store(Xs, A, i0, tid);
-    ystore();
-    __syncthreads();
-    if (k0 + BKT < ke) {
-      xt.load(A, i0, k0 + BKT, ke, tid);
-      yload(k0 + BKT);
+  if constexpr (DB) {
+    if (kb < ke) {
+      xt.store(Xs[0], A, i0, tid);
+      ystore(Ys[0]);
     }
-    mma_stage_mn<BKT>(Xs, wr, Ys, wc, lane, acc);
+    __syncthreads();
+    int cur = 0;
+    for (int64_t k0 = kb; k0 < ke; k0 += BKT) {
+      const bool more = k0 + BKT < ke;
+      if (more) {
+        xt.load(A, i0, k0 + BKT, ke, tid);
+        yload(k0 + BKT);
+      }
+      mma_stage_mn<BKT>(Xs[cur], wr, Ys[cur], wc, lane, acc);
+      if (more) {
+        xt.store(Xs[cur ^ 1], A, i0, tid);
+        ystore(Ys[cur ^ 1]);
+      }
+      __syncthreads();
+      cur ^= 1;
+    }
+  } else {
+    for (int64_t k0 = kb; k0 < ke; k0 += BKT) {
+      __syncthreads();
+      xt.store(Xs[0], A, i0, tid);
+      ystore(Ys[0]);
+      __syncthreads();
+      if (k0 + BKT < ke) {
+        xt.load(A, i0, k0 + BKT, ke, tid);
+        yload(k0 + BKT);
+      }
+      mma_stage_mn<BKT>(Xs[0], wr, Ys[0], wc, lane, acc);
+    }
   }
   store_block_mn(Pout, ldp, i0 + wr, j0 + wc, A.m, r, lane, acc);
 }
@@ -732,17 +1258,23 @@ hipError_t launch_obj_from_quad(const double *F0, const double *quad, const DevS
 }
 
 // ---------------------------------------------------------------------------
-// k values per LDS stage of the FP32 contractions (measured best: 16 for the
-// triangular Gram init, which is register-bound at 32; 32 elsewhere); the
-// environment variable GCSS_MFMA_BK=16 or 32 forces one depth everywhere.
-static int mfma_bk(bool tri) {
-  static const int forced = [] {
+// k values per LDS stage of the FP32 contractions: 16 (measured best for
+// every kernel with double-buffered stages and operand reads issued one step
+// ahead); the environment variable GCSS_MFMA_BK=32 selects the deeper stage.
+static int mfma_bk(bool /*tri*/) {
+  static const int bk = [] {
     const char *e = std::getenv("GCSS_MFMA_BK");
-    const int v = e ? std::atoi(e) : 0;
-    return (v == 16 || v == 32) ? v : 0;
+    return (e && std::atoi(e) == 32) ? 32 : 16;
   }();
-  if (forced) return forced;
-  return tri ? 16 : 32;
+  return bk;
+}
+// Double-buffered LDS stages (default); GCSS_MFMA_DB=0 selects one buffer.
+static bool mfma_db() {
+  static const bool db = [] {
+    const char *e = std::getenv("GCSS_MFMA_DB");
+    return !(e && std::atoi(e) == 0);
+  }();
+  return db;
 }
 constexpr int KC_ALIGN = 32;  // split-K chunks are multiples of every stage depth
 
@@ -750,9 +1282,18 @@ template <int DT, int RB, int BKT, bool TRI>
 static hipError_t init_t(const float *X, int64_t ldx, int64_t R, const AView &A, double *f0,
                          double *g0, uint8_t *mask0, hipStream_t s) {
   constexpr int NB = 4;
+  // two buffers only where they fit the 160 KiB of LDS
+  constexpr bool kFitsDB = 2 * (64 * RB + 16 * NB) * (BKT + 4) * 4 + 8 * 1024 <= 160 * 1024;
   const unsigned grid = (unsigned)((A.n + 16 * NB - 1) / (16 * NB));
-  hipLaunchKernelGGL((k_init<DT, RB, NB, BKT, TRI>), dim3(grid), dim3(256), 0, s, X, ldx, R, A,
-                     f0, g0, mask0);
+  if constexpr (kFitsDB) {
+    if (mfma_db()) {
+      hipLaunchKernelGGL((k_init<DT, RB, NB, BKT, TRI, true>), dim3(grid), dim3(256), 0, s, X,
+                         ldx, R, A, f0, g0, mask0);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((k_init<DT, RB, NB, BKT, TRI, false>), dim3(grid), dim3(256), 0, s, X, ldx,
+                     R, A, f0, g0, mask0);
   return hipGetLastError();
 }
 
@@ -769,6 +1310,21 @@ static hipError_t init_bk(const float *X, int64_t ldx, int64_t R, const AView &A
 template <int DT>
 static hipError_t init_dt(const float *X, int64_t ldx, int64_t R, const AView &A, double *f0,
                           double *g0, uint8_t *mask0, bool gram, hipStream_t s) {
+  // large tiles once the row dimension fills them (GCSS_MFMA_INIT256=0: off)
+  static const bool big_ok = [] {
+    const char *e = std::getenv("GCSS_MFMA_INIT256");
+    return !(e && std::atoi(e) == 0);
+  }();
+  if (big_ok && R >= 192 && A.n >= 1024) {
+    const unsigned grid = (unsigned)((A.n + 255) / 256);
+    if (gram)
+      hipLaunchKernelGGL((k_init256<DT, true>), dim3(grid), dim3(kI2Threads), 0, s, X, ldx, R, A,
+                         f0, g0, mask0);
+    else
+      hipLaunchKernelGGL((k_init256<DT, false>), dim3(grid), dim3(kI2Threads), 0, s, X, ldx, R, A,
+                         f0, g0, mask0);
+    return hipGetLastError();
+  }
   if (mfma_bk(gram) == 16) return init_bk<DT, 16>(X, ldx, R, A, f0, g0, mask0, gram, s);
   return init_bk<DT, 32>(X, ldx, R, A, f0, g0, mask0, gram, s);
 }
@@ -793,51 +1349,110 @@ hipError_t launch_init_gram(const float *C, int64_t ldc, const AView &A, double 
   return hipErrorInvalidValue;
 }
 
-static void gram_plan(int64_t m, int64_t n, int num_cu, int *ntile, int *nsplit,
-                      int64_t *kchunk) {
-  const int64_t nt = (m + 127) / 128;
-  const int64_t T = nt * (nt + 1) / 2;
-  int64_t sp = (8LL * num_cu + T - 1) / T;
-  if (sp > 8) sp = 8;
-  if (sp < 1) sp = 1;
+// Tiling of a split-K product: tile edge (128, or 256 for the large-tile
+// kernel), tile grid, k splits.  The split count fills whole rounds of
+// resident workgroups as far as the partial-sum budget allows.  Plans depend
+// only on the shapes (a fixed CU count), so the workspace sized from a plan
+// always matches the launch.
+struct KPlan {
+  int tile, ntm, ntile, nsplit;
+  int64_t kchunk;
+};
+constexpr int kPlanSlots256 = 256;  // resident large-tile workgroups (one per CU)
+
+static int64_t pick_split(int64_t T, int64_t n, int64_t cap_sp, int64_t slots) {
+  int64_t max_sp = (n + 255) / 256;  // every split at least 256 columns
+  if (max_sp > cap_sp) max_sp = cap_sp;
+  if (max_sp < 1) max_sp = 1;
+  int64_t best = 1;
+  double best_eff = -1.0;
+  for (int64_t sp = 1; sp <= max_sp; ++sp) {
+    const int64_t w = T * sp, rounds = (w + slots - 1) / slots;
+    const double eff = (double)w / (double)(rounds * slots);
+    if (eff > best_eff + 1e-9) {
+      best_eff = eff;
+      best = sp;
+    }
+  }
+  return best;
+}
+
+static void finish_plan(int64_t n, int64_t sp, KPlan *p) {
   int64_t kc = (n + sp - 1) / sp;
   kc = ((kc + KC_ALIGN - 1) / KC_ALIGN) * KC_ALIGN;
-  sp = (n + kc - 1) / kc;
-  *ntile = (int)T;
-  *nsplit = (int)sp;
-  *kchunk = kc;
+  p->kchunk = kc;
+  p->nsplit = (int)((n + kc - 1) / kc);
+}
+
+static KPlan gram_plan(int64_t m, int64_t n) {
+  KPlan p{};
+  const int64_t ldp = ((m + 3) / 4) * 4;
+  if (m >= 256) {
+    p.tile = 256;
+    const int64_t nt = (m + 255) / 256;
+    const int64_t T = nt * (nt + 1) / 2;
+    int64_t cap = (int64_t)(512LL << 20) / (ldp * m * (int64_t)sizeof(float));
+    if (cap < 1) cap = 1;
+    p.ntm = (int)nt;
+    p.ntile = (int)T;
+    finish_plan(n, pick_split(T, n, cap, kPlanSlots256), &p);
+  } else {
+    p.tile = 128;
+    const int64_t nt = (m + 127) / 128;
+    const int64_t T = nt * (nt + 1) / 2;
+    int64_t sp = (8LL * 256 + T - 1) / T;
+    if (sp > 8) sp = 8;
+    if (sp < 1) sp = 1;
+    p.ntm = (int)nt;
+    p.ntile = (int)T;
+    finish_plan(n, sp, &p);
+  }
+  return p;
 }
 
 size_t gram_scratch_bytes(int64_t m, int64_t n, int64_t ldc, int num_cu) {
-  int nt, sp;
-  int64_t kc;
-  gram_plan(m, n, num_cu, &nt, &sp, &kc);
   (void)ldc;
+  (void)num_cu;
+  const KPlan p = gram_plan(m, n);
   const int64_t ldp = ((m + 3) / 4) * 4;
-  return (size_t)sp * ldp * m * sizeof(float);
+  return (size_t)p.nsplit * ldp * m * sizeof(float);
 }
 
 hipError_t launch_gram(const AView &A, float *C, int64_t ldc, void *scratch, int num_cu,
                        hipStream_t s) {
-  int nt, sp;
-  int64_t kc;
-  gram_plan(A.m, A.n, num_cu, &nt, &sp, &kc);
+  (void)num_cu;
+  const KPlan pl = gram_plan(A.m, A.n);
   const int64_t ldp = ((A.m + 3) / 4) * 4;
   float *P = (float *)scratch;
+  const int nt = pl.ntile, sp = pl.nsplit;
+  const int64_t kc = pl.kchunk;
   const dim3 grid((unsigned)(nt * sp));
-  const bool bk16 = mfma_bk(false) == 16;
-  switch (A.dtype) {
+  if (pl.tile == 256) {
+    switch (A.dtype) {
+      case DT_F32: hipLaunchKernelGGL((k_gemm256<DT_F32, 16, false>), grid, dim3(kG2Threads), 0, s, A, nullptr, 0, P, ldp, pl.ntm, nt, kc); break;
+      case DT_BF16: hipLaunchKernelGGL((k_gemm256<DT_BF16, 16, false>), grid, dim3(kG2Threads), 0, s, A, nullptr, 0, P, ldp, pl.ntm, nt, kc); break;
+      case DT_FP8: hipLaunchKernelGGL((k_gemm256<DT_FP8, 16, false>), grid, dim3(kG2Threads), 0, s, A, nullptr, 0, P, ldp, pl.ntm, nt, kc); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    const bool bk16 = mfma_bk(false) == 16, db = mfma_db();
+    switch (A.dtype) {
 #define GCSS_GRAM(DTV)                                                                        \
-  if (bk16)                                                                                   \
-    hipLaunchKernelGGL((k_gram<DTV, 16>), grid, dim3(256), 0, s, A, P, ldp, nt, kc);          \
+  if (bk16 && db)                                                                             \
+    hipLaunchKernelGGL((k_gram<DTV, 16, true>), grid, dim3(256), 0, s, A, P, ldp, nt, kc);    \
+  else if (bk16)                                                                              \
+    hipLaunchKernelGGL((k_gram<DTV, 16, false>), grid, dim3(256), 0, s, A, P, ldp, nt, kc);   \
+  else if (db)                                                                                \
+    hipLaunchKernelGGL((k_gram<DTV, 32, true>), grid, dim3(256), 0, s, A, P, ldp, nt, kc);    \
   else                                                                                        \
-    hipLaunchKernelGGL((k_gram<DTV, 32>), grid, dim3(256), 0, s, A, P, ldp, nt, kc);          \
+    hipLaunchKernelGGL((k_gram<DTV, 32, false>), grid, dim3(256), 0, s, A, P, ldp, nt, kc);   \
   break;
-    case DT_F32: GCSS_GRAM(DT_F32)
-    case DT_BF16: GCSS_GRAM(DT_BF16)
-    case DT_FP8: GCSS_GRAM(DT_FP8)
+      case DT_F32: GCSS_GRAM(DT_F32)
+      case DT_BF16: GCSS_GRAM(DT_BF16)
+      case DT_FP8: GCSS_GRAM(DT_FP8)
 #undef GCSS_GRAM
-    default: return hipErrorInvalidValue;
+      default: return hipErrorInvalidValue;
+    }
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -847,59 +1462,81 @@ hipError_t launch_gram(const AView &A, float *C, int64_t ldc, void *scratch, int
   return hipGetLastError();
 }
 
-static void proj_plan(int64_t m, int64_t n, int64_t r, int num_cu, int *ntm, int *ntn,
-                      int *nsplit, int64_t *kchunk) {
-  const int64_t tm = (m + 127) / 128, tn = (r + 127) / 128;
-  const int64_t T = tm * tn;
-  int64_t sp = (8LL * num_cu + T - 1) / T;
+static KPlan proj_plan(int64_t m, int64_t n, int64_t r) {
+  KPlan p{};
   // keep the partials within ~128 MiB and every split at least 256 columns long
   const int64_t ldp = ((m + 3) / 4) * 4;
   const int64_t per = ldp * r * (int64_t)sizeof(float);
   int64_t cap = (int64_t)(128LL << 20) / (per > 0 ? per : 1);
   if (cap < 1) cap = 1;
-  if (sp > cap) sp = cap;
-  if (sp > (n + 255) / 256) sp = (n + 255) / 256;
-  if (sp < 1) sp = 1;
-  int64_t kc = (n + sp - 1) / sp;
-  kc = ((kc + KC_ALIGN - 1) / KC_ALIGN) * KC_ALIGN;
-  sp = (n + kc - 1) / kc;
-  *ntm = (int)tm;
-  *ntn = (int)tn;
-  *nsplit = (int)sp;
-  *kchunk = kc;
+  if (m >= 256 && r >= 192) {
+    p.tile = 256;
+    const int64_t tm = (m + 255) / 256, tn = (r + 255) / 256;
+    p.ntm = (int)tm;
+    p.ntile = (int)(tm * tn);
+    finish_plan(n, pick_split(tm * tn, n, cap, kPlanSlots256), &p);
+  } else {
+    p.tile = 128;
+    const int64_t tm = (m + 127) / 128, tn = (r + 127) / 128;
+    const int64_t T = tm * tn;
+    int64_t sp = (8LL * 256 + T - 1) / T;
+    if (sp > cap) sp = cap;
+    if (sp > (n + 255) / 256) sp = (n + 255) / 256;
+    if (sp < 1) sp = 1;
+    p.ntm = (int)tm;
+    p.ntile = (int)T;
+    finish_plan(n, sp, &p);
+  }
+  return p;
 }
 
 size_t proj_scratch_bytes(int64_t m, int64_t n, int64_t r, int num_cu) {
-  int tm, tn, sp;
-  int64_t kc;
-  proj_plan(m, n, r, num_cu, &tm, &tn, &sp, &kc);
+  (void)num_cu;
+  const KPlan p = proj_plan(m, n, r);
   const int64_t ldp = ((m + 3) / 4) * 4;
-  return (size_t)sp * ldp * r * sizeof(float);
+  return (size_t)p.nsplit * ldp * r * sizeof(float);
 }
 
 hipError_t launch_project(const AView &A, const float *omega, int64_t r, float *B,
                           int64_t ldb, void *scratch, int num_cu, hipStream_t s) {
-  int tm, tn, sp;
-  int64_t kc;
-  proj_plan(A.m, A.n, r, num_cu, &tm, &tn, &sp, &kc);
+  (void)num_cu;
+  const KPlan pl = proj_plan(A.m, A.n, r);
   const int64_t ldp = ((A.m + 3) / 4) * 4;
   float *P = (float *)scratch;
-  const dim3 grid((unsigned)(tm * tn * sp));
-  const bool bk16 = mfma_bk(false) == 16;
-  switch (A.dtype) {
+  const int tm = pl.ntm, nt = pl.ntile, sp = pl.nsplit;
+  const int tn = nt / tm;
+  const int64_t kc = pl.kchunk;
+  const dim3 grid((unsigned)(nt * sp));
+  if (pl.tile == 256) {
+    switch (A.dtype) {
+      case DT_F32: hipLaunchKernelGGL((k_gemm256<DT_F32, 16, true>), grid, dim3(kG2Threads), 0, s, A, omega, r, P, ldp, tm, nt, kc); break;
+      case DT_BF16: hipLaunchKernelGGL((k_gemm256<DT_BF16, 16, true>), grid, dim3(kG2Threads), 0, s, A, omega, r, P, ldp, tm, nt, kc); break;
+      case DT_FP8: hipLaunchKernelGGL((k_gemm256<DT_FP8, 16, true>), grid, dim3(kG2Threads), 0, s, A, omega, r, P, ldp, tm, nt, kc); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    const bool bk16 = mfma_bk(false) == 16, db = mfma_db();
+    switch (A.dtype) {
 #define GCSS_PROJ(DTV)                                                                        \
-  if (bk16)                                                                                   \
-    hipLaunchKernelGGL((k_project<DTV, 16>), grid, dim3(256), 0, s, A, omega, r, P, ldp, tm,  \
-                       tn, kc);                                                               \
+  if (bk16 && db)                                                                             \
+    hipLaunchKernelGGL((k_project<DTV, 16, true>), grid, dim3(256), 0, s, A, omega, r, P, ldp, \
+                       tm, tn, kc);                                                           \
+  else if (bk16)                                                                              \
+    hipLaunchKernelGGL((k_project<DTV, 16, false>), grid, dim3(256), 0, s, A, omega, r, P,     \
+                       ldp, tm, tn, kc);                                                      \
+  else if (db)                                                                                \
+    hipLaunchKernelGGL((k_project<DTV, 32, true>), grid, dim3(256), 0, s, A, omega, r, P, ldp, \
+                       tm, tn, kc);                                                           \
   else                                                                                        \
-    hipLaunchKernelGGL((k_project<DTV, 32>), grid, dim3(256), 0, s, A, omega, r, P, ldp, tm,  \
-                       tn, kc);                                                               \
+    hipLaunchKernelGGL((k_project<DTV, 32, false>), grid, dim3(256), 0, s, A, omega, r, P,     \
+                       ldp, tm, tn, kc);                                                      \
   break;
-    case DT_F32: GCSS_PROJ(DT_F32)
-    case DT_BF16: GCSS_PROJ(DT_BF16)
-    case DT_FP8: GCSS_PROJ(DT_FP8)
+      case DT_F32: GCSS_PROJ(DT_F32)
+      case DT_BF16: GCSS_PROJ(DT_BF16)
+      case DT_FP8: GCSS_PROJ(DT_FP8)
 #undef GCSS_PROJ
-    default: return hipErrorInvalidValue;
+      default: return hipErrorInvalidValue;
+    }
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

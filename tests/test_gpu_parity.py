@@ -53,6 +53,46 @@ def test_projection_matches_oracle_dots(gpu, m, n, r):
     torch.cuda.synchronize()
 
 
+def _quantized(gpu, A32, m, dt):
+    """Stored codes on the GPU and the values they decode to (oracle decoder)."""
+    Adev, sc = gpu.quantize_tensor(dev(A32), m, dt)
+    if dt == "bf16":
+        Aval = oracle.decode_columns(oracle.quantize_bf16(A32, m), m, "bf16").T
+    else:
+        codes, scl = oracle.quantize_fp8(A32, m)
+        Aval = oracle.decode_columns(codes, m, "fp8", scl).T
+    return Adev, sc, Aval
+
+
+@pytest.mark.parametrize("m,n,r,dt", [(300, 1000, 256, "bf16"), (520, 700, 200, "fp8")])
+def test_projection_quantized_storage(gpu, m, n, r, dt):
+    """B = A_hat Omega from BF16 / FP8 codes (large-tile path), entry by entry."""
+    A32 = colstore32(synth.gauss_lowrank_dense(m, n, 10, 0.1, seed=m + 1))
+    Om = synth.omega_gauss(n, r, seed=r + 1)
+    Adev, sc, Aval = _quantized(gpu, A32, m, dt)
+    s = gpu.Selector(Adev, m, k_max=4, r_max=r, scales=sc)
+    B = s.project_target(dev(Om)).cpu().numpy()[:, :m].T.astype(np.float64)
+    Bref = Aval @ Om.astype(np.float64)
+    scale = np.sqrt(np.sum(Aval ** 2, axis=1))[:, None] * np.sqrt(np.sum(Om.astype(np.float64) ** 2, axis=0))[None, :]
+    assert np.max(np.abs(B - Bref) / scale) < 1e-6
+
+
+@pytest.mark.parametrize("m,n,dt", [(300, 500, "bf16"), (257, 400, "fp8")])
+def test_gram_quantized_storage(gpu, m, n, dt):
+    """C = A_hat A_hat^T from BF16 / FP8 codes (large-tile path), exactly symmetric."""
+    A32 = colstore32(synth.gauss_lowrank_dense(m, n, 12, 0.05, seed=m + 2))
+    Adev, sc, Aval = _quantized(gpu, A32, m, dt)
+    s = gpu.Selector(Adev, m, k_max=4, self_target=True, scales=sc)
+    s.set_target(None)
+    C = s.read(gpu.STATE_GRAM, m * m, np.float32).reshape(m, m).astype(np.float64)
+    Cr = Aval @ Aval.T
+    assert np.array_equal(C, C.T)
+    np.testing.assert_allclose(C, Cr, rtol=0, atol=1e-5 * np.abs(Cr).max())
+    f = s.read(gpu.STATE_F0, n, np.float64)
+    fr, _ = oracle.init_scores(f64cs(Aval), m)
+    np.testing.assert_allclose(f, fr, rtol=1e-4)
+
+
 # ---------------------------------------------------------------- a1 ---------
 @pytest.mark.parametrize("m,n,r,dt", [(37, 70, 3, "f32"), (500, 1000, 64, "f32"), (1000, 300, 256, "f32"),
                                       (300, 500, 300, "f32"), (600, 400, 130, "bf16"), (700, 333, 40, "fp8")])
