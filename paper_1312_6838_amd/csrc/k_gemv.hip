@@ -10,6 +10,8 @@
 //   z  = w - Q (Q^T w)    -- rows final: records the pick and F_t
 // "cols" kernels are the dot products Q^T v, B^T q; "rows" kernels are the
 // updates v - Q c, B c.  All reductions have a fixed order.
+#include <type_traits>
+
 #include "gcss_device.h"
 
 namespace gcss {
@@ -90,6 +92,115 @@ __global__ __launch_bounds__(256) void k_cols(const MT *__restrict__ M, int64_t 
     __syncthreads();
     u2 = ((red[0] + red[1]) + red[2]) + red[3];
   } else {  // CF_GRAM_U2: the last coefficient is q . (C q)
+    u2 = out[t];
+  }
+  if (threadIdx.x == 0) {
+    st->u2 = u2;
+    st->cnt[1] = 0;
+  }
+}
+
+// Column dots, several outputs per workgroup: the vector stays in registers
+// (PAIRS row pairs per thread, m <= 512 * PAIRS) and the workgroup streams
+// CPW columns of M against it, so the vector is read once per CPW outputs
+// instead of once per output.  Per-column partials meet in one fixed-order
+// reduction at the end.
+template <typename MT, int CPW, int PAIRS>
+__global__ __launch_bounds__(256) void k_cols_multi(const MT *__restrict__ M, int64_t ldm,
+                                                    int64_t m, int ns_from_t, int ns_add,
+                                                    const double *__restrict__ vec, AView A,
+                                                    double *__restrict__ out, int final_mode,
+                                                    StepBufs sb, BatchStride bs, ArgStride as) {
+  __shared__ double red[4][CPW];
+  __shared__ double red4[4];
+  {
+    const int b = blockIdx.y;
+    sb = shift_bufs(sb, bs, b);
+    M += b * as.m;
+    if (vec) vec += b * as.vec;
+    out += b * as.out;
+  }
+  DevState *st = sb.st;
+  if (st->done || st->skip) return;
+  const int t = st->t;
+  const int ns = (ns_from_t ? t : 0) + ns_add;
+  const int s0 = blockIdx.x * CPW;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (s0 < ns) {
+    double2 v[PAIRS];
+#pragma unroll
+    for (int i = 0; i < PAIRS; ++i) {
+      const int64_t j = 2 * threadIdx.x + 512 * i;
+      v[i] = j + 1 < m ? *(const double2 *)(vec + j)
+                       : make_double2(j < m ? vec[j] : 0.0, 0.0);
+    }
+    // every load is issued before any is used: clamped (valid) columns and
+    // rows, raw element pairs kept until the FMA, no branches around loads
+    typedef typename std::conditional<sizeof(MT) == 8, double2, float2>::type MT2;
+    MT2 xr[CPW][PAIRS];
+    const int64_t jmax = m >= 2 ? ((m - 2) & ~(int64_t)1) : 0;
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      const int sc = (s0 + c) < ns ? (s0 + c) : (ns - 1);
+      const MT *col = M + (int64_t)sc * ldm;
+#pragma unroll
+      for (int i = 0; i < PAIRS; ++i) {
+        const int64_t j = 2 * threadIdx.x + 512 * i;
+        xr[c][i] = *(const MT2 *)(col + (j + 1 < m ? j : jmax));
+      }
+    }
+    double acc[CPW];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+      for (int i = 0; i < PAIRS; ++i) {
+        const int64_t j = 2 * threadIdx.x + 512 * i;
+        if (j + 1 < m) {
+          a0 = fma((double)xr[c][i].x, v[i].x, a0);
+          a1 = fma((double)xr[c][i].y, v[i].y, a1);
+        }
+      }
+      acc[c] = (s0 + c) < ns ? a0 + a1 : 0.0;
+    }
+    if (m & 1) {  // odd m: the last row (its pair is (m - 1, m)), by the thread owning it
+#pragma unroll
+      for (int i = 0; i < PAIRS; ++i) {
+        const int64_t j = 2 * threadIdx.x + 512 * i;
+        if (j == m - 1) {
+#pragma unroll
+          for (int c = 0; c < CPW; ++c)
+            if (s0 + c < ns) acc[c] = fma((double)M[(int64_t)(s0 + c) * ldm + j], v[i].x, acc[c]);
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      const double w = wave_sum(acc[c]);
+      if (lane == 0) red[wave][c] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x < CPW && s0 + (int)threadIdx.x < ns) {
+      const int c = threadIdx.x;
+      out[s0 + c] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+    }
+  }
+  if (final_mode == CF_NONE) return;
+  if (!last_block_arrive(&st->cnt[1])) return;
+  // last workgroup: the outputs of all workgroups are visible after the
+  // fence and barrier of last_block_arrive (fixed-order sum over threads)
+  double u2;
+  if (final_mode == CF_UPS) {
+    double a = 0.0;
+    for (int x = threadIdx.x; x < ns; x += blockDim.x) {
+      const double w = out[x];
+      a = fma(w, w, a);
+    }
+    a = wave_sum(a);
+    if (lane == 0) red4[wave] = a;
+    __syncthreads();
+    u2 = ((red4[0] + red4[1]) + red4[2]) + red4[3];
+  } else {
     u2 = out[t];
   }
   if (threadIdx.x == 0) {
@@ -429,6 +540,31 @@ static hipError_t cols_t(const MT *M, int64_t ldm, int64_t m, int ns_from_t, int
                          int max_ns, int vsrc, const double *vec, const AView &A, double *out,
                          int final_mode, const StepBufs &sb, hipStream_t s, int nprob,
                          BatchStride bs, ArgStride as) {
+  // FP32 matrices with many outputs (B^T q, C q): several outputs per
+  // workgroup (32 element pairs per thread in flight), while keeping at
+  // least 256 workgroups
+  if constexpr (sizeof(MT) == 4) {
+    // (measured: B^T q at m = 8192, r = 512 16.4 -> 12.7 us; with thousands
+    // of outputs, C q, one output per workgroup already streams M at ~5 TB/s)
+    if (vsrc == VEC_F64 && max_ns >= 512 && max_ns < 2048 && m <= 8192) {
+      const int pairs = m <= 2048 ? 4 : (m <= 4096 ? 8 : 16);
+      int cpw = 32 / pairs;
+      while (cpw > 1 && (max_ns + cpw - 1) / cpw < 256) cpw >>= 1;
+      const dim3 grid((unsigned)((max_ns + cpw - 1) / cpw), (unsigned)nprob);
+#define GCSS_CM(CPW, PAIRS)                                                                    \
+  hipLaunchKernelGGL((k_cols_multi<MT, CPW, PAIRS>), grid, dim3(256), 0, s, M, ldm, m,        \
+                     ns_from_t, ns_add, vec, A, out, final_mode, sb, bs, as)
+      if (pairs == 4) {
+        if (cpw >= 8) GCSS_CM(8, 4); else if (cpw == 4) GCSS_CM(4, 4); else if (cpw == 2) GCSS_CM(2, 4); else GCSS_CM(1, 4);
+      } else if (pairs == 8) {
+        if (cpw >= 4) GCSS_CM(4, 8); else if (cpw == 2) GCSS_CM(2, 8); else GCSS_CM(1, 8);
+      } else {
+        if (cpw >= 2) GCSS_CM(2, 16); else GCSS_CM(1, 16);
+      }
+#undef GCSS_CM
+      return hipGetLastError();
+    }
+  }
   const dim3 grid((unsigned)(max_ns > 0 ? max_ns : 1), (unsigned)nprob);
   if (vsrc == VEC_ACOL)
     hipLaunchKernelGGL((k_cols<MT, VEC_ACOL>), grid, dim3(256), 0, s, M, ldm, m, ns_from_t,

@@ -944,16 +944,36 @@ __global__ __launch_bounds__(kG2Threads, 1) void k_gemm256(AView A, const float 
   store_block_mn256(Pout, ldp, i0 + wr, j0 + wc, m, ncol, lane, acc);
 }
 
-// C[i,j] = sum_s P_s[min, max] (upper tiles only were computed; exact symmetry)
-__global__ void k_gram_reduce(const float *__restrict__ P, int64_t ldp, int64_t m, int nsplit,
-                              float *__restrict__ C, int64_t ldc) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= m * m) return;
-  const int64_t j = e / m, i = e % m;
-  const int64_t src = (i <= j) ? (j * ldp + i) : (i * ldp + j);
-  float s = 0.f;
-  for (int x = 0; x < nsplit; ++x) s += P[x * ldp * m + src];
-  C[j * ldc + i] = s;
+// C = sum_s P_s over the upper triangle, mirrored (exact symmetry).  One
+// workgroup per 64 x 64 tile (bi <= bj) of the upper part: partial sums are
+// read along the contiguous rows, the tile is written in place and, through
+// LDS, transposed into the lower part, so every access is coalesced.
+__global__ __launch_bounds__(256) void k_gram_reduce(const float *__restrict__ P, int64_t ldp,
+                                                     int64_t m, int nsplit,
+                                                     float *__restrict__ C, int64_t ldc) {
+  __shared__ float T[64][65];
+  int64_t bj = 0;
+  const int64_t tile = blockIdx.x;
+  while ((bj + 1) * (bj + 2) / 2 <= tile) ++bj;
+  const int64_t bi = tile - bj * (bj + 1) / 2;
+  const int rr = threadIdx.x & 63, c0 = threadIdx.x >> 6;
+  const int64_t i = bi * 64 + rr;
+  for (int x = c0; x < 64; x += 4) {
+    const int64_t j = bj * 64 + x;
+    float v = 0.f;
+    if (i < m && j < m && (bi < bj || i <= j)) {
+      for (int sp = 0; sp < nsplit; ++sp) v += P[(int64_t)sp * ldp * m + j * ldp + i];
+      C[j * ldc + i] = v;
+    }
+    T[rr][x] = v;
+  }
+  __syncthreads();
+  // lower part: C[j][i] = C[i][j] for the tile's (i, j), i < j
+  for (int x = c0; x < 64; x += 4) {
+    const int64_t ic = bi * 64 + x;   // column of the lower element
+    const int64_t jr = bj * 64 + rr;  // its row
+    if (ic < m && jr < m && ic < jr) C[ic * ldc + jr] = T[x][rr];
+  }
 }
 
 // B = A Omega: left operand A (MN-major), right operand Omega[k][j]
@@ -1391,7 +1411,7 @@ static KPlan gram_plan(int64_t m, int64_t n) {
     p.tile = 256;
     const int64_t nt = (m + 255) / 256;
     const int64_t T = nt * (nt + 1) / 2;
-    int64_t cap = (int64_t)(512LL << 20) / (ldp * m * (int64_t)sizeof(float));
+    int64_t cap = (int64_t)(1LL << 30) / (ldp * m * (int64_t)sizeof(float));
     if (cap < 1) cap = 1;
     p.ntm = (int)nt;
     p.ntile = (int)T;
@@ -1456,8 +1476,8 @@ hipError_t launch_gram(const AView &A, float *C, int64_t ldc, void *scratch, int
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int64_t total = A.m * A.m;
-  hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, P,
+  const int64_t nb64 = (A.m + 63) / 64;
+  hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)(nb64 * (nb64 + 1) / 2)), dim3(256), 0, s, P,
                      ldp, A.m, sp, C, ldc);
   return hipGetLastError();
 }

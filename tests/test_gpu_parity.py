@@ -178,12 +178,17 @@ def _prefix_len(a, b):
     return n
 
 
-@pytest.mark.parametrize("case", ["css_500x1000", "gcss_1000x20000_r128", "ragged_333x4097_r7"])
+@pytest.mark.parametrize("case", ["css_500x1000", "gcss_1000x20000_r128", "ragged_333x4097_r7",
+                                  "gcss_odd_601x3000_r512"])
 def test_selection_matches_oracle(gpu, case):
     if case == "css_500x1000":
         m, n, k = 500, 1000, 20
         A = synth.gauss_lowrank_dense(m, n, 50, 0.01, seed=0)
         r = 0
+    elif case == "gcss_odd_601x3000_r512":
+        # odd m with many target columns (several column dots per workgroup)
+        m, n, k, r = 601, 3000, 15, 512
+        A = synth.gauss_lowrank_dense(m, n, 60, 0.05, seed=21)
     elif case == "gcss_1000x20000_r128":
         m, n, k, r = 1000, 20000, 30, 128
         A = synth.spectral_lowrank_dense(m, n, 256, 0.7, 1e-3, seed=1)
