@@ -162,6 +162,37 @@ gcss_status gcss_select_async(gcss_ctx *h, int32_t k, int64_t *d_idx, double *d_
 gcss_status gcss_reconstruction_error(gcss_ctx *h, const int64_t *idx, int32_t k, double *err);
 
 /*
+ * Low-dimensional embedding of every column in the span of the picks
+ * (Section 3, Eq. CSS_LowDim): W = Q^T A, with Q the orthonormal basis of
+ * A_S in pick order.  Row t of W is omega = A^T q_{t+1}, the vector each
+ * step's streaming pass already forms, so the embedding costs one extra
+ * coalesced store of n floats per step (and, after the last pick, one more
+ * pass over A for the last row).
+ * w: device float, row-major k_max x ldw (row t starts at element t*ldw),
+ * ldw >= n; owned by the caller, borrowed by the context until it is
+ * replaced or turned off (w = NULL).  gcss_select and gcss_select_async
+ * write rows 0 .. n_selected-1 (binary32; FP8 columns include their
+ * scale); other rows are left as they were.  Batched selection does not
+ * write it.  Changing the pointer rebuilds gcss_select_async's graph.
+ * Errors: GCSS_ERR_ARG (ldw < n, misaligned w).
+ */
+gcss_status gcss_set_embedding(gcss_ctx *h, float *w, int64_t ldw);
+
+/*
+ * Q-less QR factor of the picks (Section 6): with Pi sorting the picked
+ * columns first, A Pi = Q W Pi, and the first k columns of W Pi form the
+ * upper triangular R (k x k) with A_S = Q R.
+ * w: device, row-major embedding as written by a selection (ldw >= n);
+ * idx: device, k int64 picks in pick order; r: device float, row-major
+ * k x ldr (ldr >= k).  R[s][j] = W[s][idx[j]] for s <= j and 0 below the
+ * diagonal (the entries W keeps there are rounding residue).  A column whose
+ * idx entry is outside [0, n) is written as NaN.  Ordered on stream
+ * (NULL = default stream).  Errors: GCSS_ERR_ARG, GCSS_ERR_DEVICE.
+ */
+gcss_status gcss_qless_r(const float *w, int64_t n, int64_t ldw, const int64_t *idx, int32_t k,
+                         float *r, int64_t ldr, void *stream);
+
+/*
  * Algorithm 4 on one GPU.  The columns of A are split into nblocks
  * consecutive blocks col_off[b] .. col_off[b+1]-1 (host, nblocks+1 entries,
  * col_off[0] = 0, col_off[nblocks] = n, strictly increasing).  Every block

@@ -17,10 +17,10 @@ from ._abi import (  # noqa: F401
     STATE_Q, STATE_Z, WARN_EXHAUSTED, Desc, GcssError, batched_workspace_size, create, destroy,
     last_error, load, make_desc, project_target, quantize, read_state, reconstruction_error,
     select, select_async, select_batched, set_target, version, workspace_size,
-    set_profiling, get_profile,
+    set_profiling, get_profile, set_embedding, qless_r,
 )
 
-__all__ = ["Selector", "quantize_tensor", "load", "version", "GcssError"]
+__all__ = ["Selector", "quantize_tensor", "qless_r_tensor", "load", "version", "GcssError"]
 
 
 def _dtype_code(t):
@@ -113,6 +113,19 @@ class Selector:
         select_async(self.h, int(k), out[0].data_ptr(), out[1].data_ptr(), out[2].data_ptr())
         return out
 
+    def set_embedding(self, W=None):
+        """Have selections write W = Q^T A into W, a (k_max, ldw) float32 cuda
+        tensor (row t = A^T q_{t+1}, ldw >= n); None turns it off."""
+        import torch
+        if W is None:
+            set_embedding(self.h, None, 0)
+        else:
+            if (W.dtype != torch.float32 or not W.is_cuda or W.dim() != 2
+                    or W.stride(1) != 1 or W.shape[1] < self.n):
+                raise ValueError("W must be a float32 cuda tensor (rows, ldw >= n), unit column stride")
+            set_embedding(self.h, W.data_ptr(), int(W.stride(0)))
+        self.W = W
+
     def reconstruction_error(self, idx):
         return reconstruction_error(self.h, idx)
 
@@ -140,6 +153,19 @@ class Selector:
             self.close()
         except Exception:
             pass
+
+
+def qless_r_tensor(W, n, idx, stream=None):
+    """Upper triangular R (k, k) float32 with A_S = Q R, from the embedding W
+    (rows, ldw) and the picks idx (int64 cuda tensor, k entries)."""
+    import torch
+    k = int(idx.numel())
+    if W.stride(1) != 1 or idx.dtype != torch.int64 or not idx.is_contiguous():
+        raise ValueError("W needs unit column stride and idx a contiguous int64 tensor")
+    R = torch.empty(k, k, dtype=torch.float32, device=W.device)
+    qless_r(W.data_ptr(), int(n), int(W.stride(0)), idx.data_ptr(), k, R.data_ptr(), k,
+            _stream_ptr(stream))
+    return R
 
 
 def quantize_tensor(A32, m, dtype, stream=None):

@@ -31,6 +31,7 @@ EXPORTS = [
     "gcss_project_target", "gcss_select", "gcss_select_async", "gcss_reconstruction_error",
     "gcss_select_batched", "gcss_batched_workspace_size", "gcss_quantize", "gcss_read_state",
     "gcss_last_error", "gcss_version", "gcss_set_profiling", "gcss_get_profile",
+    "gcss_set_embedding", "gcss_qless_r",
 ]
 
 
@@ -92,6 +93,10 @@ def load():
     lib.gcss_quantize.restype = st
     lib.gcss_read_state.argtypes = [_vp, _i32, _vp, _sz, _P(_sz)]
     lib.gcss_read_state.restype = st
+    lib.gcss_set_embedding.argtypes = [_vp, _vp, _i64]
+    lib.gcss_set_embedding.restype = st
+    lib.gcss_qless_r.argtypes = [_vp, _i64, _i64, _vp, _i32, _vp, _i64, _vp]
+    lib.gcss_qless_r.restype = st
     lib.gcss_set_profiling.argtypes = [_vp, _i32]
     lib.gcss_set_profiling.restype = st
     lib.gcss_get_profile.argtypes = [_vp, _P(Profile)]
@@ -201,6 +206,15 @@ def read_state(h: int, item: int, nbytes: int) -> bytes:
     got = _sz(0)
     _check(load().gcss_read_state(h, item, buf, nbytes, ctypes.byref(got)))
     return bytes(buf[: got.value])
+
+
+def set_embedding(h: int, w_ptr: int | None, ldw: int) -> None:
+    _check(load().gcss_set_embedding(h, w_ptr, ldw))
+
+
+def qless_r(w_ptr: int, n: int, ldw: int, idx_ptr: int, k: int, r_ptr: int, ldr: int,
+            stream: int = 0) -> None:
+    _check(load().gcss_qless_r(w_ptr, n, ldw, idx_ptr, k, r_ptr, ldr, stream))
 
 
 def set_profiling(h: int, enable: bool) -> None:

@@ -153,6 +153,9 @@ struct gcss_ctx {
   hipGraphExec_t bgraph = nullptr;
   const float *B = nullptr;
   int64_t r = 0, ldb = 0;
+  // caller's embedding W = Q^T A (row-major k_max x ldw), or none
+  float *emb = nullptr;
+  int64_t ldw = 0;
   // last completed selection (host copy), for reuse of its basis
   std::vector<int64_t> last_idx;
   bool basis_valid = false;
@@ -264,7 +267,7 @@ hipError_t enqueue_step(gcss_ctx *h) {
                          h->at<double>(h->L.g0), h->at<uint8_t>(h->L.mask),
                          h->at<ArgPart>(h->L.part), sb.st, h->at<double>(h->L.ap64), 0,
                          ex ? h->at<double>(h->L.qpart) : nullptr,
-                         ex ? h->at<double>(h->L.quad) : nullptr, s)))
+                         ex ? h->at<double>(h->L.quad) : nullptr, h->emb, h->ldw, s)))
     return e;
   if (h->profiling && (e = record(h))) return e;
   return hipSuccess;
@@ -291,7 +294,7 @@ hipError_t enqueue_begin(gcss_ctx *h, int k) {
                        h->at<float>(h->L.z32), h->at<double>(h->L.f), h->at<double>(h->L.g),
                        h->at<double>(h->L.g0), h->at<uint8_t>(h->L.mask),
                        h->at<ArgPart>(h->L.part), sb.st, h->at<double>(h->L.ap64), 1, nullptr,
-                       nullptr, h->stream);
+                       nullptr, nullptr, 0, h->stream);
 }
 
 gcss_status check_ctx(gcss_ctx *h) {
@@ -590,6 +593,28 @@ gcss_status gcss_reconstruction_error(gcss_ctx *h, const int64_t *idx, int32_t k
   }
   HIPCHK(hipMemcpyAsync(err, h->err_dev(), sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  return GCSS_OK;
+}
+
+gcss_status gcss_set_embedding(gcss_ctx *h, float *w, int64_t ldw) {
+  if (check_ctx(h)) return GCSS_ERR_ARG;
+  if (w && ldw < h->d.n) return fail(GCSS_ERR_ARG, "ldw (%lld) < n (%lld)", (long long)ldw, (long long)h->d.n);
+  if (((uintptr_t)w) % 4) return fail(GCSS_ERR_ARG, "w must be 4-byte aligned");
+  if (w != h->emb) drop_graph(h);
+  h->emb = w;
+  h->ldw = w ? ldw : 0;
+  return GCSS_OK;
+}
+
+gcss_status gcss_qless_r(const float *w, int64_t n, int64_t ldw, const int64_t *idx, int32_t k,
+                         float *r, int64_t ldr, void *stream) {
+  if (!w || !idx || !r) return fail(GCSS_ERR_ARG, "null w, idx or r");
+  if (n < 1 || ldw < n) return fail(GCSS_ERR_ARG, "need n >= 1 and ldw >= n");
+  if (k < 1 || ldr < k) return fail(GCSS_ERR_ARG, "need k >= 1 and ldr >= k");
+  if (k > 65535) return fail(GCSS_ERR_UNSUPPORTED, "k = %d exceeds 65535", k);
+  if (((uintptr_t)w) % 4 || ((uintptr_t)r) % 4 || ((uintptr_t)idx) % 8)
+    return fail(GCSS_ERR_ARG, "misaligned w, r or idx");
+  HIPCHK(launch_qless_r(w, n, ldw, idx, k, r, ldr, (hipStream_t)stream));
   return GCSS_OK;
 }
 

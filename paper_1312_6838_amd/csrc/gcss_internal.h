@@ -73,12 +73,13 @@ StreamGeo stream_geometry(int64_t m, int64_t n, int dtype, int num_cu);
 // Sets the grid from the occupancy of the chosen kernel (needs the device).
 hipError_t stream_finalize(StreamGeo &geo, int64_t n, int dtype, int num_cu);
 // qpart/quad non-null: the exact-decrease variant (Gram target), which reads
-// q64 and writes sum_i (A_i . q)^2 to quad[t - 1].
+// q64 and writes sum_i (A_i . q)^2 to quad[t - 1].  emb non-null: row t - 1
+// of the row-major embedding W (leading dimension ldw) receives A_i . q.
 hipError_t launch_stream(const StreamGeo &geo, const AView &A, const float *q32,
                          const double *q64, const float *z32, double *f, double *g,
                          const double *g0, uint8_t *mask, ArgPart *part, DevState *st,
                          double *ap64, int score_only, double *qpart, double *quad,
-                         hipStream_t s);
+                         float *emb, int64_t ldw, hipStream_t s);
 
 // ---- launchers (k_gemv.hip) ----
 // Buffers of one selection problem that the per-step kernels touch.
@@ -201,6 +202,9 @@ hipError_t launch_obj_from_quad(const double *F0, const double *quad, const DevS
 // ---- launchers (k_quant.hip) ----
 hipError_t launch_quantize(const float *a, int64_t m, int64_t n, int64_t lda, int dtype,
                            void *out, int64_t ldo, float *scales, hipStream_t s);
+// ---- launchers (k_embed.hip) ----
+hipError_t launch_qless_r(const float *w, int64_t n, int64_t ldw, const int64_t *idx, int k,
+                          float *r, int64_t ldr, hipStream_t s);
 
 // ---- batched (k_batched.hip) ----
 // One group of consecutive columns inside one block of Algorithm 4.

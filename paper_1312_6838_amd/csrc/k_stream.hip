@@ -100,7 +100,8 @@ __global__ __launch_bounds__(512) void k_stream(AView A, int ucol, const float *
                                                 ArgPart *__restrict__ part, DevState *st,
                                                 double *__restrict__ ap64, int score_only,
                                                 double *__restrict__ qpart,
-                                                double *__restrict__ quad) {
+                                                double *__restrict__ quad,
+                                                float *__restrict__ emb, int64_t ldw) {
   constexpr int EPC = Elem<DT>::epc;
   constexpr int TEAMS = kStreamWaves / W;
   constexpr int U = (8 / NJ) > 0 ? (8 / NJ) : 1;  // columns per load group
@@ -111,11 +112,13 @@ __global__ __launch_bounds__(512) void k_stream(AView A, int ucol, const float *
   __shared__ int64_t bi_s[kStreamWaves];
   __shared__ double qs[kStreamWaves];
 
-  // after the last pick (done) the exact-decrease variant still makes one
-  // pass for that pick's decrease, without scores or a next pick
-  const bool qonly = EX && st->done && st->dec_pending;
+  // after the last pick (done) one more pass runs for that pick's exact
+  // decrease (EX) or its row of the embedding, without scores or a next pick
+  const bool qonly = (EX || emb != nullptr) && st->done && st->dec_pending;
   if (st->done && !qonly) return;
   const bool rescore = score_only || st->skip;
+  // embedding: row t - 1 of W = Q^T A receives omega = A^T q_t
+  float *const wrow = (emb != nullptr && !rescore) ? emb + (int64_t)(st->t - 1) * ldw : nullptr;
   const double u2 = st->u2;
   const double tau = st->tau;
 
@@ -303,6 +306,7 @@ __global__ __launch_bounds__(512) void k_stream(AView A, int ucol, const float *
       fv = fv - 2.0 * ww * y + u2 * ww * ww;
       gv = gv - ww * ww;
       if constexpr (EX) qacc += mine ? ww * ww : 0.0;
+      if (wrow != nullptr && mine) wrow[col] = (float)ww;
     }
     const bool elig = mine && mk == 0 && gv > tau * g0v && isfinite(fv) && isfinite(gv);
     const double scv = fv / gv;
@@ -356,11 +360,17 @@ __global__ __launch_bounds__(512) void k_stream(AView A, int ucol, const float *
         st->dec_pending = 0;
       }
     }
-    if (qonly) {
-      if (threadIdx.x == 0) st->cnt[0] = 0;
-      return;
-    }
   }
+  if (qonly) {
+    if (threadIdx.x == 0) {
+      st->dec_pending = 0;
+      st->cnt[0] = 0;
+    }
+    return;
+  }
+  // a pass with a new basis vector settles its pick (the final pass above
+  // then has nothing left to do)
+  if (!EX && !rescore && threadIdx.x == 0) st->dec_pending = 0;
   // ... and the winner over all workgroups -> next pick
   best = -INFINITY;
   besti = kNoIdx;
@@ -438,7 +448,7 @@ static int pow2_at_least(int64_t x) {
 
 typedef void (*StreamFn)(AView, int, const float *, const double *, const float *, double *,
                          double *, const double *, const uint8_t *, ArgPart *, DevState *, double *,
-                         int, double *, double *);
+                         int, double *, double *, float *, int64_t);
 
 template <int DT, int NJ, int W, bool EX>
 static StreamFn pick_pd(int pd) {
@@ -553,13 +563,13 @@ hipError_t launch_stream(const StreamGeo &geo, const AView &A, const float *q32,
                          const double *q64, const float *z32, double *f, double *g,
                          const double *g0, uint8_t *mask, ArgPart *part, DevState *st,
                          double *ap64, int score_only, double *qpart, double *quad,
-                         hipStream_t s) {
+                         float *emb, int64_t ldw, hipStream_t s) {
   const bool ex = qpart != nullptr;
   StreamFn fn = pick_kernel(A.dtype, geo.nj, geo.w, geo.pd, ex);
   if (!fn) return hipErrorInvalidValue;
   hipLaunchKernelGGL(fn, dim3(ex ? geo.grid_ex : geo.grid), dim3(kStreamThreads), 0, s, A,
                      ex ? geo.ucol_ex : geo.ucol, q32, q64, z32, f, g, g0, mask, part, st, ap64,
-                     score_only, qpart, quad);
+                     score_only, qpart, quad, emb, ldw);
   return hipGetLastError();
 }
 

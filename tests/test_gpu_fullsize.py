@@ -44,6 +44,17 @@ def check_greedy(A, m, idx, B, steps, rng, ncand=32, tol=1e-5):
         assert sc[-1] >= np.max(sc[:-1]) * (1 - tol), (t, sc[-1], np.max(sc[:-1]))
 
 
+def check_embedding(sel, gpu, A, m, W, cols, tol=1e-5):
+    """Sampled columns of W = Q^T A against the GPU basis in FP64."""
+    k = W.shape[0]
+    Q = sel.read(gpu.STATE_Q, m * k, np.float64).reshape(k, m).T
+    Ac = host(A, m, cols).T                                   # m x c
+    ref = Q.T @ Ac
+    got = W[:, cols].double().cpu().numpy()
+    err = np.abs(got - ref) / np.sqrt(np.sum(Ac * Ac, axis=0))[None, :]
+    assert err.max() <= tol, err.max()
+
+
 def common_checks(idx, obj, ns, k):
     assert ns == k
     assert len(set(int(x) for x in idx)) == k
@@ -74,7 +85,16 @@ def test_full_css_4096x65536_k200(gpu):
     assert rel(obj[k], e) <= 1e-5 and rel(err, e) <= 1e-5
     assert rel(obj[k // 2], dense.error(Ah[idx[:k // 2]].T, Bt)) <= 1e-5
     check_greedy(A, m, idx, Bt, [0, k - 1], rng, ncand=24)
-    del A
+    # embedding W = Q^T A written by the same passes: no pick or objective bit
+    # changes; sampled columns against Q^T A_i in FP64; row norms = decreases
+    W = torch.zeros(k, n, dtype=torch.float32, device="cuda")
+    sel.set_embedding(W)
+    i2, o2, _, _ = sel.select(k)
+    assert np.array_equal(i2, idx) and np.array_equal(o2.view(np.int64), obj.view(np.int64))
+    check_embedding(sel, gpu, A, m, W, samp)
+    dec = W.double().pow(2).sum(1).cpu().numpy()
+    np.testing.assert_allclose(dec, obj[:-1] - obj[1:], rtol=1e-4, atol=1e-7 * obj[0])
+    del A, W
     torch.cuda.empty_cache()
 
 
@@ -101,6 +121,13 @@ def test_full_gcss_2048x1048576_r256_k100_fp32_and_bf16(gpu):
     e32 = dense.error(host(A, m, idx).T, B)
     assert rel(obj[k], e32) <= 1e-5 and rel(err, e32) <= 1e-5
     check_greedy(A, m, idx, B, [0, k // 2, k - 1], rng)
+    W = torch.zeros(k, n, dtype=torch.float32, device="cuda")
+    sel.set_embedding(W)
+    i2, o2, _, _ = sel.select(k)
+    assert np.array_equal(i2, idx) and np.array_equal(o2.view(np.int64), obj.view(np.int64))
+    check_embedding(sel, gpu, A, m, W, samp)
+    sel.set_embedding(None)
+    del W
     # BF16 stream of the same data: stored codes bit-exact with the oracle's,
     # selection quality within 1e-3 of the FP32 run on the FP32 data
     A16, _ = gpu.quantize_tensor(A, m, "bf16")
