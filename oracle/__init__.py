@@ -17,6 +17,8 @@ for Large-scale Data Sets"):
 * :func:`init_scores`          initial f, g of Algorithms 1 and 3
 * storage formats: bfloat16 and OCP FP8 E4M3 encode/decode and quantizers
 * :mod:`oracle.brute`          numpy brute force (explicit least squares)
+* :mod:`oracle.embed`          embedding W = Q^T A and the rank-k approximation
+                               in span(A_S) (Section 3)
 """
 from __future__ import annotations
 
