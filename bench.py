@@ -231,6 +231,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--embedding", action="store_true",
+                    help="the timed selections also write the embedding W = Q^T A")
+    ap.add_argument("--rank-k", type=int, default=0, metavar="K",
+                    help="with --embedding: time one rank-K approximation in the span of "
+                         "the picks after the timed steps")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run one device-to-device copy of BYTES bytes (scales the "
                          "HBM traffic counters of a profiling run)")
@@ -271,6 +276,9 @@ def main():
 
     sel = g.Selector(A, m, k_max=k, r_max=r, self_target=self_target, scales=scales)
     state = {}
+    if args.embedding:
+        W = torch.empty(k, n, dtype=torch.float32, device="cuda")
+        sel.set_embedding(W)
 
     def step():
         if self_target:
@@ -316,6 +324,22 @@ def main():
               "selection_loop_ms": round((tc - tb) * 1e3, 3),
               "reconstruction_error_ms": round((td - tc) * 1e3, 3)}
 
+    embedding = None
+    if args.embedding:
+        embedding = {"written": True}
+        if args.rank_k > 0:
+            kk = min(args.rank_k, int(ns))
+            sel.rank_k(int(ns), kk)                      # warm (kernel load)
+            torch.cuda.synchronize()
+            te = time.perf_counter()
+            U, sig, V, err_k = sel.rank_k(int(ns), kk)
+            torch.cuda.synchronize()
+            tf = time.perf_counter()
+            embedding.update({"rank_k": kk, "l": int(ns), "rank_k_ms": round((tf - te) * 1e3, 3),
+                              "sigma_first": float(sig[0]), "sigma_last": float(sig[-1]),
+                              "rank_k_error": float(err_k)})
+            del U, V
+
     # roofline of the fused stream kernel
     src = open(os.path.join(ROOT, "paper_1312_6838_amd", "csrc", "k_stream.hip"), "rb").read()
     src_sha = hashlib.sha256(src).hexdigest()
@@ -337,12 +361,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "m": m, "n": n, "k": k, "lda": lda,
                    "target": "B = A" if self_target else f"B = A Omega, r = {r}",
-                   "a_storage": dtype},
+                   "a_storage": dtype, "embedding": bool(args.embedding)},
         "roofline": roof,
         "loop_only": {"score_updates_per_s": n * k / (prof["loop_ms"] / max(prof["selects"], 1) * 1e-3)
                       if prof["selects"] else None,
                       "loop_ms": round(prof["loop_ms"] / max(prof["selects"], 1), 3)},
         "phases": phases,
+        "embedding": embedding,
         "result": {"n_selected": int(state["ns"]), "objective_first": float(state["obj"][0]),
                    "objective_last": float(state["obj"][state["ns"]]),
                    "reconstruction_error": float(state["err"])},

@@ -193,6 +193,36 @@ gcss_status gcss_qless_r(const float *w, int64_t n, int64_t ldw, const int64_t *
                          float *r, int64_t ldr, void *stream);
 
 /*
+ * Rank-k approximation of A inside the span of the first l picks (Section 3,
+ * the procedure credited to Boutsidis et al.), and the approximate leading
+ * singular triplets of A it gives (Eq. ApproxSVD):
+ *   W = U_W Sigma V_W^T (SVD of the l x n embedding), A_{S,k} = Q W_k,
+ *   u = Q U_W[:, :k]  (m x k),  sigma = Sigma[:k],  v = V_W[:, :k]  (n x k),
+ * so that A_{S,k} = u diag(sigma) v^T is the best rank-k approximation of A
+ * whose columns lie in span(A_S).
+ * Uses the basis Q of the last gcss_select / gcss_select_async on this
+ * context (under the current target) and its embedding w (as written with
+ * gcss_set_embedding; device, row-major, ldw >= n, rows 0..l-1 read).
+ * 1 <= k <= l <= min(picks of that selection, 2048).
+ * Method: G = W W^T with FP64 sums of the binary32 products, eigenvalues and
+ * vectors of G by block Jacobi in FP64 (sigma_j = sqrt(lambda_j)), then
+ * u = Q U_k (FP64) and v = W^T U_k Sigma_k^-1 (binary32; a zero sigma_j
+ * gives a zero column).  Sign: the largest-magnitude entry of each column of
+ * u (the first on ties) is positive; v's column carries the same sign.
+ * u: device double, column-major m x k, ldu >= m, or NULL; v: device float,
+ * column-major n x k, ldv >= n, or NULL; sigma: host, k doubles (descending);
+ * err (host, may be NULL): ||A - A_{S,k}||_F^2 = ||A - Q W||_F^2 + sum of
+ * the l - k smallest lambda, with ||A - Q W||_F^2 the selection's objective
+ * F(S) when B = A, else ||A||_F^2 - ||W||_F^2 (which loses the digits of
+ * ||A||_F^2 that the binary32 W cannot hold).  Uses the workspace's
+ * scratch; synchronizes the stream.
+ * Errors: GCSS_ERR_ARG, GCSS_ERR_STATE (no selection basis),
+ * GCSS_ERR_UNSUPPORTED (l > 2048), GCSS_ERR_DEVICE.
+ */
+gcss_status gcss_rank_k(gcss_ctx *h, const float *w, int64_t ldw, int32_t l, int32_t k, double *u,
+                        int64_t ldu, float *v, int64_t ldv, double *sigma, double *err);
+
+/*
  * Algorithm 4 on one GPU.  The columns of A are split into nblocks
  * consecutive blocks col_off[b] .. col_off[b+1]-1 (host, nblocks+1 entries,
  * col_off[0] = 0, col_off[nblocks] = n, strictly increasing).  Every block

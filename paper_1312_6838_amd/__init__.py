@@ -17,7 +17,7 @@ from ._abi import (  # noqa: F401
     STATE_Q, STATE_Z, WARN_EXHAUSTED, Desc, GcssError, batched_workspace_size, create, destroy,
     last_error, load, make_desc, project_target, quantize, read_state, reconstruction_error,
     select, select_async, select_batched, set_target, version, workspace_size,
-    set_profiling, get_profile, set_embedding, qless_r,
+    set_profiling, get_profile, set_embedding, qless_r, rank_k,
 )
 
 __all__ = ["Selector", "quantize_tensor", "qless_r_tensor", "load", "version", "GcssError"]
@@ -125,6 +125,22 @@ class Selector:
                 raise ValueError("W must be a float32 cuda tensor (rows, ldw >= n), unit column stride")
             set_embedding(self.h, W.data_ptr(), int(W.stride(0)))
         self.W = W
+
+    def rank_k(self, l, k, want_u=True, want_v=True):
+        """Rank-k approximation in the span of the first l picks of the last
+        selection, from the embedding set with set_embedding.  Returns
+        (U (k, m) float64 rows = columns of U_A, sigma (k,), V (k, n) float32
+        rows = columns of V_A, err)."""
+        import torch
+        if getattr(self, "W", None) is None:
+            raise ValueError("no embedding set")
+        dev = self.A.device
+        U = torch.empty(int(k), self.m, dtype=torch.float64, device=dev) if want_u else None
+        V = torch.empty(int(k), self.n, dtype=torch.float32, device=dev) if want_v else None
+        sigma, err = rank_k(self.h, self.W.data_ptr(), int(self.W.stride(0)), int(l), int(k),
+                            U.data_ptr() if U is not None else None, self.m,
+                            V.data_ptr() if V is not None else None, self.n)
+        return U, sigma, V, err
 
     def reconstruction_error(self, idx):
         return reconstruction_error(self.h, idx)

@@ -31,7 +31,7 @@ EXPORTS = [
     "gcss_project_target", "gcss_select", "gcss_select_async", "gcss_reconstruction_error",
     "gcss_select_batched", "gcss_batched_workspace_size", "gcss_quantize", "gcss_read_state",
     "gcss_last_error", "gcss_version", "gcss_set_profiling", "gcss_get_profile",
-    "gcss_set_embedding", "gcss_qless_r",
+    "gcss_set_embedding", "gcss_qless_r", "gcss_rank_k",
 ]
 
 
@@ -97,6 +97,8 @@ def load():
     lib.gcss_set_embedding.restype = st
     lib.gcss_qless_r.argtypes = [_vp, _i64, _i64, _vp, _i32, _vp, _i64, _vp]
     lib.gcss_qless_r.restype = st
+    lib.gcss_rank_k.argtypes = [_vp, _vp, _i64, _i32, _i32, _vp, _i64, _vp, _i64, _vp, _vp]
+    lib.gcss_rank_k.restype = st
     lib.gcss_set_profiling.argtypes = [_vp, _i32]
     lib.gcss_set_profiling.restype = st
     lib.gcss_get_profile.argtypes = [_vp, _P(Profile)]
@@ -215,6 +217,16 @@ def set_embedding(h: int, w_ptr: int | None, ldw: int) -> None:
 def qless_r(w_ptr: int, n: int, ldw: int, idx_ptr: int, k: int, r_ptr: int, ldr: int,
             stream: int = 0) -> None:
     _check(load().gcss_qless_r(w_ptr, n, ldw, idx_ptr, k, r_ptr, ldr, stream))
+
+
+def rank_k(h: int, w_ptr: int, ldw: int, l: int, k: int, u_ptr: int | None, ldu: int,
+           v_ptr: int | None, ldv: int):
+    """-> (sigma float64[k], err)"""
+    sigma = np.zeros(k, dtype=np.float64)
+    err = ctypes.c_double(0.0)
+    _check(load().gcss_rank_k(h, w_ptr, ldw, l, k, u_ptr, ldu, v_ptr, ldv, sigma.ctypes.data,
+                              ctypes.byref(err)))
+    return sigma, err.value
 
 
 def set_profiling(h: int, enable: bool) -> None:

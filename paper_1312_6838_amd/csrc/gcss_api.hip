@@ -109,6 +109,7 @@ bool make_layout(const gcss_desc *d, int num_cu, Layout *L) {
                            up((size_t)L->ldq * k * 4, 256) + 3 * up((size_t)(k + 8) * 8, 256);
   s = std::max(s, err_bytes);
   if (d->self_target) s = std::max(s, qta_scratch_bytes(n, (int)k));
+  if (k <= kRankMaxL) s = std::max(s, rank_plan((int)k, n).bytes);
   L->scratch_bytes = s;
   L->scratch = c.take<uint8_t>(s);
   L->total = up(c.off, 256);
@@ -156,6 +157,9 @@ struct gcss_ctx {
   // caller's embedding W = Q^T A (row-major k_max x ldw), or none
   float *emb = nullptr;
   int64_t ldw = 0;
+  // Q (and obj) hold the basis (objective) of the last gcss_select(_async)
+  // under the current target
+  bool q_from_select = false;
   // last completed selection (host copy), for reuse of its basis
   std::vector<int64_t> last_idx;
   bool basis_valid = false;
@@ -397,6 +401,7 @@ void gcss_destroy(gcss_ctx *h) {
 
 gcss_status gcss_set_target(gcss_ctx *h, const float *b, int64_t r, int64_t ldb) {
   if (check_ctx(h)) return GCSS_ERR_ARG;
+  h->q_from_select = false;
   const int64_t m = h->d.m;
   if (b == nullptr && r == 0) {
     if (!h->d.self_target) return fail(GCSS_ERR_STATE, "self target not reserved at creation");
@@ -494,6 +499,7 @@ gcss_status gcss_select(gcss_ctx *h, int32_t k, int64_t *idx, double *objective,
   if (n_selected) *n_selected = t;
   h->last_idx.assign(hidx.begin(), hidx.begin() + t);
   h->basis_valid = true;
+  h->q_from_select = true;
   return hs.exhausted ? GCSS_WARN_EXHAUSTED : GCSS_OK;
 }
 
@@ -538,6 +544,7 @@ gcss_status gcss_select_async(gcss_ctx *h, int32_t k, int64_t *d_idx, double *d_
   }
   HIPCHK(hipGraphLaunch(h->graph, h->stream));
   h->basis_valid = false;  // the host does not know the picks
+  h->q_from_select = true;
   return GCSS_OK;
 }
 
@@ -575,6 +582,7 @@ gcss_status gcss_reconstruction_error(gcss_ctx *h, const int64_t *idx, int32_t k
     HIPCHK(hipStreamSynchronize(s));
     kb = hs.t;
     h->basis_valid = false;
+    h->q_from_select = false;
   }
   const double *Q = h->at<double>(h->L.Q);
   char *scr = h->at<char>(h->L.scratch);
@@ -603,6 +611,58 @@ gcss_status gcss_set_embedding(gcss_ctx *h, float *w, int64_t ldw) {
   if (w != h->emb) drop_graph(h);
   h->emb = w;
   h->ldw = w ? ldw : 0;
+  return GCSS_OK;
+}
+
+gcss_status gcss_rank_k(gcss_ctx *h, const float *w, int64_t ldw, int32_t l, int32_t k, double *u,
+                        int64_t ldu, float *v, int64_t ldv, double *sigma, double *err) {
+  if (check_ctx(h)) return GCSS_ERR_ARG;
+  const int64_t m = h->d.m, n = h->d.n;
+  if (!w || !sigma) return fail(GCSS_ERR_ARG, "null w or sigma");
+  if (ldw < n) return fail(GCSS_ERR_ARG, "ldw (%lld) < n (%lld)", (long long)ldw, (long long)n);
+  if (k < 1 || k > l) return fail(GCSS_ERR_ARG, "need 1 <= k <= l (k = %d, l = %d)", k, l);
+  if (u && ldu < m) return fail(GCSS_ERR_ARG, "ldu < m");
+  if (v && ldv < n) return fail(GCSS_ERR_ARG, "ldv < n");
+  if (((uintptr_t)w) % 4 || ((uintptr_t)u) % 8 || ((uintptr_t)v) % 4)
+    return fail(GCSS_ERR_ARG, "misaligned w, u or v");
+  if (!h->q_from_select) return fail(GCSS_ERR_STATE, "no selection basis (select first, under the current target)");
+  if (l > kRankMaxL || l > h->d.k_max) return fail(GCSS_ERR_UNSUPPORTED, "l = %d exceeds %d", l, kRankMaxL);
+  const RankPlan P = rank_plan(l, n);
+  if (P.bytes > h->L.scratch_bytes) return fail(GCSS_ERR_UNSUPPORTED, "workspace too small for l = %d", l);
+  hipStream_t s = h->stream;
+  DevState hs;
+  HIPCHK(hipMemcpyAsync(&hs, h->at<DevState>(h->L.st), sizeof hs, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (l < 1 || l > hs.t) return fail(GCSS_ERR_ARG, "l = %d outside [1, picks of the last selection = %d]", l, hs.t);
+  char *scr = h->at<char>(h->L.scratch);
+  HIPCHK(launch_wgram(P, w, ldw, l, n, scr, s));
+  int conv = 1;
+  std::vector<int> flags((size_t)(P.L / 64));
+  for (int sweep = 0; sweep < 30 && conv; ++sweep) {
+    HIPCHK(launch_jacobi_sweep(P, scr, s));
+    HIPCHK(hipMemcpyAsync(flags.data(), scr + P.flag, sizeof(int) * flags.size(), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    conv = 0;
+    for (int f : flags) conv |= f;
+  }
+  if (conv) return fail(GCSS_ERR_DEVICE, "eigen-decomposition did not converge in 30 sweeps");
+  HIPCHK(launch_rank_outputs(P, scr, l, k, h->at<double>(h->L.Q), h->L.ldq, m, u, ldu, w, ldw, n, v,
+                             ldv, s));
+  // ||A - Q W||^2: the selection's own objective for B = A, else
+  // ||A||^2 - ||W||_F^2 (sum of g0 minus the sum of the eigenvalues)
+  double sums[3] = {0.0, 0.0, 0.0};  // [unused floor, sum of eigenvalues, tail]
+  double fres = 0.0;
+  if (h->target == 2) {
+    HIPCHK(hipMemcpyAsync(&fres, h->at<double>(h->L.obj) + l, sizeof(double), hipMemcpyDeviceToHost, s));
+  } else {
+    HIPCHK(launch_sum_f64(h->at<double>(h->L.g0), n, h->err_dev(), h->at<double>(h->L.npart), 1024, s));
+    HIPCHK(hipMemcpyAsync(&fres, h->err_dev(), sizeof(double), hipMemcpyDeviceToHost, s));
+  }
+  HIPCHK(hipMemcpyAsync(sums, scr + P.aux, sizeof sums, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(sigma, scr + P.sigma, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (h->target != 2) fres -= sums[1];
+  if (err) *err = fres + sums[2];
   return GCSS_OK;
 }
 
@@ -761,6 +821,7 @@ gcss_status gcss_select_batched(gcss_ctx *h, int32_t nblocks, const int64_t *col
     if (col_off[b + 1] <= col_off[b]) return fail(GCSS_ERR_ARG, "col_off must be strictly increasing");
   BLayout B;
   if (!make_blayout(&h->d, h->L, nblocks, k_block, k_merge, &B)) return fail(GCSS_ERR_UNSUPPORTED, "batched layout");
+  h->q_from_select = false;
   char *base = (char *)up((uintptr_t)(h->ws + h->L.total), 256);
   if ((size_t)(base - h->ws) + B.total > h->ws_bytes)
     return fail(GCSS_ERR_WORKSPACE, "workspace lacks the batched region (gcss_batched_workspace_size)");

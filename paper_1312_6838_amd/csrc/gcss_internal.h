@@ -205,6 +205,25 @@ hipError_t launch_quantize(const float *a, int64_t m, int64_t n, int64_t lda, in
 // ---- launchers (k_embed.hip) ----
 hipError_t launch_qless_r(const float *w, int64_t n, int64_t ldw, const int64_t *idx, int k,
                           float *r, int64_t ldr, hipStream_t s);
+// Rank-k approximation from the embedding: byte offsets of its buffers in a
+// scratch region, and the Gram matrix's tiling.
+struct RankPlan {
+  int L = 0, nt = 0, nsplit = 0;
+  int64_t chunk = 0;
+  size_t G = 0, U = 0, vb = 0, part = 0, mcoef = 0, perm = 0, sigma = 0, aux = 0, flag = 0, bytes = 0;
+};
+constexpr int kRankMaxL = 2048;  // largest number of picks the eigen-decomposition takes
+RankPlan rank_plan(int lmax, int64_t n);
+// G = W W^T (padded), U = I, and the sweeps' absolute threshold
+hipError_t launch_wgram(const RankPlan &P, const float *w, int64_t ldw, int l, int64_t n,
+                        char *scr, hipStream_t s);
+// one Jacobi sweep; the L / 64 ints at scr + P.flag are all 0 once G is diagonal
+hipError_t launch_jacobi_sweep(const RankPlan &P, char *scr, hipStream_t s);
+// eigenvalue order, sigma, error sums (scr + P.aux + 8: all, tail), then
+// U_A (ua may be null) and V_A (va may be null)
+hipError_t launch_rank_outputs(const RankPlan &P, char *scr, int l, int k, const double *Q,
+                               int64_t ldq, int64_t m, double *ua, int64_t ldu, const float *w,
+                               int64_t ldw, int64_t n, float *va, int64_t ldv, hipStream_t s);
 
 // ---- batched (k_batched.hip) ----
 // One group of consecutive columns inside one block of Algorithm 4.

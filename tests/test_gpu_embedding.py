@@ -11,6 +11,7 @@ import pytest
 
 import oracle
 import synth
+from oracle import embed
 from tests.gpu_util import colstore32, dev, f64cs, stored_dense
 
 pytestmark = pytest.mark.gpu
@@ -176,3 +177,122 @@ def test_embedding_argument_errors(gpu):
     idx = torch.tensor([1, n + 7, 2], dtype=torch.int64, device="cuda")
     R = gpu.qless_r_tensor(W, n, idx).cpu().numpy()
     assert np.all(np.isnan(R[:, 1])) and not np.any(np.isnan(R[:, [0, 2]]))
+
+
+# ---------------------------------------------------------------- rank-k ----
+# Tolerances: the GPU's W is binary32 (relative 2^-24 per entry) and its
+# Gram matrix and eigen-decomposition are FP64, so sigma_j is within
+# ~1e-7 sigma_1 of the oracle's; the triplets agree to ~1e-7 sigma_1 / gap;
+# the approximation's entries to 1e-5 ||A_i||.
+def _geometric(m, n, rank, ratio, noise, seed):
+    """U diag(ratio^j) V^T + noise: singular gaps of (1 - ratio) sigma_j."""
+    rng = np.random.default_rng(seed)
+    U, _ = np.linalg.qr(rng.standard_normal((m, rank)))
+    V, _ = np.linalg.qr(rng.standard_normal((n, rank)))
+    return (U * ratio ** np.arange(rank)) @ V.T + noise * rng.standard_normal((m, n))
+
+
+def _rank_case(gpu, target, dt, m, n, kmax, seed=40):
+    A = _geometric(m, n, min(3 * kmax, m), 0.85, 1e-6, seed)
+    A32 = colstore32(A)
+    Adev, sc, Aval = _values(gpu, A32, m, dt)
+    # candidates stay eligible down to the noise floor (tau), so that every
+    # case makes all kmax picks
+    if target == "self":
+        s = gpu.Selector(Adev, m, k_max=kmax, self_target=True, scales=sc, tau=1e-12)
+        s.set_target(None)
+    else:
+        Bv = stored_dense(colstore32(Aval @ synth.omega_gauss(n, 64, seed=seed + 1).astype(np.float64)), m)
+        s = gpu.Selector(Adev, m, k_max=kmax, r_max=64, scales=sc, tau=1e-12)
+        s.set_target(dev(colstore32(Bv)))
+    Wt = _embedding(kmax, n)
+    s.set_embedding(Wt)
+    idx, obj, ns, st = s.select(kmax)
+    assert ns == kmax
+    return s, Aval, idx, obj
+
+
+def _check_rank(s, Aval, idx, obj, l, k, target):
+    ref = embed.rank_k(Aval, [int(x) for x in idx[:l]], k)
+    U, sig, V, err = s.rank_k(l, k)
+    U = U.cpu().numpy().T                   # m x k
+    V = V.cpu().numpy().astype(np.float64).T  # n x k
+    s1 = ref["sigma"][0]
+    assert np.max(np.abs(sig - ref["sigma"])) <= 1e-6 * s1, np.max(np.abs(sig - ref["sigma"])) / s1
+    assert np.all(np.diff(sig) <= 0)
+    np.testing.assert_allclose(U.T @ U, np.eye(k), atol=1e-10)
+    np.testing.assert_allclose(V.T @ V, np.eye(k), atol=2e-5)
+    # singular vectors where the spectrum separates them; the approximation always
+    gap = np.minimum(np.abs(np.diff(np.r_[np.inf, ref["sigma"]])), np.abs(np.diff(np.r_[ref["sigma"], -np.inf])))
+    sep = gap > 1e-3 * s1
+    assert np.max(np.abs(U - ref["U"])[:, sep]) <= 1e-4
+    assert np.max(np.abs(V - ref["V"])[:, sep]) <= 1e-4
+    approx = (U * sig[None, :]) @ V.T
+    nrm = np.sqrt(np.sum(Aval * Aval, axis=0))
+    assert np.max(np.abs(approx - ref["approx"]) / nrm[None, :]) <= 1e-5
+    F = np.sum(Aval * Aval)
+    d = abs(err - ref["err"])
+    if target == "self":
+        assert d <= 1e-5 * ref["err"] + 1e-8 * F, (err, ref["err"], F)
+    else:
+        assert d <= 1e-5 * ref["err"] + 1e-6 * F, (err, ref["err"], F)
+
+
+@pytest.mark.parametrize("target", ["self", "proj"])
+@pytest.mark.parametrize("dt", ["f32", "fp8"])
+def test_rank_k_matches_oracle(gpu, target, dt):
+    m, n, kmax = 300, 2000, 40
+    s, Aval, idx, obj = _rank_case(gpu, target, dt, m, n, kmax)
+    for l, k in [(kmax, 1), (kmax, 10), (kmax, kmax), (17, 5)]:
+        _check_rank(s, Aval, idx, obj, l, k, target)
+
+
+@pytest.mark.parametrize("l", [64, 65, 200])
+def test_rank_k_several_jacobi_blocks(gpu, l):
+    """l spanning one to seven block pairs (padding and ragged sizes)."""
+    m, n = 260, 3000
+    s, Aval, idx, obj = _rank_case(gpu, "self", "f32", m, n, l, seed=l)
+    _check_rank(s, Aval, idx, obj, l, 10, "self")
+
+
+def test_rank_k_exact_low_rank_is_the_svd(gpu):
+    m, n, rank = 40, 100, 5
+    A = synth.int_lowrank_dense(m, n, rank, seed=8)
+    A32 = colstore32(A)
+    Av = stored_dense(A32, m)
+    s = gpu.Selector(dev(A32), m, k_max=10, self_target=True)
+    s.set_target(None)
+    Wt = _embedding(10, n)
+    s.set_embedding(Wt)
+    idx, obj, ns, st = s.select(10)
+    assert ns == rank
+    U, sig, V, err = s.rank_k(rank, rank)
+    sv = np.linalg.svd(Av, compute_uv=False)
+    np.testing.assert_allclose(sig, sv[:rank], rtol=1e-6)
+    assert err <= 1e-6 * np.sum(Av * Av)
+    approx = (U.cpu().numpy().T * sig[None, :]) @ V.cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(approx - Av)) <= 1e-5 * np.abs(Av).max()
+
+
+def test_rank_k_state_and_argument_errors(gpu):
+    m, n = 64, 300
+    A32 = colstore32(synth.gauss_lowrank_dense(m, n, 20, 0.1, seed=3))
+    s = gpu.Selector(dev(A32), m, k_max=8, self_target=True)
+    s.set_target(None)
+    Wt = _embedding(8, n)
+    s.set_embedding(Wt)
+    with pytest.raises(gpu.GcssError) as e:
+        s.rank_k(4, 2)                       # no selection yet
+    assert e.value.status == gpu.ERR_STATE
+    s.select(6)
+    with pytest.raises(gpu.GcssError) as e:
+        s.rank_k(7, 2)                       # more picks than the selection made
+    assert e.value.status == gpu.ERR_ARG
+    with pytest.raises(gpu.GcssError) as e:
+        s.rank_k(4, 5)                       # k > l
+    assert e.value.status == gpu.ERR_ARG
+    s.rank_k(6, 6)
+    s.reconstruction_error(np.array([3, 1], dtype=np.int64))   # rebuilds the basis
+    with pytest.raises(gpu.GcssError) as e:
+        s.rank_k(2, 1)
+    assert e.value.status == gpu.ERR_STATE

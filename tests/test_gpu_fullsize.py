@@ -55,6 +55,25 @@ def check_embedding(sel, gpu, A, m, W, cols, tol=1e-5):
     assert err.max() <= tol, err.max()
 
 
+def check_rank_k(sel, gpu, A, m, W, l, kr, cols, f_l):
+    """Rank-kr approximation from the GPU's W and Q against an FP64 SVD of
+    the same W on the host: singular values, the error (B = A: F(S) + tail),
+    orthonormal factors, sampled columns of Q W_k."""
+    U, sig, V, err = sel.rank_k(l, kr)
+    Wh = W.double().cpu().numpy()
+    Uw, sw, Vwt = np.linalg.svd(Wh, full_matrices=False)
+    assert np.max(np.abs(sig - sw[:kr])) <= 1e-9 * sw[0]
+    if f_l is not None:
+        assert rel(err, f_l + np.sum(sw[kr:] ** 2)) <= 1e-6
+    Uh = U.cpu().numpy()                      # kr x m
+    np.testing.assert_allclose(Uh @ Uh.T, np.eye(kr), atol=1e-10)
+    Q = sel.read(gpu.STATE_Q, m * l, np.float64).reshape(l, m).T
+    ref = Q @ ((Uw[:, :kr] * sw[:kr]) @ Vwt[:kr, cols])
+    got = (Uh.T * sig[None, :]) @ V[:, cols].double().cpu().numpy()
+    Ac = host(A, m, cols).T
+    assert np.max(np.abs(got - ref) / np.sqrt(np.sum(Ac * Ac, axis=0))[None, :]) <= 1e-5
+
+
 def common_checks(idx, obj, ns, k):
     assert ns == k
     assert len(set(int(x) for x in idx)) == k
@@ -94,6 +113,7 @@ def test_full_css_4096x65536_k200(gpu):
     check_embedding(sel, gpu, A, m, W, samp)
     dec = W.double().pow(2).sum(1).cpu().numpy()
     np.testing.assert_allclose(dec, obj[:-1] - obj[1:], rtol=1e-4, atol=1e-7 * obj[0])
+    check_rank_k(sel, gpu, A, m, W, k, 50, samp, obj[k])
     del A, W
     torch.cuda.empty_cache()
 
@@ -126,6 +146,7 @@ def test_full_gcss_2048x1048576_r256_k100_fp32_and_bf16(gpu):
     i2, o2, _, _ = sel.select(k)
     assert np.array_equal(i2, idx) and np.array_equal(o2.view(np.int64), obj.view(np.int64))
     check_embedding(sel, gpu, A, m, W, samp)
+    check_rank_k(sel, gpu, A, m, W, k, 20, samp, None)
     sel.set_embedding(None)
     del W
     # BF16 stream of the same data: stored codes bit-exact with the oracle's,
