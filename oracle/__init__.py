@@ -19,6 +19,8 @@ for Large-scale Data Sets"):
 * :mod:`oracle.brute`          numpy brute force (explicit least squares)
 * :mod:`oracle.embed`          embedding W = Q^T A and the rank-k approximation
                                in span(A_S) (Section 3)
+* :mod:`oracle.rng`            counter-based (Philox4x32-10) dense and sparse
+                               random sign Omega and B = A Omega (Section 5.1)
 """
 from __future__ import annotations
 
