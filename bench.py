@@ -231,6 +231,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--omega", default="gauss", choices=["gauss", "sign", "ssgn"],
+                    help="projection of B = A Omega workloads: Gaussian Omega from the host "
+                         "(default), or random signs drawn on the GPU: dense +-1 (sign) or "
+                         "sparse with density 1/sqrt(n) (ssgn)")
     ap.add_argument("--embedding", action="store_true",
                     help="the timed selections also write the embedding W = Q^T A")
     ap.add_argument("--rank-k", type=int, default=0, metavar="K",
@@ -280,11 +284,16 @@ def main():
         W = torch.empty(k, n, dtype=torch.float32, device="cuda")
         sel.set_embedding(W)
 
-    def step():
+    def make_target():
         if self_target:
             sel.set_target(None)
-        else:
+        elif args.omega == "gauss":
             sel.project_target(Om)
+        else:
+            sel.project_sign(1, r, density=1.0 if args.omega == "sign" else 1.0 / math.sqrt(n))
+
+    def step():
+        make_target()
         idx, obj, ns, st = sel.select(k)
         err = sel.reconstruction_error(idx[:ns])
         state.update(idx=idx, obj=obj, ns=ns, err=err)
@@ -310,10 +319,7 @@ def main():
     phases = {}
     torch.cuda.synchronize()
     ta = time.perf_counter()
-    if self_target:
-        sel.set_target(None)
-    else:
-        sel.project_target(Om)
+    make_target()
     torch.cuda.synchronize()
     tb = time.perf_counter()
     idx, obj, ns, st = sel.select(k)
@@ -361,7 +367,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "m": m, "n": n, "k": k, "lda": lda,
                    "target": "B = A" if self_target else f"B = A Omega, r = {r}",
-                   "a_storage": dtype, "embedding": bool(args.embedding)},
+                   "a_storage": dtype, "embedding": bool(args.embedding),
+                   "omega": None if self_target else args.omega},
         "roofline": roof,
         "loop_only": {"score_updates_per_s": n * k / (prof["loop_ms"] / max(prof["selects"], 1) * 1e-3)
                       if prof["selects"] else None,

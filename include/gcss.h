@@ -121,6 +121,28 @@ gcss_status gcss_project_target(gcss_ctx *h, const float *omega, int64_t r, floa
                                 int64_t ldb);
 
 /*
+ * Concise target from a random sign matrix drawn on the fly (Section 5.1:
+ * Omega's entries are i.i.d. from a univariate distribution, one row per
+ * column of A, never stored; the paper names uniform random sign and sparse
+ * random sign matrices).  B = A Omega (m x r), then B becomes the target as
+ * with gcss_set_target(h, b_out, r, ldb).
+ * Omega_ij (i < n, j < r) for seed and density d in (0, 1]: let w be word
+ * (j mod 4) of Philox4x32-10 (Salmon et al., SC 2011) applied to the counter
+ * (i mod 2^32, i div 2^32, j div 4, 0) with the key (seed mod 2^32,
+ * seed div 2^32), and t = round(d 2^31) (at least 1); then Omega_ij = 0 if
+ * (w >> 1) >= t, else -1 if w is odd and +1 if it is even.  d = 1 is the
+ * dense +-1 matrix; d = 1/sqrt(n) the sparse one of the paper.
+ * When d r <= 4 a pass reads only the columns of A with a non-zero entry in
+ * each column of Omega; otherwise the matrix-core projection runs with the
+ * Omega tiles generated in the kernel.  Sums are binary32 in a fixed order.
+ * b_out: device, ldb >= m, multiple of 4, 16-byte aligned, kept by the
+ * context.  Errors: GCSS_ERR_ARG (r outside [1, r_max], d outside (0, 1],
+ * ldb, alignment), GCSS_ERR_DEVICE.
+ */
+gcss_status gcss_project_sign(gcss_ctx *h, uint64_t seed, double density, int64_t r,
+                              float *b_out, int64_t ldb);
+
+/*
  * Greedy selection of k columns (Algorithm 3; Algorithm 1 for B = A) from the
  * initial scores of the current target.  Each call starts from those
  * scores, so repeated calls give identical results.

@@ -75,6 +75,23 @@ def omega_rows(i0, i1, r, seed, density):
     return np.where(keep, sign, 0.0)
 
 
+def omega_column(n, j, seed, density, chunk=1 << 20):
+    """Column j of Omega (all n rows) as float64, without the other columns."""
+    out = np.zeros(n)
+    seed = int(seed)
+    key = np.array([seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF], dtype=np.uint32)
+    t = threshold(density)
+    for i0 in range(0, n, chunk):
+        i = np.arange(i0, min(n, i0 + chunk), dtype=np.uint64)
+        ctr = np.stack([(i & _MASK).astype(np.uint32), (i >> np.uint64(32)).astype(np.uint32),
+                        np.full(i.size, j // 4, dtype=np.uint32),
+                        np.zeros(i.size, dtype=np.uint32)], axis=1)
+        u = philox4x32_10(ctr, key)[:, j % 4]
+        keep = np.ones(u.shape, dtype=bool) if t >= (1 << 31) else (u >> np.uint32(1)) < np.uint32(t)
+        out[i0:i0 + i.size] = np.where(keep, np.where((u & np.uint32(1)) != 0, -1.0, 1.0), 0.0)
+    return out
+
+
 def project_sign(A, seed, density, r, chunk=65536):
     """B = A Omega (Section 5.1's concise target), A dense m x n, FP64."""
     A = np.asarray(A, dtype=np.float64)

@@ -17,7 +17,7 @@ from ._abi import (  # noqa: F401
     STATE_Q, STATE_Z, WARN_EXHAUSTED, Desc, GcssError, batched_workspace_size, create, destroy,
     last_error, load, make_desc, project_target, quantize, read_state, reconstruction_error,
     select, select_async, select_batched, set_target, version, workspace_size,
-    set_profiling, get_profile, set_embedding, qless_r, rank_k,
+    set_profiling, get_profile, set_embedding, qless_r, rank_k, project_sign,
 )
 
 __all__ = ["Selector", "quantize_tensor", "qless_r_tensor", "load", "version", "GcssError"]
@@ -96,6 +96,19 @@ class Selector:
         B = torch.empty(int(r), int(ldb), dtype=torch.float32, device=self.A.device)
         project_target(self.h, Omega.data_ptr(), int(r), B.data_ptr(), int(ldb))
         self.B, self.r, self._omega = B, int(r), Omega
+        return B
+
+    def project_sign(self, seed, r, density=None, ldb=None):
+        """B = A Omega with a random sign Omega drawn on the device (Philox4x32-10,
+        counter (column, j/4)); density None = 1/sqrt(n) (sparse), 1 = dense.
+        Returns B (r, ldb)."""
+        import math
+        import torch
+        d = 1.0 / math.sqrt(self.n) if density is None else float(density)
+        ldb = ldb or ((self.m + 63) // 64) * 64
+        B = torch.empty(int(r), int(ldb), dtype=torch.float32, device=self.A.device)
+        project_sign(self.h, int(seed), d, int(r), B.data_ptr(), int(ldb))
+        self.B, self.r = B, int(r)
         return B
 
     # -- selection --

@@ -31,7 +31,7 @@ EXPORTS = [
     "gcss_project_target", "gcss_select", "gcss_select_async", "gcss_reconstruction_error",
     "gcss_select_batched", "gcss_batched_workspace_size", "gcss_quantize", "gcss_read_state",
     "gcss_last_error", "gcss_version", "gcss_set_profiling", "gcss_get_profile",
-    "gcss_set_embedding", "gcss_qless_r", "gcss_rank_k",
+    "gcss_set_embedding", "gcss_qless_r", "gcss_rank_k", "gcss_project_sign",
 ]
 
 
@@ -99,6 +99,8 @@ def load():
     lib.gcss_qless_r.restype = st
     lib.gcss_rank_k.argtypes = [_vp, _vp, _i64, _i32, _i32, _vp, _i64, _vp, _i64, _vp, _vp]
     lib.gcss_rank_k.restype = st
+    lib.gcss_project_sign.argtypes = [_vp, ctypes.c_uint64, _dbl, _i64, _vp, _i64]
+    lib.gcss_project_sign.restype = st
     lib.gcss_set_profiling.argtypes = [_vp, _i32]
     lib.gcss_set_profiling.restype = st
     lib.gcss_get_profile.argtypes = [_vp, _P(Profile)]
@@ -208,6 +210,11 @@ def read_state(h: int, item: int, nbytes: int) -> bytes:
     got = _sz(0)
     _check(load().gcss_read_state(h, item, buf, nbytes, ctypes.byref(got)))
     return bytes(buf[: got.value])
+
+
+def project_sign(h: int, seed: int, density: float, r: int, b_ptr: int, ldb: int) -> None:
+    _check(load().gcss_project_sign(h, int(seed) & 0xFFFFFFFFFFFFFFFF, float(density), r, b_ptr,
+                                    ldb))
 
 
 def set_embedding(h: int, w_ptr: int | None, ldw: int) -> None:

@@ -446,6 +446,19 @@ gcss_status gcss_project_target(gcss_ctx *h, const float *omega, int64_t r, floa
   return gcss_set_target(h, b_out, r, ldb);
 }
 
+gcss_status gcss_project_sign(gcss_ctx *h, uint64_t seed, double density, int64_t r,
+                             float *b_out, int64_t ldb) {
+  if (check_ctx(h)) return GCSS_ERR_ARG;
+  if (!b_out) return fail(GCSS_ERR_ARG, "null b_out");
+  if (r < 1 || r > h->d.r_max) return fail(GCSS_ERR_ARG, "r outside [1, r_max]");
+  if (!(density > 0.0 && density <= 1.0)) return fail(GCSS_ERR_ARG, "density must be in (0, 1]");
+  if (ldb < h->d.m || (ldb * 4) % 16) return fail(GCSS_ERR_ARG, "ldb must be >= m and a multiple of 4");
+  if (((uintptr_t)b_out) % 16) return fail(GCSS_ERR_ARG, "b_out must be 16-byte aligned");
+  HIPCHK(launch_project_sign(h->A, seed, density, r, b_out, ldb, h->at<void>(h->L.scratch),
+                             h->L.scratch_bytes, h->stream));
+  return gcss_set_target(h, b_out, r, ldb);
+}
+
 gcss_status gcss_select(gcss_ctx *h, int32_t k, int64_t *idx, double *objective,
                         int32_t *n_selected) {
   if (check_ctx(h)) return GCSS_ERR_ARG;

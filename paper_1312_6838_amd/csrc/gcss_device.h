@@ -109,8 +109,79 @@ __device__ __forceinline__ float load_elem(const AView &A, int64_t i, int64_t j)
   return v[0];
 }
 
+// Element size and elements per 16-byte chunk of each storage type.
+template <int DT>
+struct Elem;
+template <>
+struct Elem<DT_F32> {
+  static constexpr int esize = 4, epc = 4;
+};
+template <>
+struct Elem<DT_BF16> {
+  static constexpr int esize = 2, epc = 8;
+};
+template <>
+struct Elem<DT_FP8> {
+  static constexpr int esize = 1, epc = 16;
+};
+
+// Decode one 16-byte chunk into EPC floats.
+template <int DT>
+__device__ __forceinline__ void decode_chunk(const uint4 &r, float *v) {
+  if constexpr (DT == DT_F32) {
+    v[0] = __uint_as_float(r.x);
+    v[1] = __uint_as_float(r.y);
+    v[2] = __uint_as_float(r.z);
+    v[3] = __uint_as_float(r.w);
+  } else if constexpr (DT == DT_BF16) {
+    v[0] = bf16_lo(r.x);
+    v[1] = bf16_hi(r.x);
+    v[2] = bf16_lo(r.y);
+    v[3] = bf16_hi(r.y);
+    v[4] = bf16_lo(r.z);
+    v[5] = bf16_hi(r.z);
+    v[6] = bf16_lo(r.w);
+    v[7] = bf16_hi(r.w);
+  } else {
+    fp8x4_decode(r.x, v + 0);
+    fp8x4_decode(r.y, v + 4);
+    fp8x4_decode(r.z, v + 8);
+    fp8x4_decode(r.w, v + 12);
+  }
+}
+
 __device__ __forceinline__ double col_scale(const AView &A, int64_t i) {
   return A.dtype == DT_FP8 ? (double)A.scale[i] : 1.0;
+}
+
+// ---- counter-based random signs (concise target, Section 5.1) ----
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC 2011): ten rounds of
+// (c0, c1, c2, c3) -> (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1,
+// lo(M0 c0)), the key bumped by the Weyl constants before every round but
+// the first.
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int rnd = 0; rnd < 10; ++rnd) {
+    if (rnd > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t lo0 = c.x * 0xD2511F53u, hi0 = __umulhi(c.x, 0xD2511F53u);
+    const uint32_t lo1 = c.z * 0xCD9E8D57u, hi1 = __umulhi(c.z, 0xCD9E8D57u);
+    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+  }
+  return c;
+}
+
+// Entries i (row of Omega = column of A), 4*jb .. 4*jb+3 of the sign matrix
+// for key (k0, k1): word w of Philox(counter (i lo, i hi, jb, 0)) gives
+// 0 if (w >> 1) >= thr, else -1 (w odd) or +1 (w even).
+__device__ __forceinline__ uint4 sign_words(int64_t i, uint32_t jb, uint32_t k0, uint32_t k1) {
+  return philox4x32_10(make_uint4((uint32_t)(uint64_t)i, (uint32_t)((uint64_t)i >> 32), jb, 0u),
+                       k0, k1);
+}
+__device__ __forceinline__ float sign_entry(uint32_t w, uint32_t thr) {
+  return (w >> 1) < thr ? ((w & 1u) ? -1.f : 1.f) : 0.f;
 }
 
 }  // namespace gcss

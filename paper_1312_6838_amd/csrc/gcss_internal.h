@@ -202,6 +202,19 @@ hipError_t launch_obj_from_quad(const double *F0, const double *quad, const DevS
 // ---- launchers (k_quant.hip) ----
 hipError_t launch_quantize(const float *a, int64_t m, int64_t n, int64_t lda, int dtype,
                            void *out, int64_t ldo, float *scales, hipStream_t s);
+// ---- launchers (k_sign.hip, k_mfma.hip): B = A Omega, random sign Omega ----
+// threshold of sign_entry for a density in (0, 1] (round(d 2^31), >= 1)
+uint32_t sign_threshold(double density);
+// the sparse kernel (reads d r of A's columns per target column) or the MFMA one
+bool sign_uses_sparse(int64_t r, double density);
+hipError_t launch_project_sign(const AView &A, uint64_t seed, double density, int64_t r, float *B,
+                               int64_t ldb, void *scratch, size_t scratch_bytes, hipStream_t s);
+hipError_t launch_project_sign_dense(const AView &A, uint32_t k0, uint32_t k1, uint32_t thr,
+                                     int64_t r, float *B, int64_t ldb, void *scratch,
+                                     hipStream_t s);
+hipError_t launch_proj_reduce(const float *P, int64_t ldp, int64_t m, int64_t r, int nsplit,
+                              float *B, int64_t ldb, hipStream_t s);
+
 // ---- launchers (k_embed.hip) ----
 hipError_t launch_qless_r(const float *w, int64_t n, int64_t ldw, const int64_t *idx, int k,
                           float *r, int64_t ldr, hipStream_t s);

@@ -820,6 +820,40 @@ struct OmTile256 {
   }
 };
 
+// Random sign Omega generated in place of the loaded one: the same tile,
+// entries from sign_words (one Philox call per four entries).
+template <int BKT>
+struct OmGen256 {
+  static constexpr int PT = (BKT * 64 + kG2Threads - 1) / kG2Threads;
+  float4 v[PT];
+  __device__ __forceinline__ void load(uint32_t k0s, uint32_t k1s, uint32_t thr, int64_t r,
+                                       int64_t j0, int64_t k0, int64_t kend, int tid) {
+#pragma unroll
+    for (int u = 0; u < PT; ++u) {
+      const int q = tid + kG2Threads * u;
+      const int kk = q >> 6, jj = (q & 63) * 4;
+      const int64_t gk = k0 + kk, gj = j0 + jj;
+      float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (kk < BKT && gk < kend && gj < r) {
+        const uint4 w = sign_words(gk, (uint32_t)(gj >> 2), k0s, k1s);
+        x.x = sign_entry(w.x, thr);
+        x.y = gj + 1 < r ? sign_entry(w.y, thr) : 0.f;
+        x.z = gj + 2 < r ? sign_entry(w.z, thr) : 0.f;
+        x.w = gj + 3 < r ? sign_entry(w.w, thr) : 0.f;
+      }
+      v[u] = x;
+    }
+  }
+  __device__ __forceinline__ void store(float *Ts, int tid) const {
+#pragma unroll
+    for (int u = 0; u < PT; ++u) {
+      const int q = tid + kG2Threads * u;
+      const int kk = q >> 6, jj = (q & 63) * 4;
+      if (kk < BKT) *(float4 *)(Ts + kk * MP2 + jj) = v[u];
+    }
+  }
+};
+
 template <int BKT>
 __device__ __forceinline__ void mma_stage_mn256(const float *Xs, int xr0, const float *Ys, int yc0,
                                                 int lane, f32x4 (&acc)[8][4]) {
@@ -872,12 +906,16 @@ __device__ __forceinline__ void store_block_mn256(float *P, int64_t ldp, int64_t
   }
 }
 
-// PROJ = false: upper 256-tiles of C = A A^T; true: tiles of B = A Omega.
-template <int DT, int BKT, bool PROJ>
+// MODE 0: upper 256-tiles of C = A A^T; 1: tiles of B = A Omega (Omega
+// loaded); 2: tiles of B = A Omega with the random sign Omega generated from
+// the key (gk0, gk1) and threshold gthr.
+template <int DT, int BKT, int MODE>
 __global__ __launch_bounds__(kG2Threads, 1) void k_gemm256(AView A, const float *__restrict__ Om,
                                                            int64_t r, float *__restrict__ P,
                                                            int64_t ldp, int ntm, int ntile,
-                                                           int64_t kchunk) {
+                                                           int64_t kchunk, uint32_t gk0,
+                                                           uint32_t gk1, uint32_t gthr) {
+  constexpr bool PROJ = MODE != 0;
   __shared__ __align__(16) float Xs[2][BKT * MP2];
   __shared__ __align__(16) float Ys[2][BKT * MP2];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -905,9 +943,13 @@ __global__ __launch_bounds__(kG2Threads, 1) void k_gemm256(AView A, const float 
     for (int b = 0; b < 4; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
 
   MnTile256<DT, BKT> xt;
-  typename std::conditional<PROJ, OmTile256<BKT>, MnTile256<DT, BKT>>::type yt;
+  typename std::conditional<
+      MODE == 2, OmGen256<BKT>,
+      typename std::conditional<PROJ, OmTile256<BKT>, MnTile256<DT, BKT>>::type>::type yt;
   auto yload = [&](int64_t k0) {
-    if constexpr (PROJ)
+    if constexpr (MODE == 2)
+      yt.load(gk0, gk1, gthr, r, j0, k0, ke, tid);
+    else if constexpr (PROJ)
       yt.load(Om, r, j0, k0, ke, tid);
     else
       yt.load(A, j0, k0, ke, tid);
@@ -1449,9 +1491,9 @@ hipError_t launch_gram(const AView &A, float *C, int64_t ldc, void *scratch, int
   const dim3 grid((unsigned)(nt * sp));
   if (pl.tile == 256) {
     switch (A.dtype) {
-      case DT_F32: hipLaunchKernelGGL((k_gemm256<DT_F32, 16, false>), grid, dim3(kG2Threads), 0, s, A, nullptr, 0, P, ldp, pl.ntm, nt, kc); break;
-      case DT_BF16: hipLaunchKernelGGL((k_gemm256<DT_BF16, 16, false>), grid, dim3(kG2Threads), 0, s, A, nullptr, 0, P, ldp, pl.ntm, nt, kc); break;
-      case DT_FP8: hipLaunchKernelGGL((k_gemm256<DT_FP8, 16, false>), grid, dim3(kG2Threads), 0, s, A, nullptr, 0, P, ldp, pl.ntm, nt, kc); break;
+      case DT_F32: hipLaunchKernelGGL((k_gemm256<DT_F32, 16, 0>), grid, dim3(kG2Threads), 0, s, A, nullptr, 0, P, ldp, pl.ntm, nt, kc, 0u, 0u, 0u); break;
+      case DT_BF16: hipLaunchKernelGGL((k_gemm256<DT_BF16, 16, 0>), grid, dim3(kG2Threads), 0, s, A, nullptr, 0, P, ldp, pl.ntm, nt, kc, 0u, 0u, 0u); break;
+      case DT_FP8: hipLaunchKernelGGL((k_gemm256<DT_FP8, 16, 0>), grid, dim3(kG2Threads), 0, s, A, nullptr, 0, P, ldp, pl.ntm, nt, kc, 0u, 0u, 0u); break;
       default: return hipErrorInvalidValue;
     }
   } else {
@@ -1482,14 +1524,14 @@ hipError_t launch_gram(const AView &A, float *C, int64_t ldc, void *scratch, int
   return hipGetLastError();
 }
 
-static KPlan proj_plan(int64_t m, int64_t n, int64_t r) {
+static KPlan proj_plan(int64_t m, int64_t n, int64_t r, bool force256 = false) {
   KPlan p{};
   // keep the partials within ~128 MiB and every split at least 256 columns long
   const int64_t ldp = ((m + 3) / 4) * 4;
   const int64_t per = ldp * r * (int64_t)sizeof(float);
   int64_t cap = (int64_t)(128LL << 20) / (per > 0 ? per : 1);
   if (cap < 1) cap = 1;
-  if (m >= 256 && r >= 192) {
+  if (force256 || (m >= 256 && r >= 192)) {
     p.tile = 256;
     const int64_t tm = (m + 255) / 256, tn = (r + 255) / 256;
     p.ntm = (int)tm;
@@ -1512,9 +1554,38 @@ static KPlan proj_plan(int64_t m, int64_t n, int64_t r) {
 
 size_t proj_scratch_bytes(int64_t m, int64_t n, int64_t r, int num_cu) {
   (void)num_cu;
-  const KPlan p = proj_plan(m, n, r);
+  const KPlan p = proj_plan(m, n, r), p2 = proj_plan(m, n, r, true);
   const int64_t ldp = ((m + 3) / 4) * 4;
-  return (size_t)p.nsplit * ldp * r * sizeof(float);
+  const int64_t sp = p.nsplit > p2.nsplit ? p.nsplit : p2.nsplit;
+  return (size_t)sp * ldp * r * sizeof(float);
+}
+
+hipError_t launch_proj_reduce(const float *P, int64_t ldp, int64_t m, int64_t r, int nsplit,
+                              float *B, int64_t ldb, hipStream_t s) {
+  const int64_t total = m * r;
+  hipLaunchKernelGGL(k_proj_reduce, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, P,
+                     ldp, m, r, nsplit, B, ldb);
+  return hipGetLastError();
+}
+
+// B = A Omega with the random sign Omega generated inside the large-tile
+// MFMA kernel (dense Omega: every entry +-1, or any density).
+hipError_t launch_project_sign_dense(const AView &A, uint32_t k0, uint32_t k1, uint32_t thr,
+                                     int64_t r, float *B, int64_t ldb, void *scratch,
+                                     hipStream_t s) {
+  const KPlan pl = proj_plan(A.m, A.n, r, true);
+  const int64_t ldp = ((A.m + 3) / 4) * 4;
+  float *P = (float *)scratch;
+  const dim3 grid((unsigned)(pl.ntile * pl.nsplit));
+  switch (A.dtype) {
+    case DT_F32: hipLaunchKernelGGL((k_gemm256<DT_F32, 16, 2>), grid, dim3(kG2Threads), 0, s, A, nullptr, r, P, ldp, pl.ntm, pl.ntile, pl.kchunk, k0, k1, thr); break;
+    case DT_BF16: hipLaunchKernelGGL((k_gemm256<DT_BF16, 16, 2>), grid, dim3(kG2Threads), 0, s, A, nullptr, r, P, ldp, pl.ntm, pl.ntile, pl.kchunk, k0, k1, thr); break;
+    case DT_FP8: hipLaunchKernelGGL((k_gemm256<DT_FP8, 16, 2>), grid, dim3(kG2Threads), 0, s, A, nullptr, r, P, ldp, pl.ntm, pl.ntile, pl.kchunk, k0, k1, thr); break;
+    default: return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_proj_reduce(P, ldp, A.m, r, pl.nsplit, B, ldb, s);
 }
 
 hipError_t launch_project(const AView &A, const float *omega, int64_t r, float *B,
@@ -1529,9 +1600,9 @@ hipError_t launch_project(const AView &A, const float *omega, int64_t r, float *
   const dim3 grid((unsigned)(nt * sp));
   if (pl.tile == 256) {
     switch (A.dtype) {
-      case DT_F32: hipLaunchKernelGGL((k_gemm256<DT_F32, 16, true>), grid, dim3(kG2Threads), 0, s, A, omega, r, P, ldp, tm, nt, kc); break;
-      case DT_BF16: hipLaunchKernelGGL((k_gemm256<DT_BF16, 16, true>), grid, dim3(kG2Threads), 0, s, A, omega, r, P, ldp, tm, nt, kc); break;
-      case DT_FP8: hipLaunchKernelGGL((k_gemm256<DT_FP8, 16, true>), grid, dim3(kG2Threads), 0, s, A, omega, r, P, ldp, tm, nt, kc); break;
+      case DT_F32: hipLaunchKernelGGL((k_gemm256<DT_F32, 16, 1>), grid, dim3(kG2Threads), 0, s, A, omega, r, P, ldp, tm, nt, kc, 0u, 0u, 0u); break;
+      case DT_BF16: hipLaunchKernelGGL((k_gemm256<DT_BF16, 16, 1>), grid, dim3(kG2Threads), 0, s, A, omega, r, P, ldp, tm, nt, kc, 0u, 0u, 0u); break;
+      case DT_FP8: hipLaunchKernelGGL((k_gemm256<DT_FP8, 16, 1>), grid, dim3(kG2Threads), 0, s, A, omega, r, P, ldp, tm, nt, kc, 0u, 0u, 0u); break;
       default: return hipErrorInvalidValue;
     }
   } else {

@@ -25,46 +25,6 @@
 
 namespace gcss {
 
-template <int DT>
-struct Elem;
-template <>
-struct Elem<DT_F32> {
-  static constexpr int esize = 4, epc = 4;
-};
-template <>
-struct Elem<DT_BF16> {
-  static constexpr int esize = 2, epc = 8;
-};
-template <>
-struct Elem<DT_FP8> {
-  static constexpr int esize = 1, epc = 16;
-};
-
-// Decode one 16-byte chunk into EPC floats.
-template <int DT>
-__device__ __forceinline__ void decode_chunk(const uint4 &r, float *v) {
-  if constexpr (DT == DT_F32) {
-    v[0] = __uint_as_float(r.x);
-    v[1] = __uint_as_float(r.y);
-    v[2] = __uint_as_float(r.z);
-    v[3] = __uint_as_float(r.w);
-  } else if constexpr (DT == DT_BF16) {
-    v[0] = bf16_lo(r.x);
-    v[1] = bf16_hi(r.x);
-    v[2] = bf16_lo(r.y);
-    v[3] = bf16_hi(r.y);
-    v[4] = bf16_lo(r.z);
-    v[5] = bf16_hi(r.z);
-    v[6] = bf16_lo(r.w);
-    v[7] = bf16_hi(r.w);
-  } else {
-    fp8x4_decode(r.x, v + 0);
-    fp8x4_decode(r.y, v + 4);
-    fp8x4_decode(r.z, v + 8);
-    fp8x4_decode(r.w, v + 12);
-  }
-}
-
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 // 16-byte non-temporal load of a chunk of A (A is read once per pass).

@@ -166,6 +166,37 @@ def test_full_gcss_2048x1048576_r256_k100_fp32_and_bf16(gpu):
 
 
 @pytest.mark.timeout(600)
+def test_full_gcss_2048x1048576_r256_sparse_sign(gpu):
+    """The paper's sparse random sign target (density 1/sqrt(n)) drawn on the
+    GPU at full size: sampled columns of B against the oracle's column of
+    Omega and the FP64 sum of the hit columns; then the selection on it."""
+    import math
+    import torch
+    from oracle import rng
+    w = synth.workload("gcss_2048x1048576_r256_k100")
+    m, n, k, r = w["m"], w["n"], w["k"], w["r"]
+    A = synth.spectral_lowrank_torch(m, n, w["rank"], w["decay"], w["noise"], 0)
+    d = 1.0 / math.sqrt(n)
+    sel = gpu.Selector(A, m, k_max=k, r_max=r)
+    Bg = sel.project_sign(11, r, density=d)[:, :m].double().cpu().numpy()   # r x m
+    for j in (0, 77, 255):
+        om = rng.omega_column(n, j, 11, d)
+        hit = np.nonzero(om)[0]
+        Ah = host(A, m, hit)                                 # len(hit) x m
+        ref = Ah.T @ om[hit]
+        scale = np.sqrt(np.sum(Ah * Ah, axis=0)) * math.sqrt(max(len(hit), 1))
+        assert np.max(np.abs(Bg[j] - ref) / scale) < 1e-6, j
+    idx, obj, ns, st = sel.select(k)
+    common_checks(idx, obj, ns, k)
+    B = Bg.T
+    assert rel(obj[k], dense.error(host(A, m, idx).T, B)) <= 1e-5
+    rng_np = np.random.default_rng(3)
+    check_greedy(A, m, idx, B, [0, k - 1], rng_np)
+    del A
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.timeout(600)
 def test_full_batched_1024_64blocks(gpu):
     import torch
     w = synth.workload("batched_1024_64blocks_r128")

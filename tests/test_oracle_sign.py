@@ -71,3 +71,11 @@ def test_projection_is_the_sum_of_column_outer_products():
     for i in range(500):
         Bl += np.outer(A[:, i], rng.omega_rows(i, i + 1, 9, 5, 0.1)[0])
     np.testing.assert_allclose(B, Bl, atol=1e-12)
+
+
+def test_single_column_equals_the_matrix_column():
+    Om = rng.omega_rows(0, 3000, 11, seed=9, density=0.05)
+    for j in (0, 3, 4, 10):
+        assert np.array_equal(rng.omega_column(3000, j, 9, 0.05, chunk=700), Om[:, j])
+    Od = rng.omega_rows(0, 500, 6, seed=2, density=1.0)
+    assert np.array_equal(rng.omega_column(500, 5, 2, 1.0), Od[:, 5])
