@@ -235,6 +235,10 @@ def main():
                     help="projection of B = A Omega workloads: Gaussian Omega from the host "
                          "(default), or random signs drawn on the GPU: dense +-1 (sign) or "
                          "sparse with density 1/sqrt(n) (ssgn)")
+    ap.add_argument("--quality", type=int, default=0, metavar="L",
+                    help="B = A workloads: after the timed steps, time the relative accuracy "
+                         "(Section 7) of the first L picks against 10 uniform subsets and the "
+                         "best rank-L error")
     ap.add_argument("--embedding", action="store_true",
                     help="the timed selections also write the embedding W = Q^T A")
     ap.add_argument("--rank-k", type=int, default=0, metavar="K",
@@ -346,6 +350,22 @@ def main():
                               "rank_k_error": float(err_k)})
             del U, V
 
+    quality = None
+    if args.quality > 0 and self_target:
+        import synth
+        from paper_1312_6838_amd import quality as gq
+        lq = min(args.quality, int(ns))
+        subsets = synth.uniform_subsets(n, lq, range(10))
+        torch.cuda.synchronize()
+        tq = time.perf_counter()
+        q = gq.relative_accuracy(sel, idx, subsets, l=lq, s=min(2 * lq, k, m), max_iters=60)
+        torch.cuda.synchronize()
+        quality = {"l": lq, "uniform_draws": 10, "ms": round((time.perf_counter() - tq) * 1e3, 2),
+                   "relative_accuracy_pct": q["relative_accuracy"], "err_s": q["err_s"],
+                   "err_u_mean": float(sum(q["errs_u"]) / len(q["errs_u"])), "err_l": q["err_l"],
+                   "eig_block": min(2 * lq, k, m), "eig_iters": q["eig_iters"],
+                   "eig_change": q["eig_change"]}
+
     # roofline of the fused stream kernel
     src = open(os.path.join(ROOT, "paper_1312_6838_amd", "csrc", "k_stream.hip"), "rb").read()
     src_sha = hashlib.sha256(src).hexdigest()
@@ -375,6 +395,7 @@ def main():
                       "loop_ms": round(prof["loop_ms"] / max(prof["selects"], 1), 3)},
         "phases": phases,
         "embedding": embedding,
+        "quality": quality,
         "result": {"n_selected": int(state["ns"]), "objective_first": float(state["obj"][0]),
                    "objective_last": float(state["obj"][state["ns"]]),
                    "reconstruction_error": float(state["err"])},

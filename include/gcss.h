@@ -215,6 +215,37 @@ gcss_status gcss_qless_r(const float *w, int64_t n, int64_t ldw, const int64_t *
                          float *r, int64_t ldr, void *stream);
 
 /*
+ * Leading eigenpairs of C = A A^T (the squared singular values and left
+ * singular vectors of A) by block subspace iteration with Rayleigh-Ritz,
+ * for the quality metric of Section 7 (the best rank-l error
+ * ||A||_F^2 - sum_{j<=l} lambda_j) and for the target B = U_k Sigma_k of the
+ * paper's DistApproxSVD baseline.  Needs the Gram matrix (self target set).
+ * Method: Y = C Omega (Omega an m x s dense random sign matrix from seed,
+ * drawn in the kernel); then per iteration Q = orth(Y) (Cholesky QR in
+ * FP64: Y <- Y R^-1 with R^T R = Y^T Y; twice before each check) and
+ * Y = C Q (matrix cores, binary32); every 4 iterations and at the last, the
+ * Ritz values of T = Q^T C Q (FP64 block Jacobi); it stops when the sum of
+ * the k leading
+ * Ritz values changed by at most tol (relative) since the previous check,
+ * or after max_iters iterations.  Accuracy is limited by the binary32 C
+ * (relative ~1e-7 of lambda_1) and by the convergence of the block
+ * (clustered spectra converge slowly; the returned change says how far).
+ * 1 <= k <= s <= min(k_max, m, 2048).  lambda: host, k doubles, descending.
+ * u: device double, column-major m x k (ldu >= m), or NULL: Q times the
+ * Ritz vectors, sign convention of gcss_rank_k; computing u overwrites the
+ * selection basis, so gcss_rank_k needs a new selection afterwards.
+ * b_out (device float, column-major m x k, ldb >= m, multiple of 4, or
+ * NULL; needs u): the DistApproxSVD target U_k Sigma_k in binary32, ready
+ * for gcss_set_target.
+ * iters, change (host, may be NULL): iterations run, last relative change.
+ * Uses the workspace's scratch; synchronizes.  Errors: GCSS_ERR_ARG,
+ * GCSS_ERR_STATE (no Gram target), GCSS_ERR_UNSUPPORTED, GCSS_ERR_DEVICE.
+ */
+gcss_status gcss_top_eig(gcss_ctx *h, int32_t s, int32_t max_iters, double tol, uint64_t seed,
+                         int32_t k, double *lambda, double *u, int64_t ldu, float *b_out,
+                         int64_t ldb, int32_t *iters, double *change);
+
+/*
  * Rank-k approximation of A inside the span of the first l picks (Section 3,
  * the procedure credited to Boutsidis et al.), and the approximate leading
  * singular triplets of A it gives (Eq. ApproxSVD):

@@ -17,7 +17,7 @@ from ._abi import (  # noqa: F401
     STATE_Q, STATE_Z, WARN_EXHAUSTED, Desc, GcssError, batched_workspace_size, create, destroy,
     last_error, load, make_desc, project_target, quantize, read_state, reconstruction_error,
     select, select_async, select_batched, set_target, version, workspace_size,
-    set_profiling, get_profile, set_embedding, qless_r, rank_k, project_sign,
+    set_profiling, get_profile, set_embedding, qless_r, rank_k, project_sign, top_eig,
 )
 
 __all__ = ["Selector", "quantize_tensor", "qless_r_tensor", "load", "version", "GcssError"]
@@ -154,6 +154,31 @@ class Selector:
                             U.data_ptr() if U is not None else None, self.m,
                             V.data_ptr() if V is not None else None, self.n)
         return U, sigma, V, err
+
+    def top_eig(self, k, s=None, max_iters=20, tol=1e-7, seed=1, want_u=True):
+        """Leading eigenpairs of A A^T (needs the self target): returns
+        (lambda (k,), U (k, m) float64 rows = left singular vectors or None,
+        iterations, last relative change)."""
+        import torch
+        s = int(s or min(2 * k, self.desc.k_max, self.m))
+        U = torch.empty(int(k), self.m, dtype=torch.float64, device=self.A.device) if want_u else None
+        lam, it, ch = top_eig(self.h, s, int(max_iters), float(tol), int(seed), int(k),
+                              U.data_ptr() if U is not None else None, self.m)
+        return lam, U, it, ch
+
+    def svd_target(self, k, s=None, max_iters=20, tol=1e-7, seed=1, ldb=None):
+        """The DistApproxSVD target B = U_k Sigma_k of A (leading singular
+        triplets by subspace iteration on A A^T; needs the self target), set as
+        the explicit target.  Returns (B (k, ldb) float32, lambda, iterations)."""
+        import torch
+        s = int(s or min(2 * k, self.desc.k_max, self.m))
+        ldb = ldb or ((self.m + 63) // 64) * 64
+        U = torch.empty(int(k), self.m, dtype=torch.float64, device=self.A.device)
+        B = torch.empty(int(k), int(ldb), dtype=torch.float32, device=self.A.device)
+        lam, it, ch = top_eig(self.h, s, int(max_iters), float(tol), int(seed), int(k),
+                              U.data_ptr(), self.m, B.data_ptr(), int(ldb))
+        self.set_target(B)
+        return B, lam, it
 
     def reconstruction_error(self, idx):
         return reconstruction_error(self.h, idx)

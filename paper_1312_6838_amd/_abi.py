@@ -31,7 +31,7 @@ EXPORTS = [
     "gcss_project_target", "gcss_select", "gcss_select_async", "gcss_reconstruction_error",
     "gcss_select_batched", "gcss_batched_workspace_size", "gcss_quantize", "gcss_read_state",
     "gcss_last_error", "gcss_version", "gcss_set_profiling", "gcss_get_profile",
-    "gcss_set_embedding", "gcss_qless_r", "gcss_rank_k", "gcss_project_sign",
+    "gcss_set_embedding", "gcss_qless_r", "gcss_rank_k", "gcss_project_sign", "gcss_top_eig",
 ]
 
 
@@ -101,6 +101,9 @@ def load():
     lib.gcss_rank_k.restype = st
     lib.gcss_project_sign.argtypes = [_vp, ctypes.c_uint64, _dbl, _i64, _vp, _i64]
     lib.gcss_project_sign.restype = st
+    lib.gcss_top_eig.argtypes = [_vp, _i32, _i32, _dbl, ctypes.c_uint64, _i32, _vp, _vp, _i64, _vp,
+                                 _i64, _vp, _vp]
+    lib.gcss_top_eig.restype = st
     lib.gcss_set_profiling.argtypes = [_vp, _i32]
     lib.gcss_set_profiling.restype = st
     lib.gcss_get_profile.argtypes = [_vp, _P(Profile)]
@@ -215,6 +218,18 @@ def read_state(h: int, item: int, nbytes: int) -> bytes:
 def project_sign(h: int, seed: int, density: float, r: int, b_ptr: int, ldb: int) -> None:
     _check(load().gcss_project_sign(h, int(seed) & 0xFFFFFFFFFFFFFFFF, float(density), r, b_ptr,
                                     ldb))
+
+
+def top_eig(h: int, s: int, max_iters: int, tol: float, seed: int, k: int, u_ptr: int | None,
+            ldu: int, b_ptr: int | None = None, ldb: int = 0):
+    """-> (lambda float64[k], iterations, last relative change)"""
+    lam = np.zeros(k, dtype=np.float64)
+    it = _i32(0)
+    ch = ctypes.c_double(0.0)
+    _check(load().gcss_top_eig(h, s, max_iters, float(tol), int(seed) & 0xFFFFFFFFFFFFFFFF, k,
+                               lam.ctypes.data, u_ptr, ldu, b_ptr, ldb, ctypes.byref(it),
+                               ctypes.byref(ch)))
+    return lam, it.value, ch.value
 
 
 def set_embedding(h: int, w_ptr: int | None, ldw: int) -> None:

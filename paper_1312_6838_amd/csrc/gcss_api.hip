@@ -65,6 +65,28 @@ struct Layout {
   int64_t ldq;
 };
 
+// Scratch of gcss_top_eig for a block of width s: the projection's
+// partial sums, Y, Q (column-major) and Q (row-major), then the eigensolver's
+// buffers.
+struct EigLayout {
+  size_t y, qf, qr, rank, bytes;
+  RankPlan P;
+};
+EigLayout eig_layout(int64_t m, int64_t ldq, int s, int num_cu) {
+  EigLayout E{};
+  size_t off = up(proj_scratch_bytes(m, m, s, num_cu), 256);
+  E.y = off;
+  off += up((size_t)ldq * s * 4, 256);
+  E.qf = off;
+  off += up((size_t)ldq * s * 4, 256);
+  E.qr = off;
+  off += up((size_t)m * s * 4, 256);
+  E.rank = off;
+  E.P = rank_plan(s, m);
+  E.bytes = off + E.P.bytes;
+  return E;
+}
+
 bool make_layout(const gcss_desc *d, int num_cu, Layout *L) {
   const int64_t m = d->m, n = d->n, k = d->k_max, r = d->r_max;
   L->ldq = ld_for(m);
@@ -110,6 +132,10 @@ bool make_layout(const gcss_desc *d, int num_cu, Layout *L) {
   s = std::max(s, err_bytes);
   if (d->self_target) s = std::max(s, qta_scratch_bytes(n, (int)k));
   if (k <= kRankMaxL) s = std::max(s, rank_plan((int)k, n).bytes);
+  if (d->self_target) {
+    const int64_t smax = std::min<int64_t>(std::min<int64_t>(k, m), kRankMaxL);
+    s = std::max(s, eig_layout(m, L->ldq, (int)smax, num_cu).bytes);
+  }
   L->scratch_bytes = s;
   L->scratch = c.take<uint8_t>(s);
   L->total = up(c.off, 256);
@@ -627,6 +653,101 @@ gcss_status gcss_set_embedding(gcss_ctx *h, float *w, int64_t ldw) {
   return GCSS_OK;
 }
 
+// Block Jacobi sweeps on the prepared G until it is diagonal (at most 30).
+constexpr int kEigCheck = 4;  // subspace iterations between Rayleigh-Ritz checks
+
+static gcss_status run_jacobi(gcss_ctx *h, const RankPlan &P, char *scr) {
+  hipStream_t s = h->stream;
+  int conv = 1;
+  std::vector<int> flags((size_t)(P.L / 64));
+  for (int sweep = 0; sweep < 30 && conv; ++sweep) {
+    HIPCHK(launch_jacobi_sweep(P, scr, s));
+    HIPCHK(hipMemcpyAsync(flags.data(), scr + P.flag, sizeof(int) * flags.size(), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    conv = 0;
+    for (int f : flags) conv |= f;
+  }
+  if (conv) return fail(GCSS_ERR_DEVICE, "eigen-decomposition did not converge in 30 sweeps");
+  return GCSS_OK;
+}
+
+gcss_status gcss_top_eig(gcss_ctx *h, int32_t s_block, int32_t max_iters, double tol, uint64_t seed,
+                         int32_t k, double *lambda, double *u, int64_t ldu, float *b_out,
+                         int64_t ldb, int32_t *iters, double *change) {
+  if (check_ctx(h)) return GCSS_ERR_ARG;
+  const int64_t m = h->d.m, ldq = h->L.ldq;
+  if (!lambda) return fail(GCSS_ERR_ARG, "null lambda");
+  if (h->target != 2) return fail(GCSS_ERR_STATE, "needs the Gram matrix of A (set_target(NULL) first)");
+  const int64_t smax = std::min<int64_t>(std::min<int64_t>(h->d.k_max, m), kRankMaxL);
+  if (s_block < 1 || s_block > smax) return fail(GCSS_ERR_ARG, "block width s = %d outside [1, %lld]", s_block, (long long)smax);
+  if (k < 1 || k > s_block) return fail(GCSS_ERR_ARG, "need 1 <= k <= s");
+  if (max_iters < 1 || max_iters > 100) return fail(GCSS_ERR_ARG, "max_iters outside [1, 100]");
+  if (!(tol >= 0.0)) return fail(GCSS_ERR_ARG, "tol must be >= 0");
+  if (u && (ldu < m || ((uintptr_t)u) % 8)) return fail(GCSS_ERR_ARG, "ldu < m or misaligned u");
+  if (b_out && (!u || ldb < m || ((uintptr_t)b_out) % 16 || (ldb * 4) % 16))
+    return fail(GCSS_ERR_ARG, "b_out needs u, ldb >= m (multiple of 4) and 16-byte alignment");
+  const int sb = s_block;
+  const EigLayout E = eig_layout(m, ldq, sb, h->num_cu);
+  if (E.bytes > h->L.scratch_bytes) return fail(GCSS_ERR_UNSUPPORTED, "workspace too small for s = %d", sb);
+  hipStream_t st = h->stream;
+  char *scr = h->at<char>(h->L.scratch);
+  float *Y = (float *)(scr + E.y), *Qf = (float *)(scr + E.qf), *Qr = (float *)(scr + E.qr);
+  char *rs = scr + E.rank;
+  const AView C{h->at<float>(h->L.gram), nullptr, m, m, ldq, GCSS_F32};
+  // Y = C Omega with a dense random sign Omega (m x s, drawn in the kernel)
+  HIPCHK(launch_project_sign_dense(C, (uint32_t)seed, (uint32_t)(seed >> 32), sign_threshold(1.0), sb,
+                                   Y, ldq, scr, st));
+  std::vector<double> sig((size_t)sb);
+  double prev = -1.0, last_change = 0.0;
+  int it = 0;
+  for (it = 1; it <= max_iters; ++it) {
+    // Q = orth(Y): Cholesky QR (Y <- Y R^-1, R^T R = Y^T Y); a second pass
+    // before each Rayleigh-Ritz check, where Q must be orthonormal to
+    // rounding (the power steps in between tolerate the first pass's error)
+    const bool check = it % kEigCheck == 0 || it == max_iters;
+    const int passes = check ? 2 : 1;
+    for (int pass = 0; pass < passes; ++pass) {
+      const float *src = pass == 0 ? Y : Qf;
+      float *dst = pass == 0 ? Qf : Y;
+      HIPCHK(launch_wgram(E.P, src, ldq, sb, m, rs, st));
+      HIPCHK(launch_cholqr_apply(E.P, rs, sb, src, ldq, m, dst, ldq, st));
+    }
+    // the orthonormal block is in Qf after one pass, in Y after two; Y <- C Q
+    if (passes == 2) HIPCHK(hipMemcpyAsync(Qf, Y, (size_t)ldq * sb * 4, hipMemcpyDeviceToDevice, st));
+    HIPCHK(launch_to_rowmajor(Qf, ldq, m, sb, Qr, st));
+    HIPCHK(launch_project(C, Qr, sb, Y, ldq, scr, h->num_cu, st));
+    // Rayleigh-Ritz every kCheck iterations and at the last: T = Q^T C Q,
+    // whose eigenvalues approximate C's leading ones
+    if (!check) continue;
+    HIPCHK(launch_wgram2(E.P, Qf, Y, ldq, sb, m, rs, st));
+    gcss_status g = run_jacobi(h, E.P, rs);
+    if (g) return g;
+    HIPCHK(launch_eig_order(E.P, rs, sb, k, st));
+    HIPCHK(hipMemcpyAsync(sig.data(), rs + E.P.sigma, sizeof(double) * k, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    double sum = 0.0;
+    for (int j = 0; j < k; ++j) sum += sig[j] * sig[j];
+    last_change = prev < 0.0 ? 1.0 : std::fabs(sum - prev) / std::max(sum, 1e-300);
+    prev = sum;
+    if (last_change <= tol) break;
+  }
+  if (it > max_iters) it = max_iters;
+  for (int j = 0; j < k; ++j) lambda[j] = sig[j] * sig[j];
+  if (u) {
+    // u = Q U_T[:, :k] with Q in FP64 (the selection basis is overwritten)
+    double *Q64 = h->at<double>(h->L.Q);
+    HIPCHK(launch_cols_to_f64(Qf, ldq, m, sb, Q64, ldq, st));
+    h->q_from_select = false;
+    h->basis_valid = false;
+    HIPCHK(launch_ritz_vectors(E.P, rs, sb, k, Q64, ldq, m, u, ldu, st));
+    if (b_out) HIPCHK(launch_scale_cols(E.P, rs, u, ldu, m, k, b_out, ldb, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  if (iters) *iters = it;
+  if (change) *change = last_change;
+  return GCSS_OK;
+}
+
 gcss_status gcss_rank_k(gcss_ctx *h, const float *w, int64_t ldw, int32_t l, int32_t k, double *u,
                         int64_t ldu, float *v, int64_t ldv, double *sigma, double *err) {
   if (check_ctx(h)) return GCSS_ERR_ARG;
@@ -649,16 +770,10 @@ gcss_status gcss_rank_k(gcss_ctx *h, const float *w, int64_t ldw, int32_t l, int
   if (l < 1 || l > hs.t) return fail(GCSS_ERR_ARG, "l = %d outside [1, picks of the last selection = %d]", l, hs.t);
   char *scr = h->at<char>(h->L.scratch);
   HIPCHK(launch_wgram(P, w, ldw, l, n, scr, s));
-  int conv = 1;
-  std::vector<int> flags((size_t)(P.L / 64));
-  for (int sweep = 0; sweep < 30 && conv; ++sweep) {
-    HIPCHK(launch_jacobi_sweep(P, scr, s));
-    HIPCHK(hipMemcpyAsync(flags.data(), scr + P.flag, sizeof(int) * flags.size(), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    conv = 0;
-    for (int f : flags) conv |= f;
+  {
+    gcss_status g = run_jacobi(h, P, scr);
+    if (g) return g;
   }
-  if (conv) return fail(GCSS_ERR_DEVICE, "eigen-decomposition did not converge in 30 sweeps");
   HIPCHK(launch_rank_outputs(P, scr, l, k, h->at<double>(h->L.Q), h->L.ldq, m, u, ldu, w, ldw, n, v,
                              ldv, s));
   // ||A - Q W||^2: the selection's own objective for B = A, else

@@ -230,6 +230,28 @@ RankPlan rank_plan(int lmax, int64_t n);
 // G = W W^T (padded), U = I, and the sweeps' absolute threshold
 hipError_t launch_wgram(const RankPlan &P, const float *w, int64_t ldw, int l, int64_t n,
                         char *scr, hipStream_t s);
+// G = W V^T for a product known to be symmetric (upper tiles, mirrored)
+hipError_t launch_wgram2(const RankPlan &P, const float *w, const float *v, int64_t ldw, int l,
+                         int64_t n, char *scr, hipStream_t s);
+// eigenvalue order of the diagonalised G (perm, sigma = sqrt(lambda), sums)
+hipError_t launch_eig_order(const RankPlan &P, char *scr, int l, int k, hipStream_t s);
+// out (m x l, column-major) = Y U Sigma^-1 from the eigenpairs of Y^T Y
+hipError_t launch_orth_apply(const RankPlan &P, char *scr, int l, const float *y, int64_t ldy,
+                             int64_t m, float *out, int64_t ldo, hipStream_t s);
+// out (m x l, column-major) = Y R^-1 with R the Cholesky factor of Y^T Y
+// (G prepared by launch_wgram; U is used as R's storage)
+hipError_t launch_cholqr_apply(const RankPlan &P, char *scr, int l, const float *y, int64_t ldy,
+                               int64_t m, float *out, int64_t ldo, hipStream_t s);
+// ua = Q U[:, perm] (k columns, sign convention of rank_k)
+hipError_t launch_ritz_vectors(const RankPlan &P, char *scr, int l, int k, const double *Q,
+                               int64_t ldq, int64_t m, double *ua, int64_t ldu, hipStream_t s);
+hipError_t launch_to_rowmajor(const float *in, int64_t ldi, int64_t m, int c, float *out,
+                              hipStream_t s);
+// b = u diag(sigma) in binary32 (sigma of the last eigenvalue order)
+hipError_t launch_scale_cols(const RankPlan &P, char *scr, const double *u, int64_t ldu, int64_t m,
+                             int k, float *b, int64_t ldb, hipStream_t s);
+hipError_t launch_cols_to_f64(const float *in, int64_t ldi, int64_t m, int c, double *out,
+                              int64_t ldo, hipStream_t s);
 // one Jacobi sweep; the L / 64 ints at scr + P.flag are all 0 once G is diagonal
 hipError_t launch_jacobi_sweep(const RankPlan &P, char *scr, hipStream_t s);
 // eigenvalue order, sigma, error sums (scr + P.aux + 8: all, tail), then

@@ -77,9 +77,11 @@ __device__ __forceinline__ bool negligible(double gxy, double gxx, double gyy, d
   return a <= fl || a <= kJacRel * sqrt(fabs(gxx) * fabs(gyy));
 }
 
-// Partial Gram tiles: workgroup (tile, split) sums W[64a.., c] W[64b.., c]
-// over its column range for the upper tile pair (a, b), a <= b.
-__global__ __launch_bounds__(256) void k_wgram_part(const float *__restrict__ w, int64_t ldw,
+// Partial Gram tiles: workgroup (tile, split) sums W[64a.., c] V[64b.., c]
+// over its column range for the upper tile pair (a, b), a <= b (V = W for
+// the Gram matrix of W; otherwise a product known to be symmetric).
+__global__ __launch_bounds__(256) void k_wgram_part(const float *__restrict__ w,
+                                                    const float *__restrict__ v, int64_t ldw,
                                                     int l, int64_t n, int nt, int64_t chunk,
                                                     double *__restrict__ part) {
   __shared__ float wa[64][65];
@@ -104,7 +106,7 @@ __global__ __launch_bounds__(256) void k_wgram_part(const float *__restrict__ w,
       const int64_t c = cc + col;
       const int ra = a * 64 + row, rb = b * 64 + row;
       wa[row][col] = (ra < l && c < c1) ? w[(int64_t)ra * ldw + c] : 0.f;
-      wb[row][col] = (rb < l && c < c1) ? w[(int64_t)rb * ldw + c] : 0.f;
+      wb[row][col] = (rb < l && c < c1) ? v[(int64_t)rb * ldw + c] : 0.f;
     }
     __syncthreads();
 #pragma unroll 4
@@ -594,7 +596,191 @@ __global__ __launch_bounds__(256) void k_rank_v(const float *__restrict__ w, int
   }
 }
 
+// Orthonormalising coefficients: mcoef[s][j] = U[s][perm j] / sigma_j for
+// the k leading eigenpairs of Y^T Y, 0 where sigma_j <= 1e-6 sigma_0 (those
+// directions are rounding noise of the binary32 Y); row-major l x k, FP64.
+__global__ __launch_bounds__(256) void k_ortho_coef(const double *__restrict__ Ue, int L, int l,
+                                                    const int *__restrict__ perm,
+                                                    const double *__restrict__ sigma, int k,
+                                                    double *__restrict__ mcoef) {
+  const int j = blockIdx.x;
+  const double sj = sigma[j], s0 = sigma[0];
+  const double f = (sj > 1e-6 * s0 && sj > 0.0) ? 1.0 / sj : 0.0;
+  const int pj = clamp_idx(perm[j], l);
+  for (int s = threadIdx.x; s < l; s += 256) mcoef[(int64_t)s * k + j] = f * Ue[(int64_t)s * L + pj];
+}
+
+// out[i * c + j] = in[j * ldi + i] (binary32, m x c column-major to row-major)
+__global__ __launch_bounds__(256) void k_to_rowmajor(const float *__restrict__ in, int64_t ldi,
+                                                     int64_t m, int c, float *__restrict__ out) {
+  __shared__ float t[32][33];
+  const int64_t i0 = (int64_t)blockIdx.x * 32;
+  const int j0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int y = ty; y < 32; y += 8) {
+    const int64_t i = i0 + tx;
+    const int j = j0 + y;
+    t[y][tx] = (i < m && j < c) ? in[(int64_t)j * ldi + i] : 0.f;
+  }
+  __syncthreads();
+  for (int y = ty; y < 32; y += 8) {
+    const int64_t i = i0 + y;
+    const int j = j0 + tx;
+    if (i < m && j < c) out[i * c + j] = t[tx][y];
+  }
+}
+
+// out[j * ldo + i] = (double) in[j * ldi + i]
+__global__ __launch_bounds__(256) void k_cols_to_f64(const float *__restrict__ in, int64_t ldi,
+                                                     int64_t m, int c, double *__restrict__ out,
+                                                     int64_t ldo) {
+  const int j = blockIdx.y;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < m; i += (int64_t)gridDim.x * 256)
+    out[(int64_t)j * ldo + i] = (double)in[(int64_t)j * ldi + i];
+}
+
+// Cholesky factor R (upper, R^T R = G) of the l x l Gram matrix in G (row
+// stride L) and its inverse, by one workgroup: R row-major in rbuf (row
+// stride L), mcoef[p][c] = (R^-1)[p][c] (row-major l x l).  Each dot
+// product is split over a group of 8 lanes (lane g sums the terms p = g
+// mod 8) and reduced by shuffles, so a step's latency is about an eighth of
+// its length.  A pivot that falls to 1e-13 of its diagonal entry marks a
+// dependent column: its row and column of R^-1 are zero, so the
+// orthonormalised block loses it.
+__global__ __launch_bounds__(1024) void k_chol_inv(const double *__restrict__ G, int L, int l,
+                                                   double *__restrict__ rbuf,
+                                                   double *__restrict__ mcoef) {
+  __shared__ double invd[kRankMaxL];
+  __shared__ double vec[kRankMaxL];  // column j of R (factorisation) or row p (inverse)
+  const int g8 = threadIdx.x & 7, grp = threadIdx.x >> 3;  // 128 groups of 8 lanes
+  auto group_sum = [](double a) {
+    a += __shfl_xor(a, 1, 64);
+    a += __shfl_xor(a, 2, 64);
+    a += __shfl_xor(a, 4, 64);
+    return a;
+  };
+  for (int j = 0; j < l; ++j) {
+    for (int p = threadIdx.x; p < j; p += 1024) vec[p] = rbuf[(int64_t)p * L + j];
+    __syncthreads();
+    if (threadIdx.x < 64) {  // pivot: G[j][j] - |R[:j, j]|^2 by one wave
+      double a = 0.0;
+      for (int p = threadIdx.x; p < j; p += 64) a += vec[p] * vec[p];
+      for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+      if (threadIdx.x == 0) {
+        const double g = G[(int64_t)j * L + j];
+        const double r = g - a;
+        const double d = (r > 1e-13 * g && r > 0.0) ? sqrt(r) : 0.0;
+        rbuf[(int64_t)j * L + j] = d;
+        invd[j] = d > 0.0 ? 1.0 / d : 0.0;
+      }
+    }
+    __syncthreads();
+    const double inv = invd[j];
+    // row j: R[j][c] = (G[j][c] - R[:j, j] . R[:j, c]) / R[j][j]
+    for (int c0 = j + 1; c0 < l; c0 += 128) {
+      const int c = c0 + grp;
+      double a = 0.0;
+      if (c < l)
+        for (int p = g8; p < j; p += 8) a += vec[p] * rbuf[(int64_t)p * L + c];
+      a = group_sum(a);
+      if (c < l && g8 == 0) rbuf[(int64_t)j * L + c] = (G[(int64_t)j * L + c] - a) * inv;
+    }
+    __syncthreads();
+  }
+  // R^-1 by rows from the last: X[p][c] = -(R[p][p+1..c] . X[p+1..c][c]) / R[p][p]
+  for (int p = l - 1; p >= 0; --p) {
+    for (int q = threadIdx.x; q < l; q += 1024) vec[q] = q > p ? rbuf[(int64_t)p * L + q] : 0.0;
+    __syncthreads();
+    for (int c0 = 0; c0 < l; c0 += 128) {
+      const int c = c0 + grp;
+      double a = 0.0;
+      if (c < l && c > p)
+        for (int q = p + 1 + g8; q <= c; q += 8) a += vec[q] * mcoef[(int64_t)q * l + c];
+      a = group_sum(a);
+      if (c < l && g8 == 0) mcoef[(int64_t)p * l + c] = c == p ? invd[p] : (c > p ? -a * invd[p] : 0.0);
+    }
+    __syncthreads();
+  }
+}
+
+// b[j * ldb + i] = (float)(u[j * ldu + i] * sigma[j]): the target U_k Sigma_k
+__global__ __launch_bounds__(256) void k_scale_cols(const double *__restrict__ u, int64_t ldu,
+                                                    int64_t m, const double *__restrict__ sigma,
+                                                    float *__restrict__ b, int64_t ldb) {
+  const int j = blockIdx.y;
+  const double sj = sigma[j];
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < m; i += (int64_t)gridDim.x * 256)
+    b[(int64_t)j * ldb + i] = (float)(u[(int64_t)j * ldu + i] * sj);
+}
+
 }  // namespace
+
+hipError_t launch_scale_cols(const RankPlan &P, char *scr, const double *u, int64_t ldu, int64_t m,
+                             int k, float *b, int64_t ldb, hipStream_t s) {
+  const unsigned gx = (unsigned)((m + 255) / 256 < 64 ? (m + 255) / 256 : 64);
+  hipLaunchKernelGGL(k_scale_cols, dim3(gx, (unsigned)k), dim3(256), 0, s, u, ldu, m,
+                     (const double *)(scr + P.sigma), b, ldb);
+  return hipGetLastError();
+}
+
+hipError_t launch_cholqr_apply(const RankPlan &P, char *scr, int l, const float *y, int64_t ldy,
+                               int64_t m, float *out, int64_t ldo, hipStream_t s) {
+  double *mc = (double *)(scr + P.mcoef);
+  hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(1024), 0, s, (const double *)(scr + P.G), P.L, l,
+                     (double *)(scr + P.U), mc);
+  hipError_t e = hipGetLastError();
+  if (e) return e;
+  hipLaunchKernelGGL(k_rank_v, dim3((unsigned)((m + 63) / 64), (unsigned)((l + 63) / 64)), dim3(256),
+                     0, s, y, ldy, m, l, (const double *)mc, l, out, ldo);
+  return hipGetLastError();
+}
+
+hipError_t launch_eig_order(const RankPlan &P, char *scr, int l, int k, hipStream_t s) {
+  hipLaunchKernelGGL(k_eig_order, dim3(1), dim3(1024), 0, s, (const double *)(scr + P.G), P.L, l,
+                     k, (int *)(scr + P.perm), (double *)(scr + P.sigma),
+                     (double *)(scr + P.aux) + 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_orth_apply(const RankPlan &P, char *scr, int l, const float *y, int64_t ldy,
+                             int64_t m, float *out, int64_t ldo, hipStream_t s) {
+  double *mc = (double *)(scr + P.mcoef);
+  hipLaunchKernelGGL(k_ortho_coef, dim3((unsigned)l), dim3(256), 0, s,
+                     (const double *)(scr + P.U), P.L, l, (const int *)(scr + P.perm),
+                     (const double *)(scr + P.sigma), l, mc);
+  hipError_t e = hipGetLastError();
+  if (e) return e;
+  hipLaunchKernelGGL(k_rank_v, dim3((unsigned)((m + 63) / 64), (unsigned)((l + 63) / 64)), dim3(256),
+                     0, s, y, ldy, m, l, (const double *)mc, l, out, ldo);
+  return hipGetLastError();
+}
+
+hipError_t launch_ritz_vectors(const RankPlan &P, char *scr, int l, int k, const double *Q,
+                               int64_t ldq, int64_t m, double *ua, int64_t ldu, hipStream_t s) {
+  const double *U = (const double *)(scr + P.U);
+  const int *perm = (const int *)(scr + P.perm);
+  hipLaunchKernelGGL(k_rank_u, dim3((unsigned)((m + 63) / 64), (unsigned)((k + 63) / 64)), dim3(256),
+                     0, s, Q, ldq, m, l, U, P.L, perm, k, ua, ldu);
+  hipError_t e = hipGetLastError();
+  if (e) return e;
+  hipLaunchKernelGGL(k_rank_sign, dim3((unsigned)k), dim3(256), 0, s, ua, ldu, m, U, P.L, l, perm,
+                     (const double *)(scr + P.sigma), k, (double *)(scr + P.mcoef));
+  return hipGetLastError();
+}
+
+hipError_t launch_to_rowmajor(const float *in, int64_t ldi, int64_t m, int c, float *out,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_to_rowmajor, dim3((unsigned)((m + 31) / 32), (unsigned)((c + 31) / 32)),
+                     dim3(256), 0, s, in, ldi, m, c, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_cols_to_f64(const float *in, int64_t ldi, int64_t m, int c, double *out,
+                              int64_t ldo, hipStream_t s) {
+  const unsigned gx = (unsigned)((m + 255) / 256 < 64 ? (m + 255) / 256 : 64);
+  hipLaunchKernelGGL(k_cols_to_f64, dim3(gx, (unsigned)c), dim3(256), 0, s, in, ldi, m, c, out, ldo);
+  return hipGetLastError();
+}
 
 // Workspace of rank_k for l <= lmax picks over n columns.
 RankPlan rank_plan(int lmax, int64_t n) {
@@ -632,10 +818,15 @@ RankPlan rank_plan(int lmax, int64_t n) {
 
 hipError_t launch_wgram(const RankPlan &P, const float *w, int64_t ldw, int l, int64_t n,
                         char *scr, hipStream_t s) {
+  return launch_wgram2(P, w, w, ldw, l, n, scr, s);
+}
+
+hipError_t launch_wgram2(const RankPlan &P, const float *w, const float *v, int64_t ldw, int l,
+                         int64_t n, char *scr, hipStream_t s) {
   const int ntiles = P.nt * (P.nt + 1) / 2;
   double *part = (double *)(scr + P.part);
-  hipLaunchKernelGGL(k_wgram_part, dim3((unsigned)(ntiles * P.nsplit)), dim3(256), 0, s, w, ldw, l,
-                     n, P.nt, P.chunk, part);
+  hipLaunchKernelGGL(k_wgram_part, dim3((unsigned)(ntiles * P.nsplit)), dim3(256), 0, s, w, v, ldw,
+                     l, n, P.nt, P.chunk, part);
   hipError_t e = hipGetLastError();
   if (e) return e;
   hipLaunchKernelGGL(k_wgram_reduce, dim3((unsigned)ntiles), dim3(256), 0, s, part, P.nsplit, P.nt,

@@ -26,7 +26,7 @@ __all__ = [
     "lda_for", "to_colstore", "from_colstore",
     "gauss_lowrank_dense", "spectral_lowrank_dense", "planted_dense",
     "int_lowrank_dense", "orthogonal_columns_dense", "omega_gauss",
-    "block_widths", "workload", "WORKLOADS",
+    "block_widths", "uniform_subsets", "workload", "WORKLOADS",
     "spectral_lowrank_torch", "gauss_lowrank_torch", "omega_gauss_torch",
 ]
 
@@ -122,6 +122,11 @@ def omega_gauss(n, r, seed, dtype=np.float32):
     """Omega (n x r), i.i.d. N(0, 1/r), row-major: row i is drawn for column i."""
     rng = _rng(seed)
     return (rng.standard_normal((n, r)) / math.sqrt(r)).astype(dtype)
+
+
+def uniform_subsets(n, l, seeds):
+    """UniNoRep column subsets: l distinct columns drawn uniformly, one per seed."""
+    return [np.sort(_rng(int(s)).choice(n, l, replace=False)).astype(np.int64) for s in seeds]
 
 
 def block_widths(nblocks, lo, hi, seed):
