@@ -199,6 +199,27 @@ def bench_batched(args, w, A, scales, Om, dtype):
     ms_b = (t1 - t0) / args.steps * 1e3
     ms_s = (t2 - t1) / args.steps * 1e3
     updates = n * kb + pool_max * km
+    naive = None
+    if args.naive:
+        # the paper's naive distributed selection (each block against itself,
+        # uniform budgets l/c), and both merged selections judged on A itself
+        import numpy as np
+        from paper_1312_6838_amd import distributed
+        distributed.naive_select(A, m, off, nb * kb, k_merge=km, scales=scales)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        rn = distributed.naive_select(A, m, off, nb * kb, k_merge=km, scales=scales)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        full = g.Selector(A, m, k_max=km, self_target=True, scales=scales)
+        full.set_target(None)
+        e_dist = full.reconstruction_error(state["im"][:state["nm"]])
+        e_naive = full.reconstruction_error(rn["idx_merge"])
+        e0 = full.reconstruction_error(np.zeros(0, dtype=np.int64))
+        full.close()
+        naive = {"ms": round((tb - ta) * 1e3, 3), "budget_per_block": int(kb),
+                 "error_on_A_naive_merge": e_naive, "error_on_A_distgreedy_merge": e_dist,
+                 "norm2_A": e0}
     out = {
         "metric": METRIC, "value": updates / (ms_b / 1e3), "unit": "score updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_b, 3),
@@ -207,6 +228,7 @@ def bench_batched(args, w, A, scales, Om, dtype):
         "config": {"workload": args.workload, "m": m, "n": n, "blocks": nb, "k_block": kb,
                    "k_merge": km, "target": f"B = A Omega, r = {r}", "a_storage": dtype},
         "roofline": None,
+        "naive_distributed": naive,
         "block_sequential": {"ms_per_step": round(ms_s, 3),
                              "value": updates / (ms_s / 1e3),
                              "batched_speedup": round(ms_s / ms_b, 3)},
@@ -239,6 +261,9 @@ def main():
                     help="B = A workloads: after the timed steps, time the relative accuracy "
                          "(Section 7) of the first L picks against 10 uniform subsets and the "
                          "best rank-L error")
+    ap.add_argument("--naive", action="store_true",
+                    help="batched workload: also time the naive distributed selection (every "
+                         "block against itself) and compare both merges' errors on A")
     ap.add_argument("--embedding", action="store_true",
                     help="the timed selections also write the embedding W = Q^T A")
     ap.add_argument("--rank-k", type=int, default=0, metavar="K",

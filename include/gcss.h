@@ -317,6 +317,19 @@ gcss_status gcss_batched_workspace_size(const gcss_desc *d, int32_t nblocks, int
 gcss_status gcss_quantize(const float *a, int64_t m, int64_t n, int64_t lda, int32_t dtype,
                           void *out, int64_t ldo, float *scales, void *stream);
 
+/*
+ * Copy columns of the context's A: column j of out = stored column idx[j]
+ * (all lda elements, same storage type; FP8 also copies the scale into
+ * out_scales[j]).  For the second selection of Algorithm 4 and of the
+ * naive distributed selection (Section 5: a selection over the pooled
+ * columns A_{:L}).  idx: device, count int64; an index outside [0, n)
+ * gives a zero column (scale 1).  out: device, count * lda elements,
+ * 16-byte aligned.  Ordered on the context's stream.
+ * Errors: GCSS_ERR_ARG, GCSS_ERR_DEVICE.
+ */
+gcss_status gcss_gather_columns(gcss_ctx *h, const int64_t *idx, int64_t count, void *out,
+                                float *out_scales);
+
 /* What gcss_read_state copies back (for tests and diagnostics). */
 typedef enum {
   GCSS_STATE_F0 = 0,    /* n doubles: initial f                                 */

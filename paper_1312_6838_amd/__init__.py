@@ -18,6 +18,7 @@ from ._abi import (  # noqa: F401
     last_error, load, make_desc, project_target, quantize, read_state, reconstruction_error,
     select, select_async, select_batched, set_target, version, workspace_size,
     set_profiling, get_profile, set_embedding, qless_r, rank_k, project_sign, top_eig,
+    gather_columns,
 )
 
 __all__ = ["Selector", "quantize_tensor", "qless_r_tensor", "load", "version", "GcssError"]
@@ -179,6 +180,18 @@ class Selector:
                               U.data_ptr(), self.m, B.data_ptr(), int(ldb))
         self.set_target(B)
         return B, lam, it
+
+    def gather(self, idx):
+        """Stored columns idx of A as a new column store (count, lda) on the GPU
+        (and their FP8 scales).  Returns (A_sub, scales_sub or None)."""
+        import torch
+        idx = torch.as_tensor(idx, dtype=torch.int64).to(self.A.device).contiguous()
+        out = torch.empty(int(idx.numel()), self.lda, dtype=self.A.dtype, device=self.A.device)
+        sc = (torch.empty(int(idx.numel()), dtype=torch.float32, device=self.A.device)
+              if self.scales is not None else None)
+        gather_columns(self.h, idx.data_ptr(), int(idx.numel()), out.data_ptr(),
+                       sc.data_ptr() if sc is not None else None)
+        return out, sc
 
     def reconstruction_error(self, idx):
         return reconstruction_error(self.h, idx)

@@ -32,6 +32,7 @@ EXPORTS = [
     "gcss_select_batched", "gcss_batched_workspace_size", "gcss_quantize", "gcss_read_state",
     "gcss_last_error", "gcss_version", "gcss_set_profiling", "gcss_get_profile",
     "gcss_set_embedding", "gcss_qless_r", "gcss_rank_k", "gcss_project_sign", "gcss_top_eig",
+    "gcss_gather_columns",
 ]
 
 
@@ -104,6 +105,8 @@ def load():
     lib.gcss_top_eig.argtypes = [_vp, _i32, _i32, _dbl, ctypes.c_uint64, _i32, _vp, _vp, _i64, _vp,
                                  _i64, _vp, _vp]
     lib.gcss_top_eig.restype = st
+    lib.gcss_gather_columns.argtypes = [_vp, _vp, _i64, _vp, _vp]
+    lib.gcss_gather_columns.restype = st
     lib.gcss_set_profiling.argtypes = [_vp, _i32]
     lib.gcss_set_profiling.restype = st
     lib.gcss_get_profile.argtypes = [_vp, _P(Profile)]
@@ -230,6 +233,10 @@ def top_eig(h: int, s: int, max_iters: int, tol: float, seed: int, k: int, u_ptr
                                lam.ctypes.data, u_ptr, ldu, b_ptr, ldb, ctypes.byref(it),
                                ctypes.byref(ch)))
     return lam, it.value, ch.value
+
+
+def gather_columns(h: int, idx_ptr: int, count: int, out_ptr: int, scales_ptr: int | None) -> None:
+    _check(load().gcss_gather_columns(h, idx_ptr, count, out_ptr, scales_ptr))
 
 
 def set_embedding(h: int, w_ptr: int | None, ldw: int) -> None:

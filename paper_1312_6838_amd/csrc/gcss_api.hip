@@ -1072,6 +1072,18 @@ gcss_status gcss_select_batched(gcss_ctx *h, int32_t nblocks, const int64_t *col
   return (ns < k_merge) ? GCSS_WARN_EXHAUSTED : GCSS_OK;
 }
 
+gcss_status gcss_gather_columns(gcss_ctx *h, const int64_t *idx, int64_t count, void *out,
+                                float *out_scales) {
+  if (check_ctx(h)) return GCSS_ERR_ARG;
+  if (count < 0) return fail(GCSS_ERR_ARG, "count < 0");
+  if (count == 0) return GCSS_OK;
+  if (!idx || !out) return fail(GCSS_ERR_ARG, "null idx or out");
+  if (h->d.a_dtype == GCSS_FP8_E4M3 && !out_scales) return fail(GCSS_ERR_ARG, "FP8 needs out_scales");
+  if (((uintptr_t)out) % 16 || ((uintptr_t)idx) % 8) return fail(GCSS_ERR_ARG, "misaligned out or idx");
+  HIPCHK(launch_gather_cols(h->A, idx, count, out, out_scales, h->stream));
+  return GCSS_OK;
+}
+
 gcss_status gcss_quantize(const float *a, int64_t m, int64_t n, int64_t lda, int32_t dtype,
                           void *out, int64_t ldo, float *scales, void *stream) {
   if (!a || !out) return fail(GCSS_ERR_ARG, "null a or out");

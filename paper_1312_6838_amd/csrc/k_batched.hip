@@ -320,15 +320,22 @@ __global__ void k_batch_begin(const double *__restrict__ f0, const double *__res
 
 // Pooled matrix of Algorithm 4's second phase: A0[:, j] = A[:, pick[j]] (and
 // the FP8 column scale).  One workgroup per pooled column.
-__global__ void k_gather_cols(const char *__restrict__ a, int64_t col_bytes,
+// Column j of a0 = column pick[j] of A (whole stored column, pad included);
+// a pick outside [0, n) gives a zero column (FP8 scale 1).
+__global__ void k_gather_cols(const char *__restrict__ a, int64_t col_bytes, int64_t n,
                               const float *__restrict__ scale, const int64_t *__restrict__ pick,
                               char *__restrict__ a0, float *__restrict__ scale0) {
   const int64_t j = blockIdx.x;
   const int64_t src = pick[j];
-  const uint4 *s4 = (const uint4 *)(a + src * col_bytes);
+  const bool ok = src >= 0 && src < n;
   uint4 *d4 = (uint4 *)(a0 + j * col_bytes);
-  for (int64_t x = threadIdx.x; x < col_bytes / 16; x += blockDim.x) d4[x] = s4[x];
-  if (threadIdx.x == 0 && scale) scale0[j] = scale[src];
+  if (ok) {
+    const uint4 *s4 = (const uint4 *)(a + src * col_bytes);
+    for (int64_t x = threadIdx.x; x < col_bytes / 16; x += blockDim.x) d4[x] = s4[x];
+  } else {
+    for (int64_t x = threadIdx.x; x < col_bytes / 16; x += blockDim.x) d4[x] = make_uint4(0u, 0u, 0u, 0u);
+  }
+  if (threadIdx.x == 0 && scale) scale0[j] = ok ? scale[src] : 1.f;
 }
 
 // ---------------------------------------------------------------------------
@@ -423,8 +430,10 @@ hipError_t launch_batch_begin(const double *f0, const double *g0, const uint8_t 
 hipError_t launch_gather_cols(const AView &A, const int64_t *pick, int64_t npick, void *a0,
                               float *scale0, hipStream_t s) {
   const int64_t col_bytes = A.lda * dtype_bytes(A.dtype);
+  if (npick < 1) return hipSuccess;
   hipLaunchKernelGGL(k_gather_cols, dim3((unsigned)npick), dim3(256), 0, s, (const char *)A.a,
-                     col_bytes, A.dtype == DT_FP8 ? A.scale : nullptr, pick, (char *)a0, scale0);
+                     col_bytes, A.n, A.dtype == DT_FP8 ? A.scale : nullptr, pick, (char *)a0,
+                     scale0);
   return hipGetLastError();
 }
 
