@@ -31,6 +31,29 @@
 
 namespace gcss {
 
+namespace {
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+constexpr int kX3BK = 32;          // k per stage
+constexpr int kX3RP = 40;          // LDS row pitch in bfloat16 (32 + pad)
+constexpr int kX3Plane = 256 * kX3RP;  // one plane of a 256-row operand
+
+__device__ __forceinline__ void split3(float a, __bf16 &h, __bf16 &m, __bf16 &l) {
+  h = (__bf16)a;
+  const float r1 = a - (float)h;
+  m = (__bf16)r1;
+  l = (__bf16)(r1 - (float)m);
+}
+
+// binary32 products on the bfloat16 matrix cores (three-part split) for the
+// Gram matrix and the initial scores; GCSS_MFMA_X3=0 keeps the binary32 MFMA
+// kernels
+bool mfma_x3() {
+  const char *e = std::getenv("GCSS_MFMA_X3");
+  return !(e && e[0] == '0');
+}
+}  // namespace
+
+
 // MFMA/LDS interleaving strategy of the compiler for the stage loops
 #ifndef GCSS_IGLP
 #define GCSS_IGLP 1
@@ -589,6 +612,218 @@ __global__ __launch_bounds__(kI2Threads, 1) void k_init256(const float *__restri
 }
 
 // ---------------------------------------------------------------------------
+// Initial scores of binary32 A on the bfloat16 matrix cores: k_init256's
+// computation (f_j = ||X A_j||^2, or with TRI f_j = A_j^T (X + X^T) A_j / 2
+// for the symmetric X = C by its upper triangle) with both operands split
+// into three bfloat16 parts as in k_gram_x3 (six part products per binary32
+// product).  X rows and A columns both hold k contiguously, so a thread
+// loads eight consecutive k of one row or column and writes each plane with
+// one 16-byte LDS store.  One workgroup per 256 columns of A, all row chunks.
+template <bool TRI>
+__global__ __launch_bounds__(kI2Threads, 1) void k_init_x3(const float *__restrict__ X,
+                                                           int64_t ldx, int64_t R, AView A,
+                                                           double *__restrict__ f0,
+                                                           double *__restrict__ g0,
+                                                           uint8_t *__restrict__ mask0) {
+  constexpr int RT = 256, NT = 256;
+  static_assert(kI2Threads == 512, "two load tasks per operand and thread");
+  __shared__ __align__(16) __bf16 Ls[2][3][kX3Plane];  // [X rows / A columns][plane][.][k]
+  __shared__ double red[2][NT];     // f partial sums per row-wave, over the row chunks
+  __shared__ double gpart[4][NT];   // g partial sums per k group
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave >> 2) * 128, wc = (wave & 3) * 64;
+  const int lr = lane & 15, kq = (lane >> 4) * 8;
+  const int64_t m = A.m, n = A.n;
+  const int64_t j0 = (int64_t)blockIdx.x * NT;
+  const float *a = (const float *)A.a;
+
+  // load tasks: task t (0..1023) of an operand = row / column t & 255, k group t >> 8
+  // (partial sums live in LDS, keeping registers for the operands)
+  for (int t = tid; t < 2 * NT; t += kI2Threads) red[t >> 8][t & 255] = 0.0;
+  for (int t = tid; t < 4 * NT; t += kI2Threads) gpart[t >> 8][t & 255] = 0.0;
+  float4 xr[2][2], yr[2][2];
+
+  const int64_t nchunks = (R + RT - 1) / RT;
+  for (int64_t rc = 0; rc < nchunks; ++rc) {
+    const int64_t r0 = rc * RT;
+    f32x4 acc[8][4];
+#pragma unroll
+    for (int x = 0; x < 8; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) acc[x][y] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    auto gload = [&](int64_t k0) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int t = tid + kI2Threads * u;
+        const int row = t & 255, kg = (t >> 8) * 8;
+        const int64_t gk = k0 + kg;
+        // X row r0 + row, k gk .. gk + 7 (weighted for TRI)
+        const int64_t gr = r0 + row;
+        float v[8];
+        if (gr < R && gk < m) {
+          const float *src = X + gr * ldx + gk;
+          if (gk + 7 < m) {
+            const float4 p0 = *(const float4 *)src, p1 = *(const float4 *)(src + 4);
+            v[0] = p0.x; v[1] = p0.y; v[2] = p0.z; v[3] = p0.w;
+            v[4] = p1.x; v[5] = p1.y; v[6] = p1.z; v[7] = p1.w;
+          } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = gk + e < m ? src[e] : 0.f;
+          }
+        } else {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) v[e] = 0.f;
+        }
+        xr[u][0] = make_float4(v[0], v[1], v[2], v[3]);
+        xr[u][1] = make_float4(v[4], v[5], v[6], v[7]);
+        // A column j0 + row, k gk .. gk + 7
+        const int64_t gj = j0 + row;
+        if (gj < n && gk < m) {
+          const float *src = a + gj * A.lda + gk;
+          if (gk + 7 < m) {
+            const float4 p0 = *(const float4 *)src, p1 = *(const float4 *)(src + 4);
+            v[0] = p0.x; v[1] = p0.y; v[2] = p0.z; v[3] = p0.w;
+            v[4] = p1.x; v[5] = p1.y; v[6] = p1.z; v[7] = p1.w;
+          } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = gk + e < m ? src[e] : 0.f;
+          }
+        } else {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) v[e] = 0.f;
+        }
+        yr[u][0] = make_float4(v[0], v[1], v[2], v[3]);
+        yr[u][1] = make_float4(v[4], v[5], v[6], v[7]);
+      }
+    };
+    auto lstore = [&](int64_t k0) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int t = tid + kI2Threads * u;
+        const int row = t & 255, kg = (t >> 8) * 8;
+        const int off = row * kX3RP + kg;
+#pragma unroll
+        for (int op = 0; op < 2; ++op) {
+          const float4 q0 = op == 0 ? xr[u][0] : yr[u][0], q1 = op == 0 ? xr[u][1] : yr[u][1];
+          float v[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+          if (TRI && op == 0) {
+            // weights of the triangle: 1 above the diagonal, 1/2 on it, 0 below
+            const int d0 = (int)(k0 + kg - (r0 + row));
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] *= d0 + e > 0 ? 1.f : (d0 + e == 0 ? 0.5f : 0.f);
+          }
+          bf16x8 h, md, lo;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            __bf16 xh, xm, xl;
+            split3(v[e], xh, xm, xl);
+            h[e] = xh;
+            md[e] = xm;
+            lo[e] = xl;
+          }
+          *(bf16x8 *)(&Ls[op][0][off]) = h;
+          *(bf16x8 *)(&Ls[op][1][off]) = md;
+          *(bf16x8 *)(&Ls[op][2][off]) = lo;
+          if (op == 1 && rc == 0) {
+            double g = gpart[t >> 8][t & 255];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) g = fma((double)v[e], (double)v[e], g);
+            gpart[t >> 8][t & 255] = g;  // this thread's own entry
+          }
+        }
+      }
+    };
+
+    const int64_t kstart = TRI ? r0 : 0;
+    if (kstart < m) gload(kstart);
+    for (int64_t k0 = kstart; k0 < m; k0 += kX3BK) {
+      __syncthreads();  // the previous stage's operands are consumed
+      lstore(k0);
+      __syncthreads();
+      if (k0 + kX3BK < m) gload(k0 + kX3BK);
+      bf16x8 b[4][3];
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+          b[nb][p] = *(const bf16x8 *)(&Ls[1][p][(wc + 16 * nb + lr) * kX3RP + kq]);
+#pragma unroll
+      for (int rb = 0; rb < 8; ++rb) {
+        bf16x8 av[3];
+#pragma unroll
+        for (int p = 0; p < 3; ++p) av[p] = *(const bf16x8 *)(&Ls[0][p][(wr + 16 * rb + lr) * kX3RP + kq]);
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) {
+          f32x4 c = acc[rb][nb];
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[1], b[nb][1], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[2], b[nb][0], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[0], b[nb][2], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[1], b[nb][0], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[0], b[nb][1], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[0], b[nb][0], c, 0, 0, 0);
+          acc[rb][nb] = c;
+        }
+      }
+    }
+
+    // epilogue of this row chunk (as in k_init256), summed into red
+    double colacc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int rb = 0; rb < 8; ++rb) {
+      const int64_t i = r0 + wr + 16 * rb + 4 * (lane >> 4);
+      if constexpr (TRI) {
+        const int64_t ic = i < m ? i : 0;
+        const float w0 = i < m ? 1.f : 0.f, w1 = i + 1 < m ? 1.f : 0.f;
+        const float w2 = i + 2 < m ? 1.f : 0.f, w3 = i + 3 < m ? 1.f : 0.f;
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) {
+          const int64_t j = j0 + wc + 16 * nb + lr;
+          const float wj = j < n ? 1.f : 0.f;
+          // one load in flight at a time: hoisting all 32 would spill the tile
+          __builtin_amdgcn_sched_barrier(0);
+          const float4 av4 = *(const float4 *)(a + (j < n ? j : 0) * A.lda + ic);
+          const float p = acc[rb][nb][0] * (av4.x * w0) + acc[rb][nb][1] * (av4.y * w1) +
+                          acc[rb][nb][2] * (av4.z * w2) + acc[rb][nb][3] * (av4.w * w3);
+          colacc[nb] += (double)(p * wj);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      } else {
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) {
+          double sq = 0.0;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) sq += (double)acc[rb][nb][v] * (double)acc[rb][nb][v];
+          colacc[nb] += sq;
+        }
+      }
+    }
+    // sum over the 4 lane groups; one writer per (row-wave, column): fixed order
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+      double sv = colacc[nb];
+      sv += __shfl_xor(sv, 16, 64);
+      sv += __shfl_xor(sv, 32, 64);
+      if (lane < 16) red[wave >> 2][wc + 16 * nb + lane] += sv;
+    }
+  }
+
+  __syncthreads();
+  if (tid < NT) {
+    const int64_t j = j0 + tid;
+    if (j < n) {
+      const double fv = red[0][tid] + red[1][tid];
+      const double g = ((gpart[0][tid] + gpart[1][tid]) + gpart[2][tid]) + gpart[3][tid];
+      const double f = (TRI ? 2.0 : 1.0) * fv;
+      f0[j] = f;
+      g0[j] = g;
+      mask0[j] = (g > 0.0 && isfinite(g) && isfinite(f)) ? 0 : 2;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // MN-major operand from A: rows i0..i0+127 of columns k0..k0+BKT-1 (decoded,
 // FP8 columns scaled), staged through registers into Ts[k * MP + i].
 template <int DT, int BKT>
@@ -986,6 +1221,140 @@ __global__ __launch_bounds__(kG2Threads, 1) void k_gemm256(AView A, const float 
   store_block_mn256(Pout, ldp, i0 + wr, j0 + wc, m, ncol, lane, acc);
 }
 
+// ---------------------------------------------------------------------------
+// Gram matrix of binary32 A on the bfloat16 matrix cores.  Each element is
+// split exactly into three bfloat16 parts, a = a_h + a_m + a_l (a_h the
+// nearest bfloat16 to a, a_m the nearest to a - a_h, a_l the rest), and a
+// product a b is formed from the six part products whose order is at most
+// 2^-16 a b (h h, h m, m h, h l, l h, m m); the three dropped ones are below
+// 2^-24 |a b|, under binary32 rounding.  The bfloat16 MFMA (16 x 16 x 32)
+// runs 16 times the binary32 one, so six of them still take 3/8 of the time.
+// Tiles as in k_gemm256 (256 x 256 per workgroup, eight waves of 128 x 64);
+// each k-stage of 32 columns is split into planes once, on its way into LDS,
+// with rows of 32 consecutive k per plane (one 16-byte read per lane and
+// plane feeds an MFMA operand).
+
+__global__ __launch_bounds__(kG2Threads, 1) void k_gram_x3(AView A, float *__restrict__ P,
+                                                           int64_t ldp, int ntile,
+                                                           int64_t kchunk) {
+  // [operand 0 / 1][plane h, m, l][row][k]
+  __shared__ __align__(16) __bf16 Ls[2][3][kX3Plane];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t m = A.m, n = A.n;
+  const int64_t tile = blockIdx.x % ntile, split = blockIdx.x / ntile;
+  int64_t bj = 0;
+  while ((bj + 1) * (bj + 2) / 2 <= tile) ++bj;
+  const int64_t i0 = (tile - bj * (bj + 1) / 2) * 256, j0 = bj * 256;
+  const int64_t kb = split * kchunk;
+  const int64_t ke = (kb + kchunk) < n ? (kb + kchunk) : n;
+  float *Pout = P + split * ldp * m;
+  const float *a = (const float *)A.a;
+
+  // load task of this thread: operand op, rows r0..r0+3, k k8..k8+7 of the stage
+  const int op = tid >> 8, task = tid & 255;
+  const int r0 = (task & 63) * 4, k8 = (task >> 6) * 8;
+  const int64_t row0 = (op == 0 ? i0 : j0) + r0;
+  float4 reg[8];
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int64_t k = k0 + k8 + e;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (k < ke) {
+        const float *src = a + k * A.lda + row0;
+        if (row0 + 3 < m) {
+          v = *(const float4 *)src;
+        } else {
+          if (row0 < m) v.x = src[0];
+          if (row0 + 1 < m) v.y = src[1];
+          if (row0 + 2 < m) v.z = src[2];
+        }
+      }
+      reg[e] = v;
+    }
+  };
+  auto lstore = [&]() {
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      bf16x8 h, md, lo;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float x = rr == 0 ? reg[e].x : rr == 1 ? reg[e].y : rr == 2 ? reg[e].z : reg[e].w;
+        __bf16 xh, xm, xl;
+        split3(x, xh, xm, xl);
+        h[e] = xh;
+        md[e] = xm;
+        lo[e] = xl;
+      }
+      const int off = (r0 + rr) * kX3RP + k8;
+      *(bf16x8 *)(&Ls[op][0][off]) = h;
+      *(bf16x8 *)(&Ls[op][1][off]) = md;
+      *(bf16x8 *)(&Ls[op][2][off]) = lo;
+    }
+  };
+
+  f32x4 acc[8][4];
+#pragma unroll
+  for (int x = 0; x < 8; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) acc[x][y] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int wr = (wave >> 2) * 128, wc = (wave & 3) * 64;
+  const int lr = lane & 15, kq = (lane >> 4) * 8;
+
+  if (kb < ke) gload(kb);
+  for (int64_t k0 = kb; k0 < ke; k0 += kX3BK) {
+    __syncthreads();  // the previous stage's operands are consumed
+    lstore();
+    __syncthreads();
+    if (k0 + kX3BK < ke) gload(k0 + kX3BK);
+    // B operands of this wave's four column blocks (rows of operand 1)
+    bf16x8 b[4][3];
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+      for (int p = 0; p < 3; ++p)
+        b[nb][p] = *(const bf16x8 *)(&Ls[1][p][(wc + 16 * nb + lr) * kX3RP + kq]);
+#pragma unroll
+    for (int rb = 0; rb < 8; ++rb) {
+      bf16x8 av[3];
+#pragma unroll
+      for (int p = 0; p < 3; ++p) av[p] = *(const bf16x8 *)(&Ls[0][p][(wr + 16 * rb + lr) * kX3RP + kq]);
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) {
+        f32x4 c = acc[rb][nb];
+        // smallest terms first
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[1], b[nb][1], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[2], b[nb][0], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[0], b[nb][2], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[1], b[nb][0], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[0], b[nb][1], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[0], b[nb][0], c, 0, 0, 0);
+        acc[rb][nb] = c;
+      }
+    }
+  }
+  // D of block (rb, nb): lane holds column wc + 16 nb + (lane & 15), rows
+  // wr + 16 rb + 4 (lane >> 4) + v
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) {
+    const int64_t j = j0 + wc + 16 * nb + lr;
+    if (j >= m) continue;
+#pragma unroll
+    for (int rb = 0; rb < 8; ++rb) {
+      const int64_t i = i0 + wr + 16 * rb + 4 * (lane >> 4);
+      float *dst = Pout + j * ldp + i;
+      const f32x4 v = acc[rb][nb];
+      if (i + 3 < m) {
+        *(float4 *)dst = make_float4(v[0], v[1], v[2], v[3]);
+      } else {
+        if (i < m) dst[0] = v[0];
+        if (i + 1 < m) dst[1] = v[1];
+        if (i + 2 < m) dst[2] = v[2];
+      }
+    }
+  }
+}
+
 // C = sum_s P_s over the upper triangle, mirrored (exact symmetry).  One
 // workgroup per 64 x 64 tile (bi <= bj) of the upper part: partial sums are
 // read along the contiguous rows, the tile is written in place and, through
@@ -1379,6 +1748,15 @@ static hipError_t init_dt(const float *X, int64_t ldx, int64_t R, const AView &A
   }();
   if (big_ok && R >= 192 && A.n >= 1024) {
     const unsigned grid = (unsigned)((A.n + 255) / 256);
+    if (DT == DT_F32 && mfma_x3()) {
+      if (gram)
+        hipLaunchKernelGGL(k_init_x3<true>, dim3(grid), dim3(kI2Threads), 0, s, X, ldx, R, A, f0,
+                           g0, mask0);
+      else
+        hipLaunchKernelGGL(k_init_x3<false>, dim3(grid), dim3(kI2Threads), 0, s, X, ldx, R, A, f0,
+                           g0, mask0);
+      return hipGetLastError();
+    }
     if (gram)
       hipLaunchKernelGGL((k_init256<DT, true>), dim3(grid), dim3(kI2Threads), 0, s, X, ldx, R, A,
                          f0, g0, mask0);
@@ -1491,7 +1869,12 @@ hipError_t launch_gram(const AView &A, float *C, int64_t ldc, void *scratch, int
   const dim3 grid((unsigned)(nt * sp));
   if (pl.tile == 256) {
     switch (A.dtype) {
-      case DT_F32: hipLaunchKernelGGL((k_gemm256<DT_F32, 16, 0>), grid, dim3(kG2Threads), 0, s, A, nullptr, 0, P, ldp, pl.ntm, nt, kc, 0u, 0u, 0u); break;
+      case DT_F32:
+        if (mfma_x3())
+          hipLaunchKernelGGL(k_gram_x3, grid, dim3(kG2Threads), 0, s, A, P, ldp, nt, kc);
+        else
+          hipLaunchKernelGGL((k_gemm256<DT_F32, 16, 0>), grid, dim3(kG2Threads), 0, s, A, nullptr, 0, P, ldp, pl.ntm, nt, kc, 0u, 0u, 0u);
+        break;
       case DT_BF16: hipLaunchKernelGGL((k_gemm256<DT_BF16, 16, 0>), grid, dim3(kG2Threads), 0, s, A, nullptr, 0, P, ldp, pl.ntm, nt, kc, 0u, 0u, 0u); break;
       case DT_FP8: hipLaunchKernelGGL((k_gemm256<DT_FP8, 16, 0>), grid, dim3(kG2Threads), 0, s, A, nullptr, 0, P, ldp, pl.ntm, nt, kc, 0u, 0u, 0u); break;
       default: return hipErrorInvalidValue;

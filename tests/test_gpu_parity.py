@@ -77,6 +77,28 @@ def test_projection_quantized_storage(gpu, m, n, r, dt):
     assert np.max(np.abs(B - Bref) / scale) < 1e-6
 
 
+@pytest.mark.parametrize("m,n", [(300, 500), (601, 1333), (256, 4096)])
+def test_gram_binary32_matches_fp64(gpu, m, n):
+    """C = A A^T of binary32 A (large-tile path: bfloat16 matrix cores with
+    three-part operands) entry by entry against the FP64 product, exactly
+    symmetric.  Tolerance relative to sqrt(C_ii C_jj): binary32 accumulation
+    over n terms, 2^-24 sqrt(n) plus 1e-6 (the split's dropped products are
+    below 2^-23 |a b| each); measured 1.0e-6 - 1.5e-6 on these cases, against
+    2.0e-6 - 3.3e-6 for the binary32 matrix-core kernel."""
+    A = synth.gauss_lowrank_dense(m, n, 40, 0.1, seed=m)
+    A[:, 7] *= 1e-3                      # columns of very different scales
+    A[:, 9] *= 1e3
+    A32 = colstore32(A)
+    Av = stored_dense(A32, m)
+    s = gpu.Selector(dev(A32), m, k_max=4, self_target=True)
+    s.set_target(None)
+    C = s.read(gpu.STATE_GRAM, m * m, np.float32).reshape(m, m).astype(np.float64)
+    Cr = Av @ Av.T
+    assert np.array_equal(C, C.T)
+    scale = np.sqrt(np.outer(np.diag(Cr), np.diag(Cr)))
+    assert np.max(np.abs(C - Cr) / scale) <= 6e-8 * np.sqrt(n) + 1e-6
+
+
 @pytest.mark.parametrize("m,n,dt", [(300, 500, "bf16"), (257, 400, "fp8")])
 def test_gram_quantized_storage(gpu, m, n, dt):
     """C = A_hat A_hat^T from BF16 / FP8 codes (large-tile path), exactly symmetric."""
