@@ -612,14 +612,16 @@ __global__ __launch_bounds__(kI2Threads, 1) void k_init256(const float *__restri
 }
 
 // ---------------------------------------------------------------------------
-// Initial scores of binary32 A on the bfloat16 matrix cores: k_init256's
-// computation (f_j = ||X A_j||^2, or with TRI f_j = A_j^T (X + X^T) A_j / 2
-// for the symmetric X = C by its upper triangle) with both operands split
-// into three bfloat16 parts as in k_gram_x3 (six part products per binary32
-// product).  X rows and A columns both hold k contiguously, so a thread
-// loads eight consecutive k of one row or column and writes each plane with
-// one 16-byte LDS store.  One workgroup per 256 columns of A, all row chunks.
-template <bool TRI>
+// Initial scores on the bfloat16 matrix cores: k_init256's computation
+// (f_j = ||X A_j||^2, or with TRI f_j = A_j^T (X + X^T) A_j / 2 for the
+// symmetric X = C by its upper triangle).  X (binary32) is split into three
+// bfloat16 parts as in k_gram_x3; so is binary32 A (six part products per
+// product), while BF16 and FP8 codes are exact in one bfloat16 part (three
+// part products; the FP8 column scale enters f and g at the end).  X rows
+// and A columns both hold k contiguously, so a thread loads eight
+// consecutive k of one row or column and writes each plane with one 16-byte
+// LDS store.  One workgroup per 256 columns of A, all row chunks.
+template <bool TRI, int DT>
 __global__ __launch_bounds__(kI2Threads, 1) void k_init_x3(const float *__restrict__ X,
                                                            int64_t ldx, int64_t R, AView A,
                                                            double *__restrict__ f0,
@@ -637,12 +639,15 @@ __global__ __launch_bounds__(kI2Threads, 1) void k_init_x3(const float *__restri
   const int64_t m = A.m, n = A.n;
   const int64_t j0 = (int64_t)blockIdx.x * NT;
   const float *a = (const float *)A.a;
+  constexpr int ES = EInfo<DT>::esize;
+  constexpr int YP = DT == DT_F32 ? 3 : 1;  // bfloat16 parts of an A element
 
   // load tasks: task t (0..1023) of an operand = row / column t & 255, k group t >> 8
   // (partial sums live in LDS, keeping registers for the operands)
   for (int t = tid; t < 2 * NT; t += kI2Threads) red[t >> 8][t & 255] = 0.0;
   for (int t = tid; t < 4 * NT; t += kI2Threads) gpart[t >> 8][t & 255] = 0.0;
   float4 xr[2][2], yr[2][2];
+  uint4 yq[2];  // raw BF16 / FP8 codes: eight k of one column
 
   const int64_t nchunks = (R + RT - 1) / RT;
   for (int64_t rc = 0; rc < nchunks; ++rc) {
@@ -680,22 +685,39 @@ __global__ __launch_bounds__(kI2Threads, 1) void k_init_x3(const float *__restri
         xr[u][1] = make_float4(v[4], v[5], v[6], v[7]);
         // A column j0 + row, k gk .. gk + 7
         const int64_t gj = j0 + row;
-        if (gj < n && gk < m) {
-          const float *src = a + gj * A.lda + gk;
-          if (gk + 7 < m) {
-            const float4 p0 = *(const float4 *)src, p1 = *(const float4 *)(src + 4);
-            v[0] = p0.x; v[1] = p0.y; v[2] = p0.z; v[3] = p0.w;
-            v[4] = p1.x; v[5] = p1.y; v[6] = p1.z; v[7] = p1.w;
+        if constexpr (DT == DT_F32) {
+          if (gj < n && gk < m) {
+            const float *src = a + gj * A.lda + gk;
+            if (gk + 7 < m) {
+              const float4 p0 = *(const float4 *)src, p1 = *(const float4 *)(src + 4);
+              v[0] = p0.x; v[1] = p0.y; v[2] = p0.z; v[3] = p0.w;
+              v[4] = p1.x; v[5] = p1.y; v[6] = p1.z; v[7] = p1.w;
+            } else {
+#pragma unroll
+              for (int e = 0; e < 8; ++e) v[e] = gk + e < m ? src[e] : 0.f;
+            }
           } else {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) v[e] = gk + e < m ? src[e] : 0.f;
+            for (int e = 0; e < 8; ++e) v[e] = 0.f;
           }
+          yr[u][0] = make_float4(v[0], v[1], v[2], v[3]);
+          yr[u][1] = make_float4(v[4], v[5], v[6], v[7]);
         } else {
-#pragma unroll
-          for (int e = 0; e < 8; ++e) v[e] = 0.f;
+          // eight codes (16 or 8 bytes, inside the column's lda); elements
+          // past m are zeroed after decoding
+          const char *src = (const char *)A.a + (gj * A.lda + gk) * ES;
+          uint4 q = make_uint4(0u, 0u, 0u, 0u);
+          if (gj < n && gk < m) {
+            if constexpr (DT == DT_BF16) {
+              q = *(const uint4 *)src;
+            } else {
+              const uint2 w = *(const uint2 *)src;
+              q.x = w.x;
+              q.y = w.y;
+            }
+          }
+          yq[u] = q;
         }
-        yr[u][0] = make_float4(v[0], v[1], v[2], v[3]);
-        yr[u][1] = make_float4(v[4], v[5], v[6], v[7]);
       }
     };
     auto lstore = [&](int64_t k0) {
@@ -706,26 +728,50 @@ __global__ __launch_bounds__(kI2Threads, 1) void k_init_x3(const float *__restri
         const int off = row * kX3RP + kg;
 #pragma unroll
         for (int op = 0; op < 2; ++op) {
-          const float4 q0 = op == 0 ? xr[u][0] : yr[u][0], q1 = op == 0 ? xr[u][1] : yr[u][1];
-          float v[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+          float v[8];
+          if (op == 0 || DT == DT_F32) {
+            const float4 q0 = op == 0 ? xr[u][0] : yr[u][0], q1 = op == 0 ? xr[u][1] : yr[u][1];
+            v[0] = q0.x; v[1] = q0.y; v[2] = q0.z; v[3] = q0.w;
+            v[4] = q1.x; v[5] = q1.y; v[6] = q1.z; v[7] = q1.w;
+          } else if constexpr (DT == DT_BF16) {
+            const uint4 q = yq[u];
+            v[0] = bf16_lo(q.x); v[1] = bf16_hi(q.x); v[2] = bf16_lo(q.y); v[3] = bf16_hi(q.y);
+            v[4] = bf16_lo(q.z); v[5] = bf16_hi(q.z); v[6] = bf16_lo(q.w); v[7] = bf16_hi(q.w);
+          } else {
+            fp8x4_decode(yq[u].x, v);
+            fp8x4_decode(yq[u].y, v + 4);
+          }
+          if (op == 1 && DT != DT_F32) {
+            const int64_t gk = k0 + kg;
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+              if (gk + e >= m) v[e] = 0.f;
+          }
           if (TRI && op == 0) {
             // weights of the triangle: 1 above the diagonal, 1/2 on it, 0 below
             const int d0 = (int)(k0 + kg - (r0 + row));
 #pragma unroll
             for (int e = 0; e < 8; ++e) v[e] *= d0 + e > 0 ? 1.f : (d0 + e == 0 ? 0.5f : 0.f);
           }
-          bf16x8 h, md, lo;
+          if (op == 0 || DT == DT_F32) {
+            bf16x8 h, md, lo;
 #pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            __bf16 xh, xm, xl;
-            split3(v[e], xh, xm, xl);
-            h[e] = xh;
-            md[e] = xm;
-            lo[e] = xl;
+            for (int e = 0; e < 8; ++e) {
+              __bf16 xh, xm, xl;
+              split3(v[e], xh, xm, xl);
+              h[e] = xh;
+              md[e] = xm;
+              lo[e] = xl;
+            }
+            *(bf16x8 *)(&Ls[op][0][off]) = h;
+            *(bf16x8 *)(&Ls[op][1][off]) = md;
+            *(bf16x8 *)(&Ls[op][2][off]) = lo;
+          } else {
+            bf16x8 h;  // exact: BF16 and E4M3 values are bfloat16 numbers
+#pragma unroll
+            for (int e = 0; e < 8; ++e) h[e] = (__bf16)v[e];
+            *(bf16x8 *)(&Ls[op][0][off]) = h;
           }
-          *(bf16x8 *)(&Ls[op][0][off]) = h;
-          *(bf16x8 *)(&Ls[op][1][off]) = md;
-          *(bf16x8 *)(&Ls[op][2][off]) = lo;
           if (op == 1 && rc == 0) {
             double g = gpart[t >> 8][t & 255];
 #pragma unroll
@@ -743,11 +789,11 @@ __global__ __launch_bounds__(kI2Threads, 1) void k_init_x3(const float *__restri
       lstore(k0);
       __syncthreads();
       if (k0 + kX3BK < m) gload(k0 + kX3BK);
-      bf16x8 b[4][3];
+      bf16x8 b[4][YP];
 #pragma unroll
       for (int nb = 0; nb < 4; ++nb)
 #pragma unroll
-        for (int p = 0; p < 3; ++p)
+        for (int p = 0; p < YP; ++p)
           b[nb][p] = *(const bf16x8 *)(&Ls[1][p][(wc + 16 * nb + lr) * kX3RP + kq]);
 #pragma unroll
       for (int rb = 0; rb < 8; ++rb) {
@@ -757,12 +803,18 @@ __global__ __launch_bounds__(kI2Threads, 1) void k_init_x3(const float *__restri
 #pragma unroll
         for (int nb = 0; nb < 4; ++nb) {
           f32x4 c = acc[rb][nb];
-          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[1], b[nb][1], c, 0, 0, 0);
-          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[2], b[nb][0], c, 0, 0, 0);
-          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[0], b[nb][2], c, 0, 0, 0);
-          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[1], b[nb][0], c, 0, 0, 0);
-          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[0], b[nb][1], c, 0, 0, 0);
-          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[0], b[nb][0], c, 0, 0, 0);
+          if constexpr (YP == 3) {
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[1], b[nb][1], c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[2], b[nb][0], c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[0], b[nb][2], c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[1], b[nb][0], c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[0], b[nb][1], c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[0], b[nb][0], c, 0, 0, 0);
+          } else {
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[2], b[nb][0], c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[1], b[nb][0], c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[0], b[nb][0], c, 0, 0, 0);
+          }
           acc[rb][nb] = c;
         }
       }
@@ -783,7 +835,7 @@ __global__ __launch_bounds__(kI2Threads, 1) void k_init_x3(const float *__restri
           const float wj = j < n ? 1.f : 0.f;
           // one load in flight at a time: hoisting all 32 would spill the tile
           __builtin_amdgcn_sched_barrier(0);
-          const float4 av4 = *(const float4 *)(a + (j < n ? j : 0) * A.lda + ic);
+          const float4 av4 = load4<DT>(A.a, (j < n ? j : 0) * A.lda + ic);
           const float p = acc[rb][nb][0] * (av4.x * w0) + acc[rb][nb][1] * (av4.y * w1) +
                           acc[rb][nb][2] * (av4.z * w2) + acc[rb][nb][3] * (av4.w * w3);
           colacc[nb] += (double)(p * wj);
@@ -815,10 +867,12 @@ __global__ __launch_bounds__(kI2Threads, 1) void k_init_x3(const float *__restri
     if (j < n) {
       const double fv = red[0][tid] + red[1][tid];
       const double g = ((gpart[0][tid] + gpart[1][tid]) + gpart[2][tid]) + gpart[3][tid];
-      const double f = (TRI ? 2.0 : 1.0) * fv;
+      const double sc = col_scale(A, j);
+      const double f = (TRI ? 2.0 : 1.0) * sc * sc * fv;
+      const double gsc = sc * sc * g;
       f0[j] = f;
-      g0[j] = g;
-      mask0[j] = (g > 0.0 && isfinite(g) && isfinite(f)) ? 0 : 2;
+      g0[j] = gsc;
+      mask0[j] = (gsc > 0.0 && isfinite(gsc) && isfinite(f)) ? 0 : 2;
     }
   }
 }
@@ -1748,13 +1802,13 @@ static hipError_t init_dt(const float *X, int64_t ldx, int64_t R, const AView &A
   }();
   if (big_ok && R >= 192 && A.n >= 1024) {
     const unsigned grid = (unsigned)((A.n + 255) / 256);
-    if (DT == DT_F32 && mfma_x3()) {
+    if (mfma_x3()) {
       if (gram)
-        hipLaunchKernelGGL(k_init_x3<true>, dim3(grid), dim3(kI2Threads), 0, s, X, ldx, R, A, f0,
-                           g0, mask0);
+        hipLaunchKernelGGL((k_init_x3<true, DT>), dim3(grid), dim3(kI2Threads), 0, s, X, ldx, R, A,
+                           f0, g0, mask0);
       else
-        hipLaunchKernelGGL(k_init_x3<false>, dim3(grid), dim3(kI2Threads), 0, s, X, ldx, R, A, f0,
-                           g0, mask0);
+        hipLaunchKernelGGL((k_init_x3<false, DT>), dim3(grid), dim3(kI2Threads), 0, s, X, ldx, R, A,
+                           f0, g0, mask0);
       return hipGetLastError();
     }
     if (gram)
