@@ -1409,6 +1409,165 @@ __global__ __launch_bounds__(kG2Threads, 1) void k_gram_x3(AView A, float *__res
   }
 }
 
+// B = A Omega on the bfloat16 matrix cores: the tiles of k_gemm256's
+// projection (MODE 1), with Omega (binary32; an FP8 column scale of A is
+// folded into Omega's row) split into three bfloat16 parts and A into three
+// (binary32) or one (BF16 and FP8 codes are exact): six or three part
+// products per product, as in k_gram_x3.  Both operands are transposed on
+// their way into LDS (a thread loads four rows of A or four columns of
+// Omega for eight consecutive k) so that each plane row holds 32
+// consecutive k.  Needs m and r to be multiples of 4.
+template <int DT>
+__global__ __launch_bounds__(kG2Threads, 1) void k_proj_x3(AView A, const float *__restrict__ Om,
+                                                           int64_t r, float *__restrict__ P,
+                                                           int64_t ldp, int ntm, int ntile,
+                                                           int64_t kchunk) {
+  constexpr int AP = DT == DT_F32 ? 3 : 1;
+  constexpr int ES = EInfo<DT>::esize;
+  __shared__ __align__(16) __bf16 La[AP][kX3Plane];
+  __shared__ __align__(16) __bf16 Lo[3][kX3Plane];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t m = A.m, n = A.n;
+  const int64_t tile = blockIdx.x % ntile, split = blockIdx.x / ntile;
+  const int64_t i0 = (tile % ntm) * 256, j0 = (tile / ntm) * 256;
+  const int64_t kb = split * kchunk;
+  const int64_t ke = (kb + kchunk) < n ? (kb + kchunk) : n;
+  float *Pout = P + split * ldp * r;
+  const char *abase = (const char *)A.a;
+
+  // load task: op 0 -> rows i0 + q0 .. +3 of A, op 1 -> columns j0 + q0 .. +3
+  // of Omega, for k = k0 + k8 .. k0 + k8 + 7
+  const int op = tid >> 8, task = tid & 255;
+  const int q0 = (task & 63) * 4, k8 = (task >> 6) * 8;
+  float4 reg[8];
+  // (m and r are multiples of 4: four rows or columns are in or out together)
+  auto gload = [&](int64_t k0) {
+    const int64_t q = (op == 0 ? i0 : j0) + q0;
+    const bool inq = q < (op == 0 ? m : r);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int64_t k = k0 + k8 + e;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (inq && k < ke) {
+        if (op == 0) {
+          const char *src = abase + (k * A.lda + q) * ES;
+          if constexpr (DT == DT_F32) {
+            v = *(const float4 *)src;
+          } else if constexpr (DT == DT_BF16) {
+            const uint2 w = *(const uint2 *)src;
+            v = make_float4(bf16_lo(w.x), bf16_hi(w.x), bf16_lo(w.y), bf16_hi(w.y));
+          } else {
+            float d[4];
+            fp8x4_decode(*(const uint32_t *)src, d);
+            v = make_float4(d[0], d[1], d[2], d[3]);
+          }
+        } else {
+          v = *(const float4 *)(Om + k * r + q);
+          if constexpr (DT == DT_FP8) {
+            const float sk = A.scale[k];
+            v.x *= sk;
+            v.y *= sk;
+            v.z *= sk;
+            v.w *= sk;
+          }
+        }
+      }
+      reg[e] = v;
+    }
+  };
+  auto lstore = [&]() {
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      float x[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        x[e] = rr == 0 ? reg[e].x : rr == 1 ? reg[e].y : rr == 2 ? reg[e].z : reg[e].w;
+      const int off = (q0 + rr) * kX3RP + k8;
+      if (op == 1 || AP == 3) {
+        bf16x8 h, md, lo;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          __bf16 xh, xm, xl;
+          split3(x[e], xh, xm, xl);
+          h[e] = xh;
+          md[e] = xm;
+          lo[e] = xl;
+        }
+        __bf16 *base = op == 0 ? &La[0][0] : &Lo[0][0];
+        *(bf16x8 *)(base + off) = h;
+        *(bf16x8 *)(base + kX3Plane + off) = md;
+        *(bf16x8 *)(base + 2 * kX3Plane + off) = lo;
+      } else {
+        bf16x8 h;  // BF16 and E4M3 values are bfloat16 numbers
+#pragma unroll
+        for (int e = 0; e < 8; ++e) h[e] = (__bf16)x[e];
+        *(bf16x8 *)(&La[0][off]) = h;
+      }
+    }
+  };
+
+  f32x4 acc[8][4];
+#pragma unroll
+  for (int x = 0; x < 8; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) acc[x][y] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int wr = (wave >> 2) * 128, wc = (wave & 3) * 64;
+  const int lr = lane & 15, kq = (lane >> 4) * 8;
+
+  if (kb < ke) gload(kb);
+  for (int64_t k0 = kb; k0 < ke; k0 += kX3BK) {
+    __syncthreads();  // the previous stage's operands are consumed
+    lstore();
+    __syncthreads();
+    if (k0 + kX3BK < ke) gload(k0 + kX3BK);
+    bf16x8 b[4][3];
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+      for (int p = 0; p < 3; ++p) b[nb][p] = *(const bf16x8 *)(&Lo[p][(wc + 16 * nb + lr) * kX3RP + kq]);
+#pragma unroll
+    for (int rb = 0; rb < 8; ++rb) {
+      bf16x8 av[AP];
+#pragma unroll
+      for (int p = 0; p < AP; ++p) av[p] = *(const bf16x8 *)(&La[p][(wr + 16 * rb + lr) * kX3RP + kq]);
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) {
+        f32x4 c = acc[rb][nb];
+        if constexpr (AP == 3) {
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[1], b[nb][1], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[2], b[nb][0], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[0], b[nb][2], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[1], b[nb][0], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[0], b[nb][1], c, 0, 0, 0);
+        } else {
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[0], b[nb][2], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[0], b[nb][1], c, 0, 0, 0);
+        }
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[0], b[nb][0], c, 0, 0, 0);
+        acc[rb][nb] = c;
+      }
+    }
+  }
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) {
+    const int64_t j = j0 + wc + 16 * nb + lr;
+    if (j >= r) continue;
+#pragma unroll
+    for (int rb = 0; rb < 8; ++rb) {
+      const int64_t i = i0 + wr + 16 * rb + 4 * (lane >> 4);
+      float *dst = Pout + j * ldp + i;
+      const f32x4 v = acc[rb][nb];
+      if (i + 3 < m) {
+        *(float4 *)dst = make_float4(v[0], v[1], v[2], v[3]);
+      } else {
+        if (i < m) dst[0] = v[0];
+        if (i + 1 < m) dst[1] = v[1];
+        if (i + 2 < m) dst[2] = v[2];
+      }
+    }
+  }
+}
+
 // C = sum_s P_s over the upper triangle, mirrored (exact symmetry).  One
 // workgroup per 64 x 64 tile (bi <= bj) of the upper part: partial sums are
 // read along the contiguous rows, the tile is written in place and, through
@@ -2036,6 +2195,14 @@ hipError_t launch_project(const AView &A, const float *omega, int64_t r, float *
   const int64_t kc = pl.kchunk;
   const dim3 grid((unsigned)(nt * sp));
   if (pl.tile == 256) {
+    if (mfma_x3() && A.m % 4 == 0 && r % 4 == 0) {
+      switch (A.dtype) {
+        case DT_F32: hipLaunchKernelGGL(k_proj_x3<DT_F32>, grid, dim3(kG2Threads), 0, s, A, omega, r, P, ldp, tm, nt, kc); break;
+        case DT_BF16: hipLaunchKernelGGL(k_proj_x3<DT_BF16>, grid, dim3(kG2Threads), 0, s, A, omega, r, P, ldp, tm, nt, kc); break;
+        case DT_FP8: hipLaunchKernelGGL(k_proj_x3<DT_FP8>, grid, dim3(kG2Threads), 0, s, A, omega, r, P, ldp, tm, nt, kc); break;
+        default: return hipErrorInvalidValue;
+      }
+    } else
     switch (A.dtype) {
       case DT_F32: hipLaunchKernelGGL((k_gemm256<DT_F32, 16, 1>), grid, dim3(kG2Threads), 0, s, A, omega, r, P, ldp, tm, nt, kc, 0u, 0u, 0u); break;
       case DT_BF16: hipLaunchKernelGGL((k_gemm256<DT_BF16, 16, 1>), grid, dim3(kG2Threads), 0, s, A, omega, r, P, ldp, tm, nt, kc, 0u, 0u, 0u); break;
