@@ -142,6 +142,22 @@ def cpu_baseline(w, A32, Om, target_seconds=15.0):
             "kind": "oracle", "sample": desc, "seconds": round(t, 3)}
 
 
+def hbm_probe(args):
+    """Achievable HBM read rate: the library's read-only pass over a 4 GiB
+    buffer (beyond the 256 MB Infinity Cache), mean of 10 passes."""
+    if args.no_probe:
+        return None
+    import torch
+
+    import paper_1312_6838_amd as g
+    buf = torch.zeros(4 << 30, dtype=torch.uint8, device="cuda")
+    sec, _ = g.hbm_probe_tensor(buf, reps=10)
+    rate = buf.numel() / sec / 1e9
+    del buf
+    return {"kernel": "k_hbm_read", "achieved": round(rate, 1), "unit": "GB/s",
+            "buffer_bytes": 4 << 30, "passes": 10, "frac_of_peak": round(rate / HBM_PEAK_GBS, 4)}
+
+
 def bench_batched(args, w, A, scales, Om, dtype):
     """Algorithm 4 on one GPU: all blocks in one lockstep graph, then the merge;
     against the same blocks solved one after another with the single-problem path."""
@@ -183,6 +199,11 @@ def bench_batched(args, w, A, scales, Om, dtype):
         s0.select(min(km, len(picks)))
         s0.close()
 
+    tuning = None
+    if not args.no_tune:
+        log("[bench] autotuning the batched pass")
+        sel.project_target(Om)
+        tuning = sel.autotune_batched(off, kb, km, reps=3, cache=args.tune_cache)
     for _ in range(args.warmup):
         step()
         step_seq()
@@ -228,6 +249,7 @@ def bench_batched(args, w, A, scales, Om, dtype):
         "config": {"workload": args.workload, "m": m, "n": n, "blocks": nb, "k_block": kb,
                    "k_merge": km, "target": f"B = A Omega, r = {r}", "a_storage": dtype},
         "roofline": None,
+        "tuning": tuning,
         "naive_distributed": naive,
         "block_sequential": {"ms_per_step": round(ms_s, 3),
                              "value": updates / (ms_s / 1e3),
@@ -269,6 +291,13 @@ def main():
     ap.add_argument("--rank-k", type=int, default=0, metavar="K",
                     help="with --embedding: time one rank-K approximation in the span of "
                          "the picks after the timed steps")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default launch setting of the streaming passes instead of "
+                         "autotuning it before the warm-up")
+    ap.add_argument("--tune-cache", default=os.environ.get("GCSS_TUNE_CACHE"),
+                    help="JSON file of tuned settings (default $GCSS_TUNE_CACHE, else none)")
+    ap.add_argument("--no-probe", action="store_true",
+                    help="skip the HBM read probe (achievable bandwidth ceiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run one device-to-device copy of BYTES bytes (scales the "
                          "HBM traffic counters of a profiling run)")
@@ -327,6 +356,11 @@ def main():
         err = sel.reconstruction_error(idx[:ns])
         state.update(idx=idx, obj=obj, ns=ns, err=err)
 
+    tuning = None
+    if not args.no_tune:
+        log("[bench] autotuning the streaming pass")
+        make_target()
+        tuning = sel.autotune(min(k, 32), reps=3, cache=args.tune_cache)
     log(f"[bench] warmup x{args.warmup}")
     for _ in range(args.warmup):
         step()
@@ -405,6 +439,10 @@ def main():
             "bytes_per_launch": bytes_launch, "avg_launch_ms": round(avg_ms, 5),
             "launches_timed": prof["stream_launches"]}
 
+    probe = hbm_probe(args)
+    if probe:
+        probe["stream_frac_of_probe"] = round(achieved / probe["achieved"], 4)
+
     out = {
         "metric": METRIC, "value": value, "unit": "score updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
@@ -415,6 +453,8 @@ def main():
                    "a_storage": dtype, "embedding": bool(args.embedding),
                    "omega": None if self_target else args.omega},
         "roofline": roof,
+        "hbm_probe": probe,
+        "tuning": tuning,
         "loop_only": {"score_updates_per_s": n * k / (prof["loop_ms"] / max(prof["selects"], 1) * 1e-3)
                       if prof["selects"] else None,
                       "loop_ms": round(prof["loop_ms"] / max(prof["selects"], 1), 3)},

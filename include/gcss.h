@@ -367,6 +367,82 @@ gcss_status gcss_set_profiling(gcss_ctx *h, int32_t enable);
 /* Read the counters (host struct).  Errors: GCSS_ERR_ARG. */
 gcss_status gcss_get_profile(gcss_ctx *h, gcss_profile *out);
 
+/*
+ * Launch settings of the streaming passes (the step that reads all of A once
+ * per pick).  They set how the work is spread over the chip, never what is
+ * computed: indices, scores and explicit-target objectives are bitwise the
+ * same under every setting.  Under the Gram target (B = A) the objective's
+ * decrements are FP64 sums of per-workgroup partials, whose grouping follows
+ * the setting, so they can differ in the last bits.
+ */
+typedef struct {
+  int32_t stream_pd;        /* column groups loaded ahead of the one being reduced: 1 or 2 (default 1) */
+  int32_t stream_upw;       /* work units per workgroup that the unit size aims at: 1..64 (default 4) */
+  int32_t batch_group;      /* columns per group of the batched pass: 16, 32 or 64 (default 64)     */
+  int32_t batch_wg_per_cu;  /* resident workgroups per CU of the batched pass; 0 = all that fit     */
+} gcss_tuning;
+
+/* Current setting of a context (host struct).  Errors: GCSS_ERR_ARG. */
+gcss_status gcss_get_tuning(gcss_ctx *h, gcss_tuning *out);
+
+/* Apply a setting (host struct).  Synchronizes the stream and drops the
+ * captured loops, which the next select_async / select_batched captures
+ * again.  Errors: GCSS_ERR_ARG (a field out of range), GCSS_ERR_DEVICE. */
+gcss_status gcss_set_tuning(gcss_ctx *h, const gcss_tuning *t);
+
+/* Outcome of an autotuning call (host struct). */
+typedef struct {
+  gcss_tuning best;     /* the setting chosen, left applied to the context             */
+  double best_ms;       /* its median time per timed call, milliseconds                */
+  double initial_ms;    /* the same for the setting the context had on entry (0 when
+                           the setting came from the cache)                             */
+  int32_t candidates;   /* settings timed; 0 when the setting came from the cache       */
+} gcss_tune_result;
+
+/*
+ * Autotuner for gcss_select: times gcss_select(h, k) under each candidate
+ * setting (stream_pd in {1, 2} x stream_upw in {2, 4, 8, 16}, and the entry
+ * setting), one untimed call then `reps` calls each bracketed by HIP events
+ * on the context's stream, and applies the setting with the lowest median.
+ * cache_path (host string, may be NULL): a JSON file of settings keyed by
+ * device architecture, m, ceil(log2 n), storage type and target kind; a
+ * cached setting is applied without timing, and a new result is added to the
+ * file (written to a temporary file, then renamed over it).  Needs a target
+ * (GCSS_ERR_STATE otherwise).  Leaves the context as after gcss_select(h, k).
+ * Errors: GCSS_ERR_ARG (k, reps, an unreadable or malformed cache file),
+ * GCSS_ERR_STATE, GCSS_ERR_DEVICE.  Synchronizes the stream.
+ */
+gcss_status gcss_autotune_select(gcss_ctx *h, int32_t k, int32_t reps, const char *cache_path,
+                                 gcss_tune_result *out);
+
+/*
+ * Autotuner for gcss_select_batched (the one captured launch of Algorithm 4's
+ * per-block selections): times that call with the given blocks and budgets
+ * under batch_group in {16, 32, 64} x batch_wg_per_cu in {0, 2, 4} (and the
+ * entry setting), as gcss_autotune_select does; the cache key adds the block
+ * count.  Same arguments and errors as gcss_select_batched plus those of
+ * gcss_autotune_select.
+ */
+gcss_status gcss_autotune_batched(gcss_ctx *h, int32_t nblocks, const int64_t *col_off,
+                                  int32_t k_block, int32_t k_merge, int32_t reps,
+                                  const char *cache_path, gcss_tune_result *out);
+
+/*
+ * Achievable HBM read bandwidth: times `reps` read-only passes over buf
+ * (device, 16-byte aligned, bytes a positive multiple of 16; borrowed) with
+ * the streaming pass's access pattern, after one untimed pass, between HIP
+ * events on `stream` (hipStream_t, NULL = default), and returns the mean time
+ * of one pass in *seconds (host).  bytes / *seconds is the practical ceiling
+ * of a pass that reads each byte once.  sink: device, GCSS_PROBE_SINK_FLOATS
+ * floats; the call zeroes it, then workgroup b stores the XOR of the 32-bit
+ * words it read as the bit pattern of sink[b], so the XOR of all entries is
+ * the XOR of every word of buf.  Errors: GCSS_ERR_ARG, GCSS_ERR_DEVICE.
+ * Synchronizes the stream.
+ */
+#define GCSS_PROBE_SINK_FLOATS 4096
+gcss_status gcss_hbm_probe(const void *buf, size_t bytes, float *sink, int32_t reps, void *stream,
+                           double *seconds);
+
 /* Message for the last non-OK status returned on this thread ("" if none). */
 const char *gcss_last_error(void);
 

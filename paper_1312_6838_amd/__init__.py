@@ -18,10 +18,12 @@ from ._abi import (  # noqa: F401
     last_error, load, make_desc, project_target, quantize, read_state, reconstruction_error,
     select, select_async, select_batched, set_target, version, workspace_size,
     set_profiling, get_profile, set_embedding, qless_r, rank_k, project_sign, top_eig,
-    gather_columns,
+    gather_columns, get_tuning, set_tuning, autotune_select, autotune_batched, hbm_probe,
+    PROBE_SINK_FLOATS,
 )
 
-__all__ = ["Selector", "quantize_tensor", "qless_r_tensor", "load", "version", "GcssError"]
+__all__ = ["Selector", "quantize_tensor", "qless_r_tensor", "hbm_probe_tensor", "load",
+           "version", "GcssError"]
 
 
 def _dtype_code(t):
@@ -204,6 +206,24 @@ class Selector:
         raw = read_state(self.h, item, int(count) * np.dtype(np_dtype).itemsize)
         return np.frombuffer(raw, dtype=np_dtype).copy()
 
+    def tuning(self, **setting):
+        """Read the streaming passes' launch setting, or change some of its
+        fields (stream_pd, stream_upw, batch_group, batch_wg_per_cu)."""
+        if setting:
+            cur = get_tuning(self.h)
+            cur.update(setting)
+            set_tuning(self.h, cur["stream_pd"], cur["stream_upw"], cur["batch_group"],
+                       cur["batch_wg_per_cu"])
+        return get_tuning(self.h)
+
+    def autotune(self, k, reps=3, cache=None):
+        """Time select(k) under each candidate launch setting and keep the
+        fastest (cache: JSON path or None).  Returns the tuner's result."""
+        return autotune_select(self.h, int(k), int(reps), cache)
+
+    def autotune_batched(self, col_off, k_block, k_merge, reps=3, cache=None):
+        return autotune_batched(self.h, col_off, int(k_block), int(k_merge), int(reps), cache)
+
     def profile(self, enable=None):
         """Turn stream-kernel event timing on/off (clears counters), or read them."""
         if enable is not None:
@@ -220,6 +240,19 @@ class Selector:
             self.close()
         except Exception:
             pass
+
+
+def hbm_probe_tensor(buf, reps=5, stream=None):
+    """Mean seconds of one read pass over a cuda tensor's bytes, and the sink
+    (uint32 cuda tensor whose XOR over all entries is the XOR of the buffer's
+    32-bit words)."""
+    import torch
+    if not buf.is_cuda or not buf.is_contiguous():
+        raise ValueError("buf must be a contiguous cuda tensor")
+    sink = torch.empty(PROBE_SINK_FLOATS, dtype=torch.int32, device=buf.device)
+    sec = hbm_probe(buf.data_ptr(), buf.numel() * buf.element_size(), sink.data_ptr(), int(reps),
+                    _stream_ptr(stream))
+    return sec, sink
 
 
 def qless_r_tensor(W, n, idx, stream=None):

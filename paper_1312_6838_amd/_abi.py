@@ -32,8 +32,11 @@ EXPORTS = [
     "gcss_select_batched", "gcss_batched_workspace_size", "gcss_quantize", "gcss_read_state",
     "gcss_last_error", "gcss_version", "gcss_set_profiling", "gcss_get_profile",
     "gcss_set_embedding", "gcss_qless_r", "gcss_rank_k", "gcss_project_sign", "gcss_top_eig",
-    "gcss_gather_columns",
+    "gcss_gather_columns", "gcss_get_tuning", "gcss_set_tuning", "gcss_autotune_select",
+    "gcss_autotune_batched", "gcss_hbm_probe",
 ]
+
+PROBE_SINK_FLOATS = 4096
 
 
 class GcssError(RuntimeError):
@@ -54,6 +57,16 @@ class Desc(ctypes.Structure):
 class Profile(ctypes.Structure):
     _fields_ = [("stream_launches", ctypes.c_int64), ("stream_ms", ctypes.c_double),
                 ("selects", ctypes.c_int64), ("loop_ms", ctypes.c_double)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("stream_pd", ctypes.c_int32), ("stream_upw", ctypes.c_int32),
+                ("batch_group", ctypes.c_int32), ("batch_wg_per_cu", ctypes.c_int32)]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("best", Tuning), ("best_ms", ctypes.c_double), ("initial_ms", ctypes.c_double),
+                ("candidates", ctypes.c_int32)]
 
 
 _lib = None
@@ -111,6 +124,17 @@ def load():
     lib.gcss_set_profiling.restype = st
     lib.gcss_get_profile.argtypes = [_vp, _P(Profile)]
     lib.gcss_get_profile.restype = st
+    lib.gcss_get_tuning.argtypes = [_vp, _P(Tuning)]
+    lib.gcss_get_tuning.restype = st
+    lib.gcss_set_tuning.argtypes = [_vp, _P(Tuning)]
+    lib.gcss_set_tuning.restype = st
+    lib.gcss_autotune_select.argtypes = [_vp, _i32, _i32, ctypes.c_char_p, _P(TuneResult)]
+    lib.gcss_autotune_select.restype = st
+    lib.gcss_autotune_batched.argtypes = [_vp, _i32, _vp, _i32, _i32, _i32, ctypes.c_char_p,
+                                          _P(TuneResult)]
+    lib.gcss_autotune_batched.restype = st
+    lib.gcss_hbm_probe.argtypes = [_vp, _sz, _vp, _i32, _vp, _P(_dbl)]
+    lib.gcss_hbm_probe.restype = st
     lib.gcss_last_error.argtypes = []
     lib.gcss_last_error.restype = ctypes.c_char_p
     lib.gcss_version.argtypes = []
@@ -267,3 +291,49 @@ def get_profile(h: int) -> dict:
     _check(load().gcss_get_profile(h, ctypes.byref(p)))
     return dict(stream_launches=p.stream_launches, stream_ms=p.stream_ms, selects=p.selects,
                 loop_ms=p.loop_ms)
+
+
+def _tuning_dict(t: Tuning) -> dict:
+    return dict(stream_pd=t.stream_pd, stream_upw=t.stream_upw, batch_group=t.batch_group,
+                batch_wg_per_cu=t.batch_wg_per_cu)
+
+
+def get_tuning(h: int) -> dict:
+    t = Tuning()
+    _check(load().gcss_get_tuning(h, ctypes.byref(t)))
+    return _tuning_dict(t)
+
+
+def set_tuning(h: int, stream_pd: int, stream_upw: int, batch_group: int,
+               batch_wg_per_cu: int) -> None:
+    t = Tuning(stream_pd, stream_upw, batch_group, batch_wg_per_cu)
+    _check(load().gcss_set_tuning(h, ctypes.byref(t)))
+
+
+def _result_dict(r: TuneResult) -> dict:
+    return dict(best=_tuning_dict(r.best), best_ms=r.best_ms, initial_ms=r.initial_ms,
+                candidates=r.candidates)
+
+
+def autotune_select(h: int, k: int, reps: int, cache_path: str | None) -> dict:
+    r = TuneResult()
+    path = cache_path.encode() if cache_path else None
+    _check(load().gcss_autotune_select(h, k, reps, path, ctypes.byref(r)))
+    return _result_dict(r)
+
+
+def autotune_batched(h: int, col_off, k_block: int, k_merge: int, reps: int,
+                     cache_path: str | None) -> dict:
+    col_off = np.ascontiguousarray(np.asarray(col_off, dtype=np.int64))
+    r = TuneResult()
+    path = cache_path.encode() if cache_path else None
+    _check(load().gcss_autotune_batched(h, col_off.size - 1, col_off.ctypes.data, k_block,
+                                        k_merge, reps, path, ctypes.byref(r)))
+    return _result_dict(r)
+
+
+def hbm_probe(buf_ptr: int, nbytes: int, sink_ptr: int, reps: int, stream: int = 0) -> float:
+    """-> mean seconds of one read pass over the buffer"""
+    sec = ctypes.c_double(0.0)
+    _check(load().gcss_hbm_probe(buf_ptr, nbytes, sink_ptr, reps, stream, ctypes.byref(sec)))
+    return sec.value

@@ -194,6 +194,8 @@ struct gcss_ctx {
   std::vector<hipEvent_t> ev;  // pairs around stream launches, then the loop pair
   size_t ev_used = 0;
   gcss_profile prof{};
+  // launch settings of the streaming passes
+  gcss_tuning tune{};
   // captured loop
   hipGraphExec_t graph = nullptr;
   int graph_k = -1;
@@ -228,6 +230,29 @@ void drop_graph(gcss_ctx *h) {
   if (h->graph) (void)hipGraphExecDestroy(h->graph);
   h->graph = nullptr;
   h->graph_k = -1;
+}
+
+const char *tuning_error(const gcss_tuning &t) {
+  if (t.stream_pd != 1 && t.stream_pd != 2) return "stream_pd must be 1 or 2";
+  if (t.stream_upw < 1 || t.stream_upw > 64) return "stream_upw must be in 1..64";
+  if (t.batch_group != 16 && t.batch_group != 32 && t.batch_group != 64)
+    return "batch_group must be 16, 32 or 64";
+  if (t.batch_wg_per_cu < 0 || t.batch_wg_per_cu > 64) return "batch_wg_per_cu must be in 0..64";
+  return nullptr;
+}
+
+// Streaming-pass geometry under a launch setting: the shape follows from m
+// and the storage type, the grid and the unit size from the setting and the
+// kernel's occupancy.
+hipError_t tuned_geometry(const gcss_desc *d, int num_cu, const gcss_tuning &t, StreamGeo *out) {
+  StreamGeo geo = stream_geometry(d->m, d->n, d->a_dtype, num_cu);
+  if (geo.nj == 0) return hipErrorInvalidValue;
+  geo.pd = t.stream_pd;
+  geo.upw = t.stream_upw;
+  geo.g = t.batch_group;
+  hipError_t e = stream_finalize(geo, d->n, d->a_dtype, num_cu);
+  if (e == hipSuccess) *out = geo;
+  return e;
 }
 
 // Gram-Schmidt of column p (state) against the basis, with one re-orthogonalisation.
@@ -375,17 +400,18 @@ gcss_status gcss_create(const gcss_desc *d, void *workspace, size_t ws_bytes, gc
   if (ws_bytes < L.total)
     return fail(GCSS_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
 
-  // streaming-pass tunables: column group size of the batched pass, the
-  // load-group prefetch depth and the work units per workgroup; then size the
+  // launch settings of the streaming passes: defaults, which the environment
+  // (GCSS_STREAM_PD, GCSS_STREAM_UPW, GCSS_STREAM_G) may override, then the
   // grid and the unit from the kernel's occupancy
+  gcss_tuning tune{1, 4, 64, 0};
   if (const char *v = getenv("GCSS_STREAM_G")) {
     const int gsz = atoi(v);
-    if (gsz == 16 || gsz == 32 || gsz == 64) L.geo.g = gsz;
+    if (gsz == 16 || gsz == 32 || gsz == 64) tune.batch_group = gsz;
   }
-  if (const char *v = getenv("GCSS_STREAM_PD")) L.geo.pd = atoi(v) >= 2 ? 2 : 1;
-  if (const char *v = getenv("GCSS_STREAM_UPW")) L.geo.upw = std::max(1, atoi(v));
+  if (const char *v = getenv("GCSS_STREAM_PD")) tune.stream_pd = atoi(v) >= 2 ? 2 : 1;
+  if (const char *v = getenv("GCSS_STREAM_UPW")) tune.stream_upw = std::min(64, std::max(1, atoi(v)));
   {
-    hipError_t fe = stream_finalize(L.geo, d->n, d->a_dtype, num_cu);
+    hipError_t fe = tuned_geometry(d, num_cu, tune, &L.geo);
     if (fe != hipSuccess) return fail(GCSS_ERR_DEVICE, "stream kernel occupancy: %s", hipGetErrorString(fe));
   }
 
@@ -396,6 +422,7 @@ gcss_status gcss_create(const gcss_desc *d, void *workspace, size_t ws_bytes, gc
   h->d = *d;
   if (!(h->d.tau > 0.0)) h->d.tau = 1e-4;
   h->L = L;
+  h->tune = tune;
   h->ws = (char *)workspace;
   h->ws_bytes = ws_bytes;
   h->A.a = d->a;
@@ -978,7 +1005,8 @@ gcss_status gcss_select_batched(gcss_ctx *h, int32_t nblocks, const int64_t *col
     h->bk = k_block;
   }
   int grid = 1;
-  HIPCHK(batched_stream_grid(h->L.geo, h->d.a_dtype, h->num_cu, (int64_t)h->bgroups.size(), &grid));
+  HIPCHK(batched_stream_grid(h->L.geo, h->d.a_dtype, h->num_cu, (int64_t)h->bgroups.size(),
+                             h->tune.batch_wg_per_cu, &grid));
 
   // lockstep loop of all blocks, captured once and replayed
   if (!h->bgraph) {
@@ -1141,4 +1169,77 @@ gcss_status gcss_read_state(gcss_ctx *h, int32_t item, void *host, size_t bytes,
   return GCSS_OK;
 }
 
+gcss_status gcss_get_tuning(gcss_ctx *h, gcss_tuning *out) {
+  if (check_ctx(h)) return GCSS_ERR_ARG;
+  if (!out) return fail(GCSS_ERR_ARG, "null tuning");
+  *out = h->tune;
+  return GCSS_OK;
+}
+
+gcss_status gcss_set_tuning(gcss_ctx *h, const gcss_tuning *t) {
+  if (check_ctx(h)) return GCSS_ERR_ARG;
+  if (!t) return fail(GCSS_ERR_ARG, "null tuning");
+  if (const char *why = tuning_error(*t)) return fail(GCSS_ERR_ARG, "%s", why);
+  StreamGeo geo{};
+  hipError_t e = tuned_geometry(&h->d, h->num_cu, *t, &geo);
+  if (e != hipSuccess) return fail(GCSS_ERR_DEVICE, "stream kernel occupancy: %s", hipGetErrorString(e));
+  // captured loops hold the old grid and group table
+  HIPCHK(hipStreamSynchronize(h->stream));
+  drop_graph(h);
+  if (h->bgraph) (void)hipGraphExecDestroy(h->bgraph);
+  h->bgraph = nullptr;
+  h->L.geo = geo;
+  h->tune = *t;
+  return GCSS_OK;
+}
+
+static_assert(GCSS_PROBE_SINK_FLOATS == kProbeSinkFloats, "probe sink size");
+
+gcss_status gcss_hbm_probe(const void *buf, size_t bytes, float *sink, int32_t reps, void *stream,
+                           double *seconds) {
+  if (!buf || !sink || !seconds) return fail(GCSS_ERR_ARG, "null argument");
+  if (((uintptr_t)buf) % 16 || bytes < 16 || bytes % 16) return fail(GCSS_ERR_ARG, "buffer must be 16-byte aligned, a positive multiple of 16 bytes");
+  if (reps < 1) return fail(GCSS_ERR_ARG, "reps must be positive");
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, dev));
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(GCSS_ERR_DEVICE, "device %d is %s, not gfx950", dev, prop.gcnArchName);
+  hipStream_t s = (hipStream_t)stream;
+  const int grid = hbm_probe_grid((int64_t)bytes, prop.multiProcessorCount);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  hipError_t e = hipEventCreate(&e1);
+  if (!e) e = launch_zero_f32(sink, kProbeSinkFloats, s);
+  if (!e) e = launch_hbm_probe(buf, (int64_t)bytes, sink, grid, s);  // untimed first pass
+  if (!e) e = hipEventRecord(e0, s);
+  for (int i = 0; !e && i < reps; ++i) e = launch_hbm_probe(buf, (int64_t)bytes, sink, grid, s);
+  if (!e) e = hipEventRecord(e1, s);
+  if (!e) e = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (!e) e = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (e) return fail(GCSS_ERR_DEVICE, "hbm probe: %s", hipGetErrorString(e));
+  *seconds = (double)ms * 1e-3 / reps;
+  return GCSS_OK;
+}
+
 }  // extern "C"
+
+namespace gcss {
+
+void set_error(const char *msg) { g_err = msg ? msg : ""; }
+
+bool ctx_describe(gcss_ctx *h, CtxInfo *out) {
+  if (!h || !out) return false;
+  out->stream = h->stream;
+  out->m = h->d.m;
+  out->n = h->d.n;
+  out->dtype = h->d.a_dtype;
+  out->target = h->target;
+  return true;
+}
+
+}  // namespace gcss

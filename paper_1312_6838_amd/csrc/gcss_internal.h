@@ -6,6 +6,8 @@
 #include <stdint.h>
 #include <stddef.h>
 
+struct gcss_ctx;  // the C ABI's context (gcss_api.hip)
+
 namespace gcss {
 
 // Element codes of the stored source matrix (same values as gcss_dtype).
@@ -267,8 +269,10 @@ struct GroupEnt {
   int32_t ncol;
   int32_t blk;
 };
+// grid = resident workgroups per CU (at most wg_per_cu when > 0) x CUs, at
+// most one per team of groups
 hipError_t batched_stream_grid(const StreamGeo &geo, int dtype, int num_cu, int64_t ngroups,
-                               int *grid);
+                               int wg_per_cu, int *grid);
 hipError_t launch_stream_batched(const StreamGeo &geo, int grid, const AView &A,
                                  const GroupEnt *groups, int64_t ngroups, const float *q32,
                                  const float *z32, int64_t qstride, double *f, double *g,
@@ -284,5 +288,21 @@ hipError_t launch_batch_begin(const double *f0, const double *g0, const uint8_t 
                               const double *F0, double tau, uint32_t *bcnt, hipStream_t s);
 hipError_t launch_gather_cols(const AView &A, const int64_t *pick, int64_t npick, void *a0,
                               float *scale0, hipStream_t s);
+
+// ---- context facts the autotuner keys its cache on (gcss_api.hip) ----
+struct CtxInfo {
+  hipStream_t stream;
+  int64_t m, n;
+  int dtype;
+  int target;  // 0 none, 1 explicit B, 2 Gram (B = A)
+};
+bool ctx_describe(gcss_ctx *h, CtxInfo *out);
+// Message gcss_last_error() returns on this thread.
+void set_error(const char *msg);
+
+// ---- HBM read probe (k_probe.hip) ----
+constexpr int kProbeSinkFloats = 4096;  // largest grid, one sink entry per workgroup
+int hbm_probe_grid(int64_t bytes, int num_cu);
+hipError_t launch_hbm_probe(const void *buf, int64_t bytes, float *sink, int grid, hipStream_t s);
 
 }  // namespace gcss

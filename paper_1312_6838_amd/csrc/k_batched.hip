@@ -381,12 +381,13 @@ static BStreamFn bpick(int dtype, int nj, int w) {
 }
 
 hipError_t batched_stream_grid(const StreamGeo &geo, int dtype, int num_cu, int64_t ngroups,
-                               int *grid) {
+                               int wg_per_cu, int *grid) {
   BStreamFn fn = bpick(dtype, geo.nj, geo.w);
   if (!fn) return hipErrorInvalidValue;
   int per_cu = 0;
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)fn, 256, 0);
   if (e != hipSuccess) return e;
+  if (wg_per_cu > 0 && per_cu > wg_per_cu) per_cu = wg_per_cu;
   if (per_cu < 1) per_cu = 1;
   const int teams = 4 / geo.w;
   const int64_t nsuper = (ngroups + teams - 1) / teams;

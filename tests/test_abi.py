@@ -112,3 +112,23 @@ def test_product_package_does_not_import_the_oracle():
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True)
     assert r.returncode == 0, r.stdout + r.stderr
+
+
+def test_tuning_and_probe_check_arguments_first():
+    lib = g.load()
+    t = _abi.Tuning(1, 4, 64, 0)
+    res = _abi.TuneResult()
+    assert lib.gcss_get_tuning(None, ctypes.byref(t)) == g.ERR_ARG
+    assert lib.gcss_set_tuning(None, ctypes.byref(t)) == g.ERR_ARG
+    assert lib.gcss_autotune_select(None, 4, 3, None, ctypes.byref(res)) == g.ERR_ARG
+    off = (ctypes.c_int64 * 3)(0, 5, 10)
+    assert lib.gcss_autotune_batched(None, 2, off, 2, 2, 3, None, ctypes.byref(res)) == g.ERR_ARG
+    sec = ctypes.c_double()
+    sink = 0x20000
+    assert lib.gcss_hbm_probe(None, 1024, sink, 1, None, ctypes.byref(sec)) == g.ERR_ARG
+    assert lib.gcss_hbm_probe(0x10008, 1024, sink, 1, None, ctypes.byref(sec)) == g.ERR_ARG  # misaligned
+    assert lib.gcss_hbm_probe(0x10000, 1000, sink, 1, None, ctypes.byref(sec)) == g.ERR_ARG  # not 16k bytes
+    assert lib.gcss_hbm_probe(0x10000, 0, sink, 1, None, ctypes.byref(sec)) == g.ERR_ARG
+    assert lib.gcss_hbm_probe(0x10000, 1024, sink, 0, None, ctypes.byref(sec)) == g.ERR_ARG  # reps
+    assert lib.gcss_hbm_probe(0x10000, 1024, None, 1, None, ctypes.byref(sec)) == g.ERR_ARG
+    assert g.PROBE_SINK_FLOATS == 4096
