@@ -296,6 +296,10 @@ def main():
                          "autotuning it before the warm-up")
     ap.add_argument("--tune-cache", default=os.environ.get("GCSS_TUNE_CACHE"),
                     help="JSON file of tuned settings (default $GCSS_TUNE_CACHE, else none)")
+    ap.add_argument("--compare-f32", action="store_true",
+                    help="BF16/FP8 storage: also select from the binary32 matrix it was stored "
+                         "from, and score both pick sets against that matrix's own target "
+                         "(untimed)")
     ap.add_argument("--no-probe", action="store_true",
                     help="skip the HBM read probe (achievable bandwidth ceiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -439,6 +443,28 @@ def main():
             "bytes_per_launch": bytes_launch, "avg_launch_ms": round(avg_ms, 5),
             "launches_timed": prof["stream_launches"]}
 
+    vs_f32 = None
+    if args.compare_f32 and dtype != "f32":
+        # both selections judged on the binary32 source and its target
+        # (B = A, or B = A Omega with the same Omega), FP64 error evaluation
+        s32 = g.Selector(A32, m, k_max=k, r_max=r, self_target=self_target)
+        if self_target:
+            s32.set_target(None)
+        elif args.omega == "gauss":
+            s32.project_target(Om)
+        else:
+            s32.project_sign(1, r, density=1.0 if args.omega == "sign" else 1.0 / math.sqrt(n))
+        i32, o32, n32, _ = s32.select(k)
+        e32 = s32.reconstruction_error(i32[:n32])
+        elo = s32.reconstruction_error(state["idx"][:state["ns"]])
+        same = sum(1 for a, b in zip(i32[:n32], state["idx"][:state["ns"]]) if a == b)
+        vs_f32 = {"error_f32_picks": float(e32), "error_this_dtype_picks": float(elo),
+                  "rel_diff": float((elo - e32) / e32) if e32 else None,
+                  "objective_0": float(o32[0]), "same_position_picks": int(same),
+                  "picks_in_common": int(len(set(i32[:n32].tolist())
+                                             & set(state["idx"][:state["ns"]].tolist())))}
+        s32.close()
+
     probe = hbm_probe(args)
     if probe:
         probe["stream_frac_of_probe"] = round(achieved / probe["achieved"], 4)
@@ -461,6 +487,7 @@ def main():
         "phases": phases,
         "embedding": embedding,
         "quality": quality,
+        "vs_f32_on_f32_target": vs_f32,
         "result": {"n_selected": int(state["ns"]), "objective_first": float(state["obj"][0]),
                    "objective_last": float(state["obj"][state["ns"]]),
                    "reconstruction_error": float(state["err"])},
