@@ -117,7 +117,11 @@ def test_gram_quantized_storage(gpu, m, n, dt):
 
 # ---------------------------------------------------------------- a1 ---------
 @pytest.mark.parametrize("m,n,r,dt", [(37, 70, 3, "f32"), (500, 1000, 64, "f32"), (1000, 300, 256, "f32"),
-                                      (300, 500, 300, "f32"), (600, 400, 130, "bf16"), (700, 333, 40, "fp8")])
+                                      (300, 500, 300, "f32"), (600, 400, 130, "bf16"), (700, 333, 40, "fp8"),
+                                      # n >= 1024: binary32 128-row tiles (r < 192) and the
+                                      # bfloat16 matrix-core kernel (r >= 192), ragged tiles
+                                      (1024, 3000, 128, "f32"), (1000, 2500, 150, "bf16"),
+                                      (520, 1100, 128, "fp8"), (300, 2049, 200, "f32")])
 def test_initial_scores_factor(gpu, m, n, r, dt):
     A = synth.gauss_lowrank_dense(m, n, 8, 0.05, seed=n)
     A[:, 5] = 0.0
