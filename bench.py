@@ -319,8 +319,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs the selection on one GPU only; --gpus N > 1 is not "
-              "supported (DESIGN.md describes how the path would shard over GPUs).",
+        print("bench.py: the selection runs on one GPU; --gpus N > 1 is not supported "
+              "(the column-sharded multi-GPU path is not implemented).",
               file=sys.stderr)
         sys.exit(2)
 
