@@ -128,12 +128,20 @@ def cpu_baseline(w, A32, Om, target_seconds=15.0):
 
     ns = min(n, 1024)
     t, upd = run(ns)
-    # self target: the initial scores cost m*ns^2; explicit target: linear in ns
-    if ns < n and t < target_seconds / 2:
-        grow = math.sqrt(target_seconds / max(t, 1e-3)) if self_target else target_seconds / max(t, 1e-3)
-        ns = int(min(n, max(ns, ns * grow)))
-        ns = max(64, (ns // 64) * 64)
-        t, upd = run(ns)
+    # grow the sample towards target_seconds: cost ~ ns^p with p between 1
+    # (explicit target, the loop) and 2 (B = A: initial scores m*ns^2), taken
+    # from the last two runs once there are two
+    p = 2.0 if self_target else 1.0
+    for _ in range(3):
+        if ns >= n or t >= 0.6 * target_seconds:
+            break
+        grow = (target_seconds / max(t, 1e-3)) ** (1.0 / p)
+        ns_new = int(min(n, max(ns + 64, ns * grow)))
+        ns_new = max(64, (ns_new // 64) * 64)
+        t_new, upd = run(ns_new)
+        if t_new > t > 0 and ns_new > ns:
+            p = min(2.0, max(1.0, math.log(t_new / t) / math.log(ns_new / ns)))
+        ns, t = ns_new, t_new
     kk = min(k, ns)
     desc = (f"first {ns} of {n} columns, m={m}, k={kk}, "
             + ("B = A" if self_target else f"B = A_s Omega_s (r={r})")
