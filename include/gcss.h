@@ -409,8 +409,12 @@ typedef struct {
  * cached setting is applied without timing, and a new result is added to the
  * file (written to a temporary file, then renamed over it).  Needs a target
  * (GCSS_ERR_STATE otherwise).  Leaves the context as after gcss_select(h, k).
- * Errors: GCSS_ERR_ARG (k, reps, an unreadable or malformed cache file),
- * GCSS_ERR_STATE, GCSS_ERR_DEVICE.  Synchronizes the stream.
+ * Errors: GCSS_ERR_ARG (k, reps, an unreadable or malformed cache file, which
+ * is left as it is; a cache file that cannot be written, in which case the
+ * chosen setting is still applied), GCSS_ERR_STATE, GCSS_ERR_DEVICE (the
+ * entry setting is restored).  Synchronizes the stream.  Not thread-safe
+ * for one context, like every call on it; two processes that write the same
+ * cache file at once keep one of their results.
  */
 gcss_status gcss_autotune_select(gcss_ctx *h, int32_t k, int32_t reps, const char *cache_path,
                                  gcss_tune_result *out);
