@@ -74,6 +74,22 @@ def check_rank_k(sel, gpu, A, m, W, l, kr, cols, f_l):
     assert np.max(np.abs(got - ref) / np.sqrt(np.sum(Ac * Ac, axis=0))[None, :]) <= 1e-5
 
 
+def select_as_timed(sel, k, gram=False):
+    """Select under the launch setting bench.py times (its autotuner over
+    min(k, 32) steps), after checking that setting against the default one:
+    identical picks, and identical objectives for an explicit target (the
+    Gram target's decrements are FP64 sums grouped by the setting)."""
+    i0, o0, n0, _ = sel.select(k)
+    sel.autotune(min(k, 32), reps=3)
+    idx, obj, ns, st = sel.select(k)
+    assert np.array_equal(idx, i0) and ns == n0, sel.tuning()
+    if gram:
+        np.testing.assert_allclose(obj, o0, rtol=1e-12, atol=0)
+    else:
+        assert np.array_equal(obj.view(np.int64), o0.view(np.int64)), sel.tuning()
+    return idx, obj, ns, st
+
+
 def common_checks(idx, obj, ns, k):
     assert ns == k
     assert len(set(int(x) for x in idx)) == k
@@ -88,7 +104,7 @@ def test_full_css_4096x65536_k200(gpu):
     A = synth.spectral_lowrank_torch(m, n, w["rank"], w["decay"], w["noise"], 0)
     sel = gpu.Selector(A, m, k_max=k, self_target=True)
     sel.set_target(None)
-    idx, obj, ns, st = sel.select(k)
+    idx, obj, ns, st = select_as_timed(sel, k, gram=True)
     err = sel.reconstruction_error(idx)
     common_checks(idx, obj, ns, k)
     Ah = host(A, m)                       # (n, m) float64
@@ -164,7 +180,7 @@ def test_full_gcss_2048x1048576_r256_k100_fp32_and_bf16(gpu):
     Om = synth.omega_gauss_torch(n, r, 1)
     sel = gpu.Selector(A, m, k_max=k, r_max=r)
     Bg = sel.project_target(Om)[:, :m].double().cpu().numpy().T
-    idx, obj, ns, st = sel.select(k)
+    idx, obj, ns, st = select_as_timed(sel, k)
     err = sel.reconstruction_error(idx)
     common_checks(idx, obj, ns, k)
     B = project_ref(A, m, Om)
@@ -194,7 +210,7 @@ def test_full_gcss_2048x1048576_r256_k100_fp32_and_bf16(gpu):
     assert np.array_equal(A16[cols].cpu().numpy().view(np.uint16), ref_codes)
     s16 = gpu.Selector(A16, m, k_max=k, r_max=r)
     s16.project_target(Om)
-    i16, o16, n16, _ = s16.select(k)
+    i16, o16, n16, _ = select_as_timed(s16, k)
     common_checks(i16, o16, n16, k)
     e16 = dense.error(host(A, m, i16).T, B)
     assert abs(e16 - e32) <= 1e-3 * e32
@@ -245,8 +261,13 @@ def test_full_batched_1024_64blocks(gpu):
     Om = synth.omega_gauss_torch(n, r, 1)
     sel = gpu.Selector(A, m, k_max=kb, r_max=r, batched=(len(widths), kb, km))
     sel.project_target(Om)
+    ib0, im0, om0, _, _ = sel.select_batched(off, kb, km)
+    # the launch setting bench.py times: its autotuner of the batched pass
+    sel.autotune_batched(off, kb, km, reps=3)
     ib, im, om, nm, st = sel.select_batched(off, kb, km)
     assert nm == km and st == gpu.OK
+    assert np.array_equal(ib, ib0) and np.array_equal(im, im0), sel.tuning()
+    assert np.array_equal(om.view(np.int64), om0.view(np.int64)), sel.tuning()
     B = project_ref(A, m, Om)
     # three blocks (the two narrowest and one wide) against the oracle's Algorithm 3
     order = np.argsort(widths)
@@ -296,7 +317,7 @@ def test_full_gcss_fp8_8192x262144_r512_k500(gpu):
         B += dense.project(Ahat, m, Om[i0:i1].double().cpu().numpy(), chunk=chunk)
     sel = gpu.Selector(A8, m, k_max=k, r_max=r, scales=sc8)
     sel.project_target(Om)
-    idx, obj, ns, st = sel.select(k)
+    idx, obj, ns, st = select_as_timed(sel, k)
     err = sel.reconstruction_error(idx)
     common_checks(idx, obj, ns, k)
 
