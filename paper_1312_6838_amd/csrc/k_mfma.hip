@@ -44,6 +44,18 @@ __device__ __forceinline__ void split3(float a, __bf16 &h, __bf16 &m, __bf16 &l)
   l = (__bf16)(r1 - (float)m);
 }
 
+// Load tasks of a 256-row x 32-k operand stage, for operands whose rows are
+// contiguous in memory: task t (0..255) moves rows x3_task_row(t) .. +3 for
+// k = x3_task_k(t) .. +7 into the k-contiguous planes (pitch kX3RP).  The 16
+// tasks of a 16-lane group cover four row quads and the four k groups, so
+// their 16-byte plane stores fall in distinct bank quads (row quads alone,
+// 320 bytes apart, would share four of them).  A wave's loads still read
+// 256 contiguous bytes per k group.
+__device__ __forceinline__ int x3_task_row(int t) {
+  return 64 * (t >> 6) + 4 * ((t & 3) + 4 * ((t >> 4) & 3));
+}
+__device__ __forceinline__ int x3_task_k(int t) { return 8 * ((t >> 2) & 3); }
+
 // binary32 products on the bfloat16 matrix cores (three-part split) for the
 // Gram matrix and the initial scores; GCSS_MFMA_X3=0 keeps the binary32 MFMA
 // kernels
@@ -1306,7 +1318,7 @@ __global__ __launch_bounds__(kG2Threads, 1) void k_gram_x3(AView A, float *__res
 
   // load task of this thread: operand op, rows r0..r0+3, k k8..k8+7 of the stage
   const int op = tid >> 8, task = tid & 255;
-  const int r0 = (task & 63) * 4, k8 = (task >> 6) * 8;
+  const int r0 = x3_task_row(task), k8 = x3_task_k(task);
   const int64_t row0 = (op == 0 ? i0 : j0) + r0;
   float4 reg[8];
   auto gload = [&](int64_t k0) {
@@ -1438,7 +1450,7 @@ __global__ __launch_bounds__(kG2Threads, 1) void k_proj_x3(AView A, const float 
   // load task: op 0 -> rows i0 + q0 .. +3 of A, op 1 -> columns j0 + q0 .. +3
   // of Omega, for k = k0 + k8 .. k0 + k8 + 7
   const int op = tid >> 8, task = tid & 255;
-  const int q0 = (task & 63) * 4, k8 = (task >> 6) * 8;
+  const int q0 = x3_task_row(task), k8 = x3_task_k(task);
   float4 reg[8];
   // (m and r are multiples of 4: four rows or columns are in or out together)
   auto gload = [&](int64_t k0) {
