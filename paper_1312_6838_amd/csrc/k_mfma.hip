@@ -759,8 +759,9 @@ __global__ __launch_bounds__(kI2Threads, 1) void k_init_x3(const float *__restri
             for (int e = 0; e < 8; ++e)
               if (gk + e >= m) v[e] = 0.f;
           }
-          if (TRI && op == 0) {
+          if (TRI && op == 0 && k0 < r0 + RT) {
             // weights of the triangle: 1 above the diagonal, 1/2 on it, 0 below
+            // (stages from k = r0 + 256 on lie wholly above it: weight 1)
             const int d0 = (int)(k0 + kg - (r0 + row));
 #pragma unroll
             for (int e = 0; e < 8; ++e) v[e] *= d0 + e > 0 ? 1.f : (d0 + e == 0 ? 0.5f : 0.f);
