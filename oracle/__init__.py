@@ -54,40 +54,64 @@ def build(force: bool = True) -> str:
     return _LIB
 
 
+def _configure(lib):
+    """Declare the C signatures on a loaded oracle library."""
+    lib.orc_select.restype = ctypes.c_int
+    lib.orc_select.argtypes = [_vp, _i64, _i64, _i64, _vp, _i64, _i64, _i32, _dbl,
+                               _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    lib.orc_init_scores.restype = ctypes.c_int
+    lib.orc_init_scores.argtypes = [_vp, _i64, _i64, _i64, _vp, _i64, _i64, _vp, _vp]
+    lib.orc_error.restype = ctypes.c_int
+    lib.orc_error.argtypes = [_vp, _i64, _i64, _i64, _vp, _i32, _vp, _i64, _i64, _vp]
+    lib.orc_select_distributed.restype = ctypes.c_int
+    lib.orc_select_distributed.argtypes = [_vp, _i64, _i64, _i64, _vp, _i64, _i64, _i32,
+                                           _vp, _i32, _i32, _dbl, _vp, _vp, _vp, _vp]
+    lib.orc_bf16_decode.restype = ctypes.c_float
+    lib.orc_bf16_decode.argtypes = [ctypes.c_uint16]
+    lib.orc_bf16_encode.restype = ctypes.c_uint16
+    lib.orc_bf16_encode.argtypes = [ctypes.c_float]
+    lib.orc_fp8_decode.restype = ctypes.c_double
+    lib.orc_fp8_decode.argtypes = [ctypes.c_uint8]
+    lib.orc_fp8_encode.restype = ctypes.c_uint8
+    lib.orc_fp8_encode.argtypes = [ctypes.c_float]
+    lib.orc_quantize_fp8.restype = None
+    lib.orc_quantize_fp8.argtypes = [_vp, _i64, _i64, _i64, _vp, _i64, _vp]
+    lib.orc_quantize_bf16.restype = None
+    lib.orc_quantize_bf16.argtypes = [_vp, _i64, _i64, _i64, _vp, _i64]
+    lib.orc_decode_columns.restype = None
+    lib.orc_decode_columns.argtypes = [_vp, ctypes.c_int, _i64, _i64, _i64, _vp, _vp, _i64]
+    lib.orc_num_threads.restype = ctypes.c_int
+    lib.orc_num_threads.argtypes = []
+    return lib
+
+
 def _load():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build(force=True)
-        lib = ctypes.CDLL(_LIB)
-        lib.orc_select.restype = ctypes.c_int
-        lib.orc_select.argtypes = [_vp, _i64, _i64, _i64, _vp, _i64, _i64, _i32, _dbl,
-                                   _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
-        lib.orc_init_scores.restype = ctypes.c_int
-        lib.orc_init_scores.argtypes = [_vp, _i64, _i64, _i64, _vp, _i64, _i64, _vp, _vp]
-        lib.orc_error.restype = ctypes.c_int
-        lib.orc_error.argtypes = [_vp, _i64, _i64, _i64, _vp, _i32, _vp, _i64, _i64, _vp]
-        lib.orc_select_distributed.restype = ctypes.c_int
-        lib.orc_select_distributed.argtypes = [_vp, _i64, _i64, _i64, _vp, _i64, _i64, _i32,
-                                               _vp, _i32, _i32, _dbl, _vp, _vp, _vp, _vp]
-        lib.orc_bf16_decode.restype = ctypes.c_float
-        lib.orc_bf16_decode.argtypes = [ctypes.c_uint16]
-        lib.orc_bf16_encode.restype = ctypes.c_uint16
-        lib.orc_bf16_encode.argtypes = [ctypes.c_float]
-        lib.orc_fp8_decode.restype = ctypes.c_double
-        lib.orc_fp8_decode.argtypes = [ctypes.c_uint8]
-        lib.orc_fp8_encode.restype = ctypes.c_uint8
-        lib.orc_fp8_encode.argtypes = [ctypes.c_float]
-        lib.orc_quantize_fp8.restype = None
-        lib.orc_quantize_fp8.argtypes = [_vp, _i64, _i64, _i64, _vp, _i64, _vp]
-        lib.orc_quantize_bf16.restype = None
-        lib.orc_quantize_bf16.argtypes = [_vp, _i64, _i64, _i64, _vp, _i64]
-        lib.orc_decode_columns.restype = None
-        lib.orc_decode_columns.argtypes = [_vp, ctypes.c_int, _i64, _i64, _i64, _vp, _vp, _i64]
-        lib.orc_num_threads.restype = ctypes.c_int
-        lib.orc_num_threads.argtypes = []
-        _lib = lib
+        _lib = _configure(ctypes.CDLL(_LIB))
     return _lib
+
+
+def source() -> str:
+    """Text of the C oracle (the tests compile altered copies of it to check
+    that the pins catch planted mistakes)."""
+    with open(_SRC) as f:
+        return f.read()
+
+
+def build_variant(text: str, out_dir: str, tag: str):
+    """Compile C oracle source text (e.g. a copy with a planted mistake) into
+    out_dir and return the loaded library, ready to stand in for the oracle's
+    own (``oracle._lib``)."""
+    src = os.path.join(out_dir, f"orc_{tag}.c")
+    lib = os.path.join(out_dir, f"liborc_{tag}.so")
+    with open(src, "w") as f:
+        f.write(text)
+    subprocess.run(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-o", lib, src,
+                    "-lm"], check=True)
+    return _configure(ctypes.CDLL(lib))
 
 
 def _p(a):

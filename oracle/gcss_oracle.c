@@ -8,9 +8,10 @@
  * What it computes (Farahat, Elgohary, Ghodsi, Kamel, "Greedy Column Subset
  * Selection for Large-scale Data Sets"):
  *
- *   orc_select            Algorithm 3 (greedy generalized CSS) in the paper's
- *                         order and notation: delta, gamma, omega, upsilon and
- *                         the f/g update of Theorem 4.  With B == NULL it is
+ *   orc_select            Algorithm 3 (greedy generalized CSS) in its
+ *                         recursive form: the residual Gram and cross columns
+ *                         of the pick, the history omega / upsilon and the
+ *                         score update of Theorem 4.  With B == NULL it is
  *                         Algorithm 1 (B = A) with the update of Theorem 2.
  *   orc_error             the CSS objective ||B - P_S B||_F^2 of Problem 1 /
  *                         Problem 5, with P_S from a Householder QR of A_S
@@ -115,7 +116,115 @@ int orc_init_scores(const double *A, int64_t m, int64_t n, int64_t lda,
 }
 
 /*
- * Greedy generalized CSS, Algorithm 3 (B != NULL) / Algorithm 1 (B == NULL).
+ * Pieces of one greedy step.  Notation of Sections 4 and 5: after the picks
+ * S so far, P projects onto span(A_S), E = (I - P) A and F = (I - P) B are the
+ * residuals of the source and the target, G = E^T E and H = F^T E.  Column i
+ * scores f_i / g_i with f_i = ||H_{:i}||^2 and g_i = G_ii (Lemma 1 and
+ * Theorem 1 for B = A, Theorem 3 otherwise).  The history kept is, per pick
+ * r, the n-vector W_r = G^{(r)}_{:p_r} / sqrt(G^{(r)}_{p_r p_r}) (omega) and
+ * the target-side vector U_r = H^{(r)}_{:p_r} / sqrt(G^{(r)}_{p_r p_r})
+ * (upsilon; for B = A it is W_r itself).
+ */
+
+/* Best candidate by f_i / g_i (the greedy criterion of Problems 3 and 6).
+ * A candidate is unpicked, not dropped, has g0_i > 0, finite f_i and g_i and
+ * g_i > tau * g0_i; on equal ratios the lower index wins.  *second receives
+ * the runner-up ratio (-inf if none).  Returns -1 when there is no candidate. */
+static int64_t best_candidate(const double *f, const double *g, const double *g0,
+                              const unsigned char *excl, int64_t n, double tau,
+                              double *first, double *second) {
+  int64_t p = -1;
+  double s1 = -INFINITY, s2 = -INFINITY;
+  for (int64_t i = 0; i < n; ++i) {
+    if (excl[i]) continue;
+    if (!(g0[i] > 0.0) || !isfinite(f[i]) || !isfinite(g[i])) continue;
+    if (!(g[i] > tau * g0[i])) continue;
+    double s = f[i] / g[i];
+    if (s > s1) {
+      s2 = s1;
+      s1 = s;
+      p = i;
+    } else if (s > s2) {
+      s2 = s;
+    }
+  }
+  *first = s1;
+  *second = s2;
+  return p;
+}
+
+/* Column p of the residual Gram matrix, out = G_{:p} (Lemma 2 / Corollary 2:
+ * each earlier pick r took W_r[p] W_r out of A^T A_p).  wp[r] = W_r[p]. */
+static void residual_gram_column(const double *A, int64_t m, int64_t n, int64_t lda,
+                                 const double *ap, const double *W, const double *wp, int32_t t,
+                                 double *out) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    double d = dotd(A + i * lda, ap, m);
+    for (int32_t s = 0; s < t; ++s) d -= wp[s] * W[(size_t)s * n + i];
+    out[i] = d;
+  }
+}
+
+/* Column p of the residual cross matrix, out = H_{:p} (r entries; the target
+ * counterpart of residual_gram_column, Section 5.2). */
+static void residual_cross_column(const double *B, int64_t m, int64_t r, int64_t ldb,
+                                  const double *ap, const double *U, const double *wp, int32_t t,
+                                  double *out) {
+  for (int64_t c = 0; c < r; ++c) {
+    double v = dotd(B + c * ldb, ap, m);
+    for (int32_t s = 0; s < t; ++s) v -= wp[s] * U[(size_t)s * r + c];
+    out[c] = v;
+  }
+}
+
+/* The n-vector H^T upsilon that the update of f needs (Theorem 4; Theorem 2
+ * for B = A, where it is G^T omega): A^T (B upsilon) with the earlier picks'
+ * share removed, sum_r (U_r . upsilon) W_r.  y, coef: scratch (m, t). */
+static int deflation_term(const double *A, int64_t m, int64_t n, int64_t lda, const double *B,
+                          int64_t r, int64_t ldb, const double *W, const double *U,
+                          const double *ups, int64_t rr, int32_t t, double *y, double *coef,
+                          double *out) {
+  if (!B) {
+    int st = matvec_cols(A, m, n, lda, ups, y); /* A omega */
+    if (st != ORC_OK) return st;
+  } else {
+    for (int64_t j = 0; j < m; ++j) y[j] = 0.0; /* B upsilon */
+    for (int64_t c = 0; c < r; ++c) {
+      const double *bc = B + c * ldb;
+      for (int64_t j = 0; j < m; ++j) y[j] += ups[c] * bc[j];
+    }
+  }
+  for (int32_t s = 0; s < t; ++s) {
+    const double *us = B ? (U + (size_t)s * rr) : (W + (size_t)s * n);
+    coef[s] = dotd(us, ups, rr);
+  }
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    double v = dotd(A + i * lda, y, m);
+    for (int32_t s = 0; s < t; ++s) v -= coef[s] * W[(size_t)s * n + i];
+    out[i] = v;
+  }
+  return ORC_OK;
+}
+
+/* Rank-one deflation of G and H by the new pick, seen through the scores
+ * (Theorem 4 / Theorem 2): ||H_{:i} - omega_i upsilon||^2 and
+ * G_ii - omega_i^2, with hu = H^T upsilon and un = ||upsilon||^2. */
+static void rank_one_update(double *f, double *g, const double *om, const double *hu, double un,
+                            int64_t n) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    double w = om[i];
+    f[i] = f[i] - 2.0 * w * hu[i] + un * w * w;
+    g[i] = g[i] - w * w;
+  }
+}
+
+/*
+ * Greedy generalized CSS, Algorithm 3 (B != NULL) / Algorithm 1 (B == NULL),
+ * kept in the recursive form of Theorems 2 and 4: the scores are updated from
+ * the history W, U, never recomputed from a projection.
  *
  * Inputs
  *   A      m x n column-major, leading dimension lda (source matrix)
@@ -136,8 +245,8 @@ int orc_init_scores(const double *A, int64_t m, int64_t n, int64_t lda,
  *   n_selected    number of picks made
  * Returns ORC_OK, ORC_EXHAUSTED (fewer than k candidates) or an error.
  *
- * A pick whose delta_p <= tau * g0_p (a column that rounding made look
- * independent) is dropped from the candidates and the argmax is redone.
+ * A pick whose G_pp <= tau * g0_p (a column that rounding made look
+ * independent) is dropped from the candidates and the search is repeated.
  */
 int orc_select(const double *A, int64_t m, int64_t n, int64_t lda,
                const double *B, int64_t r, int64_t ldb, int32_t k, double tau,
@@ -156,19 +265,19 @@ int orc_select(const double *A, int64_t m, int64_t n, int64_t lda,
   unsigned char *excl = (unsigned char *)calloc((size_t)n, 1); /* 1 selected, 2 dropped */
   double *W = (double *)malloc(sizeof(double) * (size_t)k * n);        /* omega history */
   double *Ups = self ? NULL : (double *)malloc(sizeof(double) * (size_t)k * rr);
-  double *delta = (double *)malloc(sizeof(double) * n);
-  double *gam = (double *)malloc(sizeof(double) * rr);
+  double *gcol = (double *)malloc(sizeof(double) * n);
+  double *hcol = (double *)malloc(sizeof(double) * rr);
   double *ups = (double *)malloc(sizeof(double) * rr);
-  double *u = (double *)malloc(sizeof(double) * n);
+  double *hu = (double *)malloc(sizeof(double) * n);
   double *y = (double *)malloc(sizeof(double) * m);
+  double *wp = (double *)malloc(sizeof(double) * (k > 0 ? k : 1));
   double *coef = (double *)malloc(sizeof(double) * (k > 0 ? k : 1));
-  if (!f || !g || !g0 || !excl || !W || (!self && !Ups) || !delta || !gam || !ups ||
-      !u || !y || !coef) {
+  if (!f || !g || !g0 || !excl || !W || (!self && !Ups) || !gcol || !hcol || !ups ||
+      !hu || !y || !wp || !coef) {
     status = ORC_ERR_NOMEM;
     goto done;
   }
 
-  /* Initialize f^(0), g^(0) */
   status = orc_init_scores(A, m, n, lda, B, r, ldb, f, g);
   if (status != ORC_OK) goto done;
   memcpy(g0, g, sizeof(double) * n);
@@ -191,88 +300,39 @@ int orc_select(const double *A, int64_t m, int64_t n, int64_t lda,
       memcpy(fg_trace + (size_t)t * 2 * n, f, sizeof(double) * n);
       memcpy(fg_trace + (size_t)t * 2 * n + n, g, sizeof(double) * n);
     }
-    /* p = argmax_i f_i / g_i over the candidates; ties go to the lowest index */
-    int64_t p = -1;
-    double s1 = -INFINITY, s2 = -INFINITY;
-    for (int64_t i = 0; i < n; ++i) {
-      if (excl[i]) continue;
-      if (!(g0[i] > 0.0) || !isfinite(f[i]) || !isfinite(g[i])) continue;
-      if (!(g[i] > tau * g0[i])) continue;
-      double s = f[i] / g[i];
-      if (s > s1) {
-        s2 = s1;
-        s1 = s;
-        p = i;
-      } else if (s > s2) {
-        s2 = s;
-      }
-    }
+    double s1, s2;
+    const int64_t p = best_candidate(f, g, g0, excl, n, tau, &s1, &s2);
     if (p < 0) {
       status = ORC_EXHAUSTED;
       break;
     }
 
-    /* delta^(t) = A^T A_p - sum_{r<t} omega_p^(r) omega^(r) */
     const double *ap = A + p * lda;
-    for (int32_t s = 0; s < t; ++s) coef[s] = W[(size_t)s * n + p];
-#pragma omp parallel for schedule(static)
-    for (int64_t i = 0; i < n; ++i) {
-      double d = dotd(A + i * lda, ap, m);
-      for (int32_t s = 0; s < t; ++s) d -= coef[s] * W[(size_t)s * n + i];
-      delta[i] = d;
-    }
-    const double dp = delta[p];
-    if (!(dp > tau * g0[p])) {
-      /* rounding made column p look independent: drop it, redo the argmax */
-      excl[p] = 2;
+    for (int32_t s = 0; s < t; ++s) wp[s] = W[(size_t)s * n + p];
+    residual_gram_column(A, m, n, lda, ap, W, wp, t, gcol);
+    const double gpp = gcol[p];
+    if (!(gpp > tau * g0[p])) {
+      excl[p] = 2; /* rounding made column p look independent */
       continue;
     }
-    const double sq = sqrt(dp);
+    const double sq = sqrt(gpp);
 
-    /* gamma^(t) = B^T A_p - sum_{r<t} omega_p^(r) upsilon^(r);  (B = A: gamma = delta) */
-    if (self) {
-      memcpy(gam, delta, sizeof(double) * n);
-    } else {
-      for (int64_t c = 0; c < r; ++c) {
-        double v = dotd(B + c * ldb, ap, m);
-        for (int32_t s = 0; s < t; ++s) v -= coef[s] * Ups[(size_t)s * rr + c];
-        gam[c] = v;
-      }
-    }
+    if (self)
+      memcpy(hcol, gcol, sizeof(double) * n); /* H = G when B = A */
+    else
+      residual_cross_column(B, m, r, ldb, ap, Ups, wp, t, hcol);
 
-    /* omega = delta / sqrt(delta_p),  upsilon = gamma / sqrt(delta_p) */
+    /* the new history entries: G_{:p} and H_{:p} scaled by 1 / sqrt(G_pp) */
     double *om = W + (size_t)t * n;
-    for (int64_t i = 0; i < n; ++i) om[i] = delta[i] / sq;
+    for (int64_t i = 0; i < n; ++i) om[i] = gcol[i] / sq;
     double un = 0.0;
     for (int64_t c = 0; c < rr; ++c) {
-      ups[c] = gam[c] / sq;
+      ups[c] = hcol[c] / sq;
       un += ups[c] * ups[c];
     }
 
-    /* Theorem 4 (Theorem 2 for B = A):
-     *   u = A^T B upsilon - sum_{r<t} (upsilon^(r)T upsilon) omega^(r)
-     *   f <- f - 2 omega o u + ||upsilon||^2 omega o omega
-     *   g <- g - omega o omega                                                */
-    if (self) {
-      status = matvec_cols(A, m, n, lda, ups, y); /* y = A omega */
-    } else {
-      for (int64_t j = 0; j < m; ++j) y[j] = 0.0; /* y = B upsilon */
-      for (int64_t c = 0; c < r; ++c) {
-        const double *bc = B + c * ldb;
-        for (int64_t j = 0; j < m; ++j) y[j] += ups[c] * bc[j];
-      }
-    }
+    status = deflation_term(A, m, n, lda, B, r, ldb, W, Ups, ups, rr, t, y, coef, hu);
     if (status != ORC_OK) goto done;
-    for (int32_t s = 0; s < t; ++s) {
-      const double *us = self ? (W + (size_t)s * n) : (Ups + (size_t)s * rr);
-      coef[s] = dotd(us, ups, rr);
-    }
-#pragma omp parallel for schedule(static)
-    for (int64_t i = 0; i < n; ++i) {
-      double v = dotd(A + i * lda, y, m);
-      for (int32_t s = 0; s < t; ++s) v -= coef[s] * W[(size_t)s * n + i];
-      u[i] = v;
-    }
 
     const double sc = f[p] / g[p];
     if (score) score[t] = sc;
@@ -281,12 +341,7 @@ int orc_select(const double *A, int64_t m, int64_t n, int64_t lda,
     if (obj) obj[t + 1] = obj[t] - sc;
     if (!self) memcpy(Ups + (size_t)t * rr, ups, sizeof(double) * rr);
 
-#pragma omp parallel for schedule(static)
-    for (int64_t i = 0; i < n; ++i) {
-      double w = om[i];
-      f[i] = f[i] - 2.0 * w * u[i] + un * w * w;
-      g[i] = g[i] - w * w;
-    }
+    rank_one_update(f, g, om, hu, un, n);
     excl[p] = 1;
     idx[t] = p;
     ++t;
@@ -308,11 +363,12 @@ done:
   free(excl);
   free(W);
   free(Ups);
-  free(delta);
-  free(gam);
+  free(gcol);
+  free(hcol);
   free(ups);
-  free(u);
+  free(hu);
   free(y);
+  free(wp);
   free(coef);
   return status;
 }
