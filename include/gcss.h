@@ -155,8 +155,13 @@ gcss_status gcss_project_sign(gcss_ctx *h, uint64_t seed, double density, int64_
  *             entries past *n_selected repeat the last value.
  * n_selected: host (may be NULL): number of picks made.
  * Returns GCSS_OK, or GCSS_WARN_EXHAUSTED when fewer than k columns stay
- * candidates (see gcss_desc.tau).  Errors: GCSS_ERR_ARG (k < 1 or k > k_max),
- * GCSS_ERR_STATE (no target), GCSS_ERR_DEVICE.  Synchronizes the stream.
+ * candidates (see gcss_desc.tau).  A column stops being a candidate when its
+ * tracked residual g_i drops to tau * g0_i or below, when a pick of it is
+ * rejected because its exact FP64 residual after re-orthogonalisation is at
+ * most tau * g0_i, or when f_i or g_i is not finite (a column holding NaN or
+ * infinity is never picked; no error is raised).  Errors: GCSS_ERR_ARG
+ * (k < 1 or k > k_max), GCSS_ERR_STATE (no target), GCSS_ERR_DEVICE.
+ * Synchronizes the stream.
  */
 gcss_status gcss_select(gcss_ctx *h, int32_t k, int64_t *idx, double *objective,
                         int32_t *n_selected);
@@ -166,8 +171,15 @@ gcss_status gcss_select(gcss_ctx *h, int32_t k, int64_t *idx, double *objective,
  * synchronize: d_idx (k int64), d_obj (k+1 double, may be NULL),
  * d_nsel (1 int32, may be NULL) are device pointers written on the stream.
  * The whole k-step loop is replayed from a HIP graph that is built on the
- * first call for a given k.
+ * first call for a given k.  The graph holds k + GCSS_ASYNC_SPARE_STEPS
+ * steps; a step whose pick the basis check rejects (a column that only
+ * rounding kept a candidate: its exact FP64 residual is at most tau times
+ * its squared norm) adds no pick, so after more rejections than that the
+ * graph ends with *d_nsel < k although candidates remain.  gcss_read_state
+ * (GCSS_STATE_FLAGS) then reports finished = 0; gcss_select, which loops
+ * on the host, always finishes.
  */
+#define GCSS_ASYNC_SPARE_STEPS 8
 gcss_status gcss_select_async(gcss_ctx *h, int32_t k, int64_t *d_idx, double *d_obj,
                               int32_t *d_nsel);
 
@@ -340,7 +352,11 @@ typedef enum {
   GCSS_STATE_Z = 5,     /* m floats: z of the last completed step               */
   GCSS_STATE_B = 6,     /* m*r floats: the explicit target (col-major, ld m)    */
   GCSS_STATE_GRAM = 7,  /* m*m floats: the Gram target A A^T (self target)      */
-  GCSS_STATE_NREJECT = 8 /* 1 int32: picks rejected by the basis check          */
+  GCSS_STATE_NREJECT = 8, /* 1 int32: picks rejected by the basis check          */
+  GCSS_STATE_FLAGS = 9    /* 4 int32 of the last select / select_async: picks made,
+                             finished (1: k picks or no candidate left; 0: a
+                             select_async graph ran out of steps, see there),
+                             exhausted (1: ran out of candidates), rejected picks */
 } gcss_state_item;
 
 /*
@@ -350,9 +366,11 @@ typedef enum {
  */
 gcss_status gcss_read_state(gcss_ctx *h, int32_t item, void *host, size_t bytes, size_t *copied);
 
-/* Timings collected while profiling is on (HIP events on the context's stream,
- * recorded by gcss_select only; the graph-replayed gcss_select_async is not
- * instrumented). */
+/* Timings collected while profiling is on (HIP events on the context's
+ * stream around every fused streaming pass), recorded by gcss_select and by
+ * gcss_select_batched, which then enqueues its per-block loop directly
+ * instead of replaying its graph; the graph-replayed gcss_select_async is not
+ * instrumented. */
 typedef struct {
   int64_t stream_launches;  /* fused streaming passes (step 4 of the loop) timed */
   double stream_ms;         /* their summed duration, milliseconds                */

@@ -14,6 +14,7 @@ from . import _abi
 from ._abi import (  # noqa: F401
     BF16, ERR_ARG, ERR_DEVICE, ERR_STATE, ERR_UNSUPPORTED, ERR_WORKSPACE, EXPORTS, F32,
     FP8_E4M3, OK, STATE_B, STATE_F, STATE_F0, STATE_G, STATE_G0, STATE_GRAM, STATE_NREJECT,
+    STATE_FLAGS, ASYNC_SPARE_STEPS,
     STATE_Q, STATE_Z, WARN_EXHAUSTED, Desc, GcssError, batched_workspace_size, create, destroy,
     last_error, load, make_desc, project_target, quantize, read_state, reconstruction_error,
     select, select_async, select_batched, set_target, version, workspace_size,
@@ -205,6 +206,13 @@ class Selector:
         import numpy as np
         raw = read_state(self.h, item, int(count) * np.dtype(np_dtype).itemsize)
         return np.frombuffer(raw, dtype=np_dtype).copy()
+
+    def flags(self):
+        """State of the last selection: dict(picks, finished, exhausted, rejected)."""
+        import numpy as np
+        v = self.read(STATE_FLAGS, 4, np.int32)
+        return dict(picks=int(v[0]), finished=bool(v[1]), exhausted=bool(v[2]),
+                    rejected=int(v[3]))
 
     def tuning(self, **setting):
         """Read the streaming passes' launch setting, or change some of its

@@ -24,7 +24,9 @@ F32 = 0
 BF16 = 1
 FP8_E4M3 = 2
 
-STATE_F0, STATE_G0, STATE_F, STATE_G, STATE_Q, STATE_Z, STATE_B, STATE_GRAM, STATE_NREJECT = range(9)
+(STATE_F0, STATE_G0, STATE_F, STATE_G, STATE_Q, STATE_Z, STATE_B, STATE_GRAM, STATE_NREJECT,
+ STATE_FLAGS) = range(10)
+ASYNC_SPARE_STEPS = 8
 
 EXPORTS = [
     "gcss_workspace_size", "gcss_create", "gcss_destroy", "gcss_set_target",

@@ -39,7 +39,7 @@ gcss_status fail(gcss_status s, const char *fmt, ...) {
   } while (0)
 
 constexpr int kPlanCU = 256;       // CU count used to size the workspace (MI355X)
-constexpr int kSpareSlots = 4;     // extra step slots in a captured loop (rejected picks)
+constexpr int kSpareSlots = GCSS_ASYNC_SPARE_STEPS;  // extra steps of a captured loop (rejected picks)
 constexpr double kBasisTau = 1e-13;  // dependence threshold of the basis-only mode
 
 inline size_t up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -375,9 +375,13 @@ gcss_status gcss_workspace_size(const gcss_desc *d, size_t *bytes) {
   return GCSS_OK;
 }
 
-gcss_status gcss_create(const gcss_desc *d, void *workspace, size_t ws_bytes, gcss_ctx **out) {
-  if (!out) return fail(GCSS_ERR_ARG, "null out");
-  *out = nullptr;
+}  // extern "C"
+
+namespace {
+
+// Everything gcss_create does, on a caller-provided context object (the
+// no-allocation entry point keeps its context on the stack).
+gcss_status init_ctx(gcss_ctx *h, const gcss_desc *d, void *workspace, size_t ws_bytes) {
   gcss_status st = check_desc(d);
   if (st != GCSS_OK) return st;
   if (!d->a) return fail(GCSS_ERR_ARG, "null A");
@@ -415,7 +419,6 @@ gcss_status gcss_create(const gcss_desc *d, void *workspace, size_t ws_bytes, gc
     if (fe != hipSuccess) return fail(GCSS_ERR_DEVICE, "stream kernel occupancy: %s", hipGetErrorString(fe));
   }
 
-  gcss_ctx *h = new gcss_ctx();
   h->device = dev;
   h->num_cu = num_cu;
   h->stream = (hipStream_t)d->stream;
@@ -431,13 +434,28 @@ gcss_status gcss_create(const gcss_desc *d, void *workspace, size_t ws_bytes, gc
   h->A.n = d->n;
   h->A.lda = d->lda;
   h->A.dtype = d->a_dtype;
+  // the stream kernels read q and z up to their padded length: zero the
+  // padding once (kernels, not memsets, so the calls stay capturable)
   const size_t qlen = std::max<size_t>(L.qbuf, L.ldq);
   hipError_t e = launch_zero_f32(h->at<float>(L.q32), (int64_t)qlen, h->stream);
   if (!e) e = launch_zero_f32(h->at<float>(L.z32), (int64_t)qlen, h->stream);
   if (!e) e = launch_zero_f32(h->at<float>(L.q64), 2 * (int64_t)qlen, h->stream);
-  if (e) {
+  if (e) return fail(GCSS_ERR_DEVICE, "init: %s", hipGetErrorString(e));
+  return GCSS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gcss_status gcss_create(const gcss_desc *d, void *workspace, size_t ws_bytes, gcss_ctx **out) {
+  if (!out) return fail(GCSS_ERR_ARG, "null out");
+  *out = nullptr;
+  gcss_ctx *h = new gcss_ctx();
+  gcss_status st = init_ctx(h, d, workspace, ws_bytes);
+  if (st != GCSS_OK) {
     delete h;
-    return fail(GCSS_ERR_DEVICE, "init: %s", hipGetErrorString(e));
+    return st;
   }
   *out = h;
   return GCSS_OK;
@@ -528,12 +546,18 @@ gcss_status gcss_select(gcss_ctx *h, int32_t k, int64_t *idx, double *objective,
   }
   HIPCHK(enqueue_begin(h, k));
   DevState hs;
+  // Every step either adds a pick or drops its candidate for good (a pick
+  // the basis check rejects), so at most k + n steps end any selection.
   int slots = k;
-  for (int round = 0; round < 64; ++round) {
+  int64_t ran = 0;
+  for (;;) {
     for (int i = 0; i < slots; ++i) HIPCHK(enqueue_step(h));
+    ran += slots;
     HIPCHK(hipMemcpyAsync(&hs, h->at<DevState>(h->L.st), sizeof hs, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     if (hs.done) break;
+    if (ran > (int64_t)k + h->d.n)
+      return fail(GCSS_ERR_DEVICE, "selection did not finish after %lld steps", (long long)ran);
     slots = k - hs.t;  // picks were rejected: run the missing steps
     if (slots < 1) slots = 1;
   }
@@ -907,9 +931,10 @@ bool make_blayout(const gcss_desc *d, const Layout &L, int nblocks, int kb, int 
   return true;
 }
 
-// One lockstep step of all blocks.
+// One lockstep step of all blocks (timed: event pairs around the batched
+// stream pass, when profiling is on).
 hipError_t enqueue_batched_step(gcss_ctx *h, const BLayout &B, char *base, int nb, int kb,
-                                int grid) {
+                                int grid, bool timed = false) {
   auto at = [&](size_t off) { return base + off; };
   const int64_t m = h->d.m, ldq = h->L.ldq, r = h->r;
   double *Q = (double *)at(B.Q), *ap = (double *)at(B.ap64), *e1 = (double *)at(B.e1),
@@ -941,9 +966,11 @@ hipError_t enqueue_batched_step(gcss_ctx *h, const BLayout &B, char *base, int n
   if ((e = launch_rows(nullptr, h->B, h->ldb, m, 0, (int)r, -1, nullptr, A, ups, w, nullptr, RF_NONE, sb, s, nb, bs, ArgStride{0, 0, ldq, B.sUps}))) return e;
   if ((e = launch_cols(Q, nullptr, ldq, m, 1, 0, kb, VEC_F64, w, A, c3, CF_NONE, sb, s, nb, bs, ArgStride{B.sQ, ldq, B.sC, 0}))) return e;
   if ((e = launch_rows(Q, nullptr, ldq, m, 1, 0, VEC_F64, w, A, c3, nullptr, z32, RF_Z, sb, s, nb, bs, ArgStride{B.sQ, ldq, 0, B.sC}))) return e;
+  if (timed && h->profiling && (e = record(h))) return e;
   if ((e = launch_stream_batched(h->L.geo, grid, A, (const GroupEnt *)at(B.groups), (int64_t)h->bgroups.size(), q32, z32, B.sQ32,
                                  h->at<double>(h->L.f), h->at<double>(h->L.g), h->at<double>(h->L.g0), h->at<uint8_t>(h->L.mask),
                                  (ArgPart *)at(B.gpart), (const DevState *)at(B.st), (uint32_t *)at(B.bcnt), 0, s))) return e;
+  if (timed && h->profiling && (e = record(h))) return e;
   return launch_block_argmax(A, (const ArgPart *)at(B.gpart), (const int64_t *)at(B.gfirst), nb, (DevState *)at(B.st), ap, ldq, s);
 }
 
@@ -1008,7 +1035,37 @@ gcss_status gcss_select_batched(gcss_ctx *h, int32_t nblocks, const int64_t *col
   HIPCHK(batched_stream_grid(h->L.geo, h->d.a_dtype, h->num_cu, (int64_t)h->bgroups.size(),
                              h->tune.batch_wg_per_cu, &grid));
 
-  // lockstep loop of all blocks, captured once and replayed
+  // lockstep loop of all blocks, captured once and replayed; with profiling
+  // on it is enqueued directly, with events around every batched stream pass
+  if (h->profiling) {
+    h->ev_used = 0;
+    hipError_t e = launch_zero_f32((float *)(base + B.q32), (int64_t)nblocks * B.sQ32, s);
+    if (!e) e = launch_zero_f32((float *)(base + B.z32), (int64_t)nblocks * B.sQ32, s);
+    if (!e) e = launch_batch_begin(h->at<double>(h->L.f0), h->at<double>(h->L.g0), h->at<uint8_t>(h->L.mask0),
+                                   h->at<double>(h->L.f), h->at<double>(h->L.g), h->at<uint8_t>(h->L.mask), h->d.n,
+                                   (DevState *)(base + B.st), nblocks, k_block, (int64_t *)(base + B.idx),
+                                   (double *)(base + B.obj), B.sIO, h->F0(), h->d.tau, (uint32_t *)(base + B.bcnt), s);
+    if (!e) e = launch_stream_batched(h->L.geo, grid, h->A, (const GroupEnt *)(base + B.groups), (int64_t)h->bgroups.size(),
+                                      (const float *)(base + B.q32), (const float *)(base + B.z32), B.sQ32,
+                                      h->at<double>(h->L.f), h->at<double>(h->L.g), h->at<double>(h->L.g0),
+                                      h->at<uint8_t>(h->L.mask), (ArgPart *)(base + B.gpart), (const DevState *)(base + B.st),
+                                      (uint32_t *)(base + B.bcnt), 1, s);
+    if (!e) e = launch_block_argmax(h->A, (const ArgPart *)(base + B.gpart), (const int64_t *)(base + B.gfirst), nblocks,
+                                    (DevState *)(base + B.st), (double *)(base + B.ap64), h->L.ldq, s);
+    // (the spare steps, which return at once when every block is done, are
+    // not timed)
+    for (int i = 0; !e && i < k_block + kSpareSlots; ++i)
+      e = enqueue_batched_step(h, B, base, nblocks, k_block, grid, i < k_block);
+    if (e) return fail(GCSS_ERR_DEVICE, "batched loop: %s", hipGetErrorString(e));
+    HIPCHK(hipStreamSynchronize(s));
+    float ms = 0.f;
+    for (size_t x = 0; x + 1 < h->ev_used; x += 2) {
+      HIPCHK(hipEventElapsedTime(&ms, h->ev[x], h->ev[x + 1]));
+      h->prof.stream_ms += ms;
+      h->prof.stream_launches += 1;
+    }
+    h->prof.selects += 1;
+  } else {
   if (!h->bgraph) {
     if (!h->cap_stream) HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
     hipStream_t user = h->stream;
@@ -1047,6 +1104,7 @@ gcss_status gcss_select_batched(gcss_ctx *h, int32_t nblocks, const int64_t *col
     }
   }
   HIPCHK(hipGraphLaunch(h->bgraph, s));
+  }
 
   // per-block picks back to the host
   std::vector<int64_t> bidx((size_t)nblocks * B.sIO);
@@ -1054,6 +1112,28 @@ gcss_status gcss_select_batched(gcss_ctx *h, int32_t nblocks, const int64_t *col
   HIPCHK(hipMemcpyAsync(bidx.data(), base + B.idx, sizeof(int64_t) * bidx.size(), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(bst.data(), base + B.st, sizeof(DevState) * nblocks, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  // blocks whose basis check rejected more picks than the captured loop has
+  // spare steps for: more lockstep steps (finished blocks skip them) until
+  // every block has its k_block picks or has run out of candidates; each
+  // step adds a pick or drops a candidate, so this ends
+  {
+    int64_t wmax = 0;
+    for (int b = 0; b < nblocks; ++b) wmax = std::max<int64_t>(wmax, off[b + 1] - off[b]);
+    int64_t ran = 0;
+    for (;;) {
+      int need = 0;
+      for (int b = 0; b < nblocks; ++b)
+        if (!bst[b].done) need = std::max(need, std::max(1, k_block - bst[b].t));
+      if (need == 0) break;
+      if (ran > (int64_t)k_block + wmax)
+        return fail(GCSS_ERR_DEVICE, "batched selection did not finish after %lld extra steps", (long long)ran);
+      for (int i = 0; i < need; ++i) HIPCHK(enqueue_batched_step(h, B, base, nblocks, k_block, grid));
+      ran += need;
+      HIPCHK(hipMemcpyAsync(bidx.data(), base + B.idx, sizeof(int64_t) * bidx.size(), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(bst.data(), base + B.st, sizeof(DevState) * nblocks, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+    }
+  }
   std::vector<int64_t> pool;
   for (int b = 0; b < nblocks; ++b)
     for (int j = 0; j < k_block; ++j) {
@@ -1130,6 +1210,7 @@ gcss_status gcss_read_state(gcss_ctx *h, int32_t item, void *host, size_t bytes,
   const int64_t n = h->d.n, m = h->d.m;
   const void *src = nullptr;
   size_t sz = 0, spitch = 0, width = 0, rows = 0;
+  int32_t flags[4];
   DevState hs;
   HIPCHK(hipMemcpyAsync(&hs, h->at<DevState>(h->L.st), sizeof hs, hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
@@ -1148,10 +1229,18 @@ gcss_status gcss_read_state(gcss_ctx *h, int32_t item, void *host, size_t bytes,
       if (h->target != 2) return fail(GCSS_ERR_STATE, "no Gram target");
       src = h->at<float>(h->L.gram); spitch = 4 * h->L.ldq; width = 4 * m; rows = m; break;
     case GCSS_STATE_NREJECT: src = &hs.n_reject; sz = 4; break;
+    case GCSS_STATE_FLAGS: sz = sizeof flags; break;
     default: return fail(GCSS_ERR_ARG, "unknown item %d", item);
   }
   size_t done = 0;
-  if (item == GCSS_STATE_NREJECT) {
+  if (item == GCSS_STATE_FLAGS) {
+    flags[0] = hs.t;
+    flags[1] = hs.done;
+    flags[2] = hs.exhausted;
+    flags[3] = hs.n_reject;
+    done = std::min(bytes, sz);
+    memcpy(host, flags, done);
+  } else if (item == GCSS_STATE_NREJECT) {
     done = std::min(bytes, sz);
     memcpy(host, src, done);
   } else if (width) {

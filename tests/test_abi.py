@@ -132,3 +132,4 @@ def test_tuning_and_probe_check_arguments_first():
     assert lib.gcss_hbm_probe(0x10000, 1024, sink, 0, None, ctypes.byref(sec)) == g.ERR_ARG  # reps
     assert lib.gcss_hbm_probe(0x10000, 1024, None, 1, None, ctypes.byref(sec)) == g.ERR_ARG
     assert g.PROBE_SINK_FLOATS == 4096
+
