@@ -465,6 +465,31 @@ gcss_status gcss_autotune_batched(gcss_ctx *h, int32_t nblocks, const int64_t *c
 gcss_status gcss_hbm_probe(const void *buf, size_t bytes, float *sink, int32_t reps, void *stream,
                            double *seconds);
 
+/*
+ * Selection that allocates nothing, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  One call does what gcss_create + gcss_set_target(b, r,
+ * ldb) + gcss_select_async(k) do, with the workspace taken from a static
+ * device array of GCSS_STATIC_SCRATCH_BYTES bytes that the library's code
+ * object holds on every device it is loaded on until the process ends.
+ * d: as for gcss_create (d->stream orders all work; host struct read during
+ * the call only).  b, r, ldb: as for gcss_set_target (b == NULL, r == 0: B = A,
+ * needs d->self_target).  d_idx (k int64), d_obj (k+1 double, may be NULL),
+ * d_nsel (1 int32, may be NULL): device outputs as for gcss_select_async,
+ * written on the stream; the call does not synchronize.  Picks and objective
+ * are bitwise those of the context path with the default launch setting.
+ * The array keeps the last call's contents; every call initialises what it
+ * reads.  Calls that overlap on one device (other threads, or other streams
+ * before the previous call's work has finished) share the array and race:
+ * order them on one stream or wait for the previous one.
+ * Errors: GCSS_ERR_ARG, GCSS_ERR_STATE (B = A without self_target),
+ * GCSS_ERR_UNSUPPORTED (gcss_workspace_size(d) above the array's size; the
+ * message gives both), GCSS_ERR_DEVICE.
+ */
+#define GCSS_STATIC_SCRATCH_BYTES (64u << 20)
+gcss_status gcss_select_static(const gcss_desc *d, const float *b, int64_t r, int64_t ldb,
+                               int32_t k, int64_t *d_idx, double *d_obj, int32_t *d_nsel);
+
 /* Message for the last non-OK status returned on this thread ("" if none). */
 const char *gcss_last_error(void);
 

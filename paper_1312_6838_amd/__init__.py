@@ -14,7 +14,7 @@ from . import _abi
 from ._abi import (  # noqa: F401
     BF16, ERR_ARG, ERR_DEVICE, ERR_STATE, ERR_UNSUPPORTED, ERR_WORKSPACE, EXPORTS, F32,
     FP8_E4M3, OK, STATE_B, STATE_F, STATE_F0, STATE_G, STATE_G0, STATE_GRAM, STATE_NREJECT,
-    STATE_FLAGS, ASYNC_SPARE_STEPS,
+    STATE_FLAGS, ASYNC_SPARE_STEPS, STATIC_SCRATCH_BYTES, select_static,
     STATE_Q, STATE_Z, WARN_EXHAUSTED, Desc, GcssError, batched_workspace_size, create, destroy,
     last_error, load, make_desc, project_target, quantize, read_state, reconstruction_error,
     select, select_async, select_batched, set_target, version, workspace_size,
@@ -23,8 +23,8 @@ from ._abi import (  # noqa: F401
     PROBE_SINK_FLOATS,
 )
 
-__all__ = ["Selector", "quantize_tensor", "qless_r_tensor", "hbm_probe_tensor", "load",
-           "version", "GcssError"]
+__all__ = ["Selector", "quantize_tensor", "qless_r_tensor", "hbm_probe_tensor",
+           "select_static_tensor", "load", "version", "GcssError"]
 
 
 def _dtype_code(t):
@@ -248,6 +248,30 @@ class Selector:
             self.close()
         except Exception:
             pass
+
+
+def select_static_tensor(A, m, k, B=None, *, scales=None, tau=0.0, stream=None, out=None):
+    """One selection through the entry point that allocates no device memory
+    (its workspace is the library's static device array).  A: (n, lda) column
+    store; B: (r, ldb) float32 column store or None for B = A.  out: optional
+    (idx int64[k], obj float64[k+1], nsel int32[1]) cuda tensors, else
+    allocated here by torch.  Returns out; nothing is synchronised."""
+    import torch
+    if not A.is_cuda or A.dim() != 2 or not A.is_contiguous():
+        raise ValueError("A must be a contiguous 2-D cuda tensor of shape (n, lda)")
+    n, lda = A.shape
+    r, ldb = (0, 0) if B is None else B.shape
+    desc = make_desc(int(m), int(n), int(lda), _dtype_code(A), A.data_ptr(),
+                     scales.data_ptr() if scales is not None else None, int(k), int(r),
+                     B is None, tau, _stream_ptr(stream))
+    if out is None:
+        dev = A.device
+        out = (torch.empty(k, dtype=torch.int64, device=dev),
+               torch.empty(k + 1, dtype=torch.float64, device=dev),
+               torch.empty(1, dtype=torch.int32, device=dev))
+    select_static(desc, None if B is None else B.data_ptr(), int(r), int(ldb), int(k),
+                  out[0].data_ptr(), out[1].data_ptr(), out[2].data_ptr())
+    return out
 
 
 def hbm_probe_tensor(buf, reps=5, stream=None):

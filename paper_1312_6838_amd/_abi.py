@@ -35,8 +35,10 @@ EXPORTS = [
     "gcss_last_error", "gcss_version", "gcss_set_profiling", "gcss_get_profile",
     "gcss_set_embedding", "gcss_qless_r", "gcss_rank_k", "gcss_project_sign", "gcss_top_eig",
     "gcss_gather_columns", "gcss_get_tuning", "gcss_set_tuning", "gcss_autotune_select",
-    "gcss_autotune_batched", "gcss_hbm_probe",
+    "gcss_autotune_batched", "gcss_hbm_probe", "gcss_select_static",
 ]
+
+STATIC_SCRATCH_BYTES = 64 << 20
 
 PROBE_SINK_FLOATS = 4096
 
@@ -137,6 +139,8 @@ def load():
     lib.gcss_autotune_batched.restype = st
     lib.gcss_hbm_probe.argtypes = [_vp, _sz, _vp, _i32, _vp, _P(_dbl)]
     lib.gcss_hbm_probe.restype = st
+    lib.gcss_select_static.argtypes = [_P(Desc), _vp, _i64, _i64, _i32, _vp, _vp, _vp]
+    lib.gcss_select_static.restype = st
     lib.gcss_last_error.argtypes = []
     lib.gcss_last_error.restype = ctypes.c_char_p
     lib.gcss_version.argtypes = []
@@ -201,6 +205,13 @@ def select(h: int, k: int):
 
 def select_async(h: int, k: int, d_idx: int, d_obj: int | None, d_nsel: int | None) -> None:
     _check(load().gcss_select_async(h, k, d_idx, d_obj, d_nsel))
+
+
+def select_static(desc: Desc, b_ptr: int | None, r: int, ldb: int, k: int, d_idx: int,
+                  d_obj: int | None, d_nsel: int | None) -> None:
+    """The selection without device allocation (workspace in the library's
+    static device array); device outputs, no synchronisation."""
+    _check(load().gcss_select_static(ctypes.byref(desc), b_ptr, r, ldb, k, d_idx, d_obj, d_nsel))
 
 
 def reconstruction_error(h: int, idx) -> float:

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1279,6 +1280,69 @@ gcss_status gcss_set_tuning(gcss_ctx *h, const gcss_tuning *t) {
   h->bgraph = nullptr;
   h->L.geo = geo;
   h->tune = *t;
+  return GCSS_OK;
+}
+
+// ---- selection without device allocation -----------------------------------
+// The workspace of gcss_select_static: one array per device, allocated when
+// the library's code object is loaded and held until the process ends.  Its
+// host-side name is a stand-in, not a device address: kernels and copies
+// get the address hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) char scratch[GCSS_STATIC_SCRATCH_BYTES];
+
+}  // extern "C"
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch, looked up once per device.
+gcss_status scratch_for_current_device(void **ptr) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(GCSS_ERR_DEVICE, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(GCSS_ERR_DEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                  hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return GCSS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gcss_status gcss_select_static(const gcss_desc *d, const float *b, int64_t r, int64_t ldb,
+                               int32_t k, int64_t *d_idx, double *d_obj, int32_t *d_nsel) {
+  if (!d || !d_idx) return fail(GCSS_ERR_ARG, "null descriptor or d_idx");
+  if (k < 1 || k > d->k_max) return fail(GCSS_ERR_ARG, "k = %d outside [1, k_max = %d]", k, d->k_max);
+  size_t need = 0;
+  gcss_status st = gcss_workspace_size(d, &need);
+  if (st != GCSS_OK) return st;
+  if (need > (size_t)GCSS_STATIC_SCRATCH_BYTES)
+    return fail(GCSS_ERR_UNSUPPORTED,
+                "problem needs %zu bytes of workspace; the static scratch holds %zu "
+                "(use gcss_create with a caller workspace)",
+                need, (size_t)GCSS_STATIC_SCRATCH_BYTES);
+  void *ws = nullptr;
+  if ((st = scratch_for_current_device(&ws)) != GCSS_OK) return st;
+  gcss_ctx h;  // host state only, released on return; the device work keeps running
+  if ((st = init_ctx(&h, d, ws, (size_t)GCSS_STATIC_SCRATCH_BYTES)) != GCSS_OK) return st;
+  if ((st = gcss_set_target(&h, b, r, ldb)) != GCSS_OK) return st;
+  // the loop of gcss_select_async, enqueued directly (no graph, no events)
+  hipError_t e = enqueue_begin(&h, k);
+  for (int i = 0; !e && i < k + kSpareSlots; ++i) e = enqueue_step(&h);
+  if (!e) e = enqueue_exact_objective(&h);
+  if (!e) e = launch_finish(h.bufs(), k, d_idx, d_obj, d_nsel, h.stream);
+  if (e) return fail(GCSS_ERR_DEVICE, "static selection: %s", hipGetErrorString(e));
   return GCSS_OK;
 }
 

@@ -133,3 +133,18 @@ def test_tuning_and_probe_check_arguments_first():
     assert lib.gcss_hbm_probe(0x10000, 1024, None, 1, None, ctypes.byref(sec)) == g.ERR_ARG
     assert g.PROBE_SINK_FLOATS == 4096
 
+
+def test_static_selection_checks_arguments_before_the_device():
+    """gcss_select_static validates and sizes on the host first: a null
+    descriptor or a bad k is an argument error, a problem whose workspace
+    exceeds the static array is unsupported, all without touching a device."""
+    lib = g.load()
+    assert lib.gcss_select_static(None, None, 0, 0, 1, 0x1000, None, None) == g.ERR_ARG
+    d = _desc()
+    assert lib.gcss_select_static(ctypes.byref(d), None, 0, 0, 0, 0x1000, None, None) == g.ERR_ARG
+    assert lib.gcss_select_static(ctypes.byref(d), None, 0, 0, 11, 0x1000, None, None) == g.ERR_ARG
+    big = _desc(n=4_000_000, m=64, lda=64)
+    assert g.workspace_size(big) > g.STATIC_SCRATCH_BYTES
+    st = lib.gcss_select_static(ctypes.byref(big), None, 0, 0, 8, 0x1000, None, None)
+    assert st == g.ERR_UNSUPPORTED
+    assert "static scratch" in g.last_error()
