@@ -399,11 +399,15 @@ def test_batched_blocks_and_merge_match_oracle(gpu, dt):
         rb = oracle.select(f64cs(Av[:, off[b]:off[b + 1]]), m, kb, B=f64cs(Bv))
         sep = int(np.argmax(rb["gap"] < 1e-4)) if np.any(rb["gap"] < 1e-4) else kb
         assert _prefix_len(ib[b], ref["idx_block"][b]) >= sep, b
+    # the merge against the oracle run on the GPU's own pool (block order,
+    # then pick order), whatever the blocks picked
+    pool = [int(x) for x in ib.ravel() if x >= 0]
+    rm = oracle.select(f64cs(Av[:, pool]), m, km, B=f64cs(Bv))
+    sep = int(np.argmax(rm["gap"] < 1e-4)) if np.any(rm["gap"] < 1e-4) else km
+    got = _prefix_len(im, [pool[i] for i in rm["idx"]])
+    assert got >= sep
+    np.testing.assert_allclose(om[:got + 1], rm["obj"][:got + 1], rtol=1e-5)
     if np.array_equal(ib, ref["idx_block"]):
-        pool = [int(x) for x in ref["idx_block"].ravel() if x >= 0]
-        rm = oracle.select(f64cs(Av[:, pool]), m, km, B=f64cs(Bv))
-        sep = int(np.argmax(rm["gap"] < 1e-4)) if np.any(rm["gap"] < 1e-4) else km
-        assert _prefix_len(im, ref["idx_merge"]) >= sep
         np.testing.assert_allclose(om, ref["obj_merge"], rtol=1e-5)
     e_gpu = oracle.error(f64cs(Av), m, im, B=f64cs(Bv))
     e_orc = oracle.error(f64cs(Av), m, ref["idx_merge"], B=f64cs(Bv))
