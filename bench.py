@@ -248,7 +248,7 @@ def run_single(args, name, w, A, scales, Om, dtype, steps, warmup, extras=True):
         if self_target:
             sel.set_target(None)
         elif args.omega == "gauss":
-            sel.project_target(Om)
+            sel.project_target(Om, b_dtype=w.get("b_dtype", "f32"))
         else:
             sel.project_sign(1, r, density=1.0 if args.omega == "sign" else 1.0 / math.sqrt(n))
 
@@ -302,6 +302,7 @@ def run_single(args, name, w, A, scales, Om, dtype, steps, warmup, extras=True):
         "data": "synthetic",
         "config": {"workload": name, "m": m, "n": n, "k": k, "lda": int(A.shape[1]),
                    "target": "B = A" if self_target else f"B = A Omega, r = {r}",
+                   "b_storage": None if self_target else w.get("b_dtype", "f32"),
                    "a_storage": dtype, "embedding": bool(extras and args.embedding),
                    "omega": None if self_target else args.omega},
         "roofline": roof,

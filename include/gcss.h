@@ -98,27 +98,35 @@ void gcss_destroy(gcss_ctx *h);
 /*
  * Set the target and compute the initial scores of Algorithms 1/3:
  *     f_i = || B^T A_i ||^2 ,  g_i = || A_i ||^2 ,  F_0 = || B ||_F^2 .
- * b: device, borrowed, m x r binary32 column-major with leading dimension
- *    ldb >= m (ldb*4 a multiple of 16), 1 <= r <= r_max.
- * b == NULL and r == 0: B = A (Algorithm 1).  The target then enters only
- *    through its Gram matrix A A^T (m x m), which is formed in the workspace;
- *    requires self_target at creation.
- * Errors: GCSS_ERR_ARG, GCSS_ERR_STATE (self target not reserved),
- * GCSS_ERR_DEVICE.
+ * b: device, borrowed, m x r column-major with leading dimension ldb >= m
+ *    (ldb * element size a multiple of 16 bytes), 1 <= r <= r_max.
+ * b_dtype: GCSS_F32 (binary32) or GCSS_BF16 (bfloat16).  A bfloat16 target
+ *    is the matrix of its bfloat16 values: they are copied exactly into a
+ *    binary32 copy in the workspace, which every kernel then reads.
+ * b == NULL and r == 0: B = A (Algorithm 1; b_dtype is ignored).  The
+ *    target then enters only through its Gram matrix A A^T (m x m), which is
+ *    formed in the workspace; requires self_target at creation.
+ * Errors: GCSS_ERR_ARG (also an unknown b_dtype), GCSS_ERR_STATE (self
+ * target not reserved), GCSS_ERR_DEVICE.
  */
-gcss_status gcss_set_target(gcss_ctx *h, const float *b, int64_t r, int64_t ldb);
+gcss_status gcss_set_target(gcss_ctx *h, const void *b, int32_t b_dtype, int64_t r, int64_t ldb);
 
 /*
  * The paper's concise target (Section 5.1, Algorithm 2): B = A * Omega,
  * written to b_out, then set as the target as by gcss_set_target.
  * omega: device, n x r binary32 ROW-major (row i is the r-vector drawn for
  *        column i of A), borrowed only during the call.
- * b_out: device, m x r binary32 column-major, leading dimension ldb >= m;
- *        borrowed for the context's life (it becomes the target).
+ * b_out: device, m x r column-major, leading dimension ldb >= m (ldb *
+ *        element size a multiple of 16 bytes), 16-byte aligned; borrowed for
+ *        the context's life (it becomes the target).
+ * b_dtype: GCSS_F32 stores the binary32 product; GCSS_BF16 rounds each
+ *        binary32 entry once to the nearest bfloat16 (ties to even), and
+ *        those values are the target.  Rows m..ldb-1 of a bfloat16 b_out are
+ *        set to zero.
  * Errors: as gcss_set_target.
  */
-gcss_status gcss_project_target(gcss_ctx *h, const float *omega, int64_t r, float *b_out,
-                                int64_t ldb);
+gcss_status gcss_project_target(gcss_ctx *h, const float *omega, int64_t r, void *b_out,
+                                int32_t b_dtype, int64_t ldb);
 
 /*
  * Concise target from a random sign matrix drawn on the fly (Section 5.1:
@@ -350,7 +358,7 @@ typedef enum {
   GCSS_STATE_G = 3,     /* n doubles: g after the last select                   */
   GCSS_STATE_Q = 4,     /* m*t doubles: orthonormal basis of the picks (col-major, ld m) */
   GCSS_STATE_Z = 5,     /* m floats: z of the last completed step               */
-  GCSS_STATE_B = 6,     /* m*r floats: the explicit target (col-major, ld m)    */
+  GCSS_STATE_B = 6,     /* m*r floats: the explicit target's values (col-major, ld m) */
   GCSS_STATE_GRAM = 7,  /* m*m floats: the Gram target A A^T (self target)      */
   GCSS_STATE_NREJECT = 8, /* 1 int32: picks rejected by the basis check          */
   GCSS_STATE_FLAGS = 9    /* 4 int32 of the last select / select_async: picks made,
@@ -473,8 +481,8 @@ gcss_status gcss_hbm_probe(const void *buf, size_t bytes, float *sink, int32_t r
  * device array of GCSS_STATIC_SCRATCH_BYTES bytes that the library's code
  * object holds on every device it is loaded on until the process ends.
  * d: as for gcss_create (d->stream orders all work; host struct read during
- * the call only).  b, r, ldb: as for gcss_set_target (b == NULL, r == 0: B = A,
- * needs d->self_target).  d_idx (k int64), d_obj (k+1 double, may be NULL),
+ * the call only).  b, b_dtype, r, ldb: as for gcss_set_target (b == NULL,
+ * r == 0: B = A, needs d->self_target).  d_idx (k int64), d_obj (k+1 double, may be NULL),
  * d_nsel (1 int32, may be NULL): device outputs as for gcss_select_async,
  * written on the stream; the call does not synchronize.  Picks and objective
  * are bitwise those of the context path with the default launch setting.
@@ -487,8 +495,9 @@ gcss_status gcss_hbm_probe(const void *buf, size_t bytes, float *sink, int32_t r
  * message gives both), GCSS_ERR_DEVICE.
  */
 #define GCSS_STATIC_SCRATCH_BYTES (64u << 20)
-gcss_status gcss_select_static(const gcss_desc *d, const float *b, int64_t r, int64_t ldb,
-                               int32_t k, int64_t *d_idx, double *d_obj, int32_t *d_nsel);
+gcss_status gcss_select_static(const gcss_desc *d, const void *b, int32_t b_dtype, int64_t r,
+                               int64_t ldb, int32_t k, int64_t *d_idx, double *d_obj,
+                               int32_t *d_nsel);
 
 /* Message for the last non-OK status returned on this thread ("" if none). */
 const char *gcss_last_error(void);

@@ -38,6 +38,15 @@ def _dtype_code(t):
     raise TypeError(f"unsupported A dtype {t.dtype}")
 
 
+def _target_code(B):
+    import torch
+    if B.dtype == torch.float32:
+        return F32
+    if B.dtype in (torch.bfloat16, torch.int16, torch.uint16):
+        return BF16
+    raise TypeError(f"unsupported target dtype {B.dtype} (float32 or bfloat16)")
+
+
 def _stream_ptr(stream):
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
@@ -83,22 +92,25 @@ class Selector:
 
     # -- targets --
     def set_target(self, B=None):
-        """B: (r, ldb) float32 column store on the GPU, or None for B = A."""
+        """B: (r, ldb) float32 or bfloat16 column store on the GPU, or None for B = A."""
         if B is None:
             set_target(self.h, None, 0, 0)
             self.B, self.r = None, 0
         else:
             r, ldb = B.shape
-            set_target(self.h, B.data_ptr(), int(r), int(ldb))
+            set_target(self.h, B.data_ptr(), int(r), int(ldb), _target_code(B))
             self.B, self.r = B, int(r)
 
-    def project_target(self, Omega, ldb=None):
-        """B = A Omega; Omega (n, r) float32 row-major on the GPU.  Returns B (r, ldb)."""
+    def project_target(self, Omega, ldb=None, b_dtype="f32"):
+        """B = A Omega; Omega (n, r) float32 row-major on the GPU.  b_dtype "f32"
+        keeps the binary32 product, "bf16" rounds it to bfloat16.  Returns B
+        (r, ldb) as float32 or bfloat16."""
         import torch
         n, r = Omega.shape
         ldb = ldb or ((self.m + 63) // 64) * 64
-        B = torch.empty(int(r), int(ldb), dtype=torch.float32, device=self.A.device)
-        project_target(self.h, Omega.data_ptr(), int(r), B.data_ptr(), int(ldb))
+        tdt = {"f32": torch.float32, "bf16": torch.bfloat16}[b_dtype]
+        B = torch.empty(int(r), int(ldb), dtype=tdt, device=self.A.device)
+        project_target(self.h, Omega.data_ptr(), int(r), B.data_ptr(), int(ldb), _target_code(B))
         self.B, self.r, self._omega = B, int(r), Omega
         return B
 
@@ -253,7 +265,7 @@ class Selector:
 def select_static_tensor(A, m, k, B=None, *, scales=None, tau=0.0, stream=None, out=None):
     """One selection through the entry point that allocates no device memory
     (its workspace is the library's static device array).  A: (n, lda) column
-    store; B: (r, ldb) float32 column store or None for B = A.  out: optional
+    store; B: (r, ldb) float32 or bfloat16 column store, or None for B = A.  out: optional
     (idx int64[k], obj float64[k+1], nsel int32[1]) cuda tensors, else
     allocated here by torch.  Returns out; nothing is synchronised."""
     import torch
@@ -270,7 +282,8 @@ def select_static_tensor(A, m, k, B=None, *, scales=None, tau=0.0, stream=None, 
                torch.empty(k + 1, dtype=torch.float64, device=dev),
                torch.empty(1, dtype=torch.int32, device=dev))
     select_static(desc, None if B is None else B.data_ptr(), int(r), int(ldb), int(k),
-                  out[0].data_ptr(), out[1].data_ptr(), out[2].data_ptr())
+                  out[0].data_ptr(), out[1].data_ptr(), out[2].data_ptr(),
+                  F32 if B is None else _target_code(B))
     return out
 
 

@@ -93,9 +93,9 @@ def load():
     lib.gcss_create.restype = st
     lib.gcss_destroy.argtypes = [_vp]
     lib.gcss_destroy.restype = None
-    lib.gcss_set_target.argtypes = [_vp, _vp, _i64, _i64]
+    lib.gcss_set_target.argtypes = [_vp, _vp, _i32, _i64, _i64]
     lib.gcss_set_target.restype = st
-    lib.gcss_project_target.argtypes = [_vp, _vp, _i64, _vp, _i64]
+    lib.gcss_project_target.argtypes = [_vp, _vp, _i64, _vp, _i32, _i64]
     lib.gcss_project_target.restype = st
     lib.gcss_select.argtypes = [_vp, _i32, _vp, _vp, _vp]
     lib.gcss_select.restype = st
@@ -139,7 +139,7 @@ def load():
     lib.gcss_autotune_batched.restype = st
     lib.gcss_hbm_probe.argtypes = [_vp, _sz, _vp, _i32, _vp, _P(_dbl)]
     lib.gcss_hbm_probe.restype = st
-    lib.gcss_select_static.argtypes = [_P(Desc), _vp, _i64, _i64, _i32, _vp, _vp, _vp]
+    lib.gcss_select_static.argtypes = [_P(Desc), _vp, _i32, _i64, _i64, _i32, _vp, _vp, _vp]
     lib.gcss_select_static.restype = st
     lib.gcss_last_error.argtypes = []
     lib.gcss_last_error.restype = ctypes.c_char_p
@@ -185,12 +185,12 @@ def destroy(h: int) -> None:
     load().gcss_destroy(h)
 
 
-def set_target(h: int, b_ptr: int | None, r: int, ldb: int) -> None:
-    _check(load().gcss_set_target(h, b_ptr, r, ldb))
+def set_target(h: int, b_ptr: int | None, r: int, ldb: int, b_dtype: int = F32) -> None:
+    _check(load().gcss_set_target(h, b_ptr, b_dtype, r, ldb))
 
 
-def project_target(h: int, omega_ptr: int, r: int, b_ptr: int, ldb: int) -> None:
-    _check(load().gcss_project_target(h, omega_ptr, r, b_ptr, ldb))
+def project_target(h: int, omega_ptr: int, r: int, b_ptr: int, ldb: int, b_dtype: int = F32) -> None:
+    _check(load().gcss_project_target(h, omega_ptr, r, b_ptr, b_dtype, ldb))
 
 
 def select(h: int, k: int):
@@ -208,10 +208,11 @@ def select_async(h: int, k: int, d_idx: int, d_obj: int | None, d_nsel: int | No
 
 
 def select_static(desc: Desc, b_ptr: int | None, r: int, ldb: int, k: int, d_idx: int,
-                  d_obj: int | None, d_nsel: int | None) -> None:
+                  d_obj: int | None, d_nsel: int | None, b_dtype: int = F32) -> None:
     """The selection without device allocation (workspace in the library's
     static device array); device outputs, no synchronisation."""
-    _check(load().gcss_select_static(ctypes.byref(desc), b_ptr, r, ldb, k, d_idx, d_obj, d_nsel))
+    _check(load().gcss_select_static(ctypes.byref(desc), b_ptr, b_dtype, r, ldb, k, d_idx, d_obj,
+                                     d_nsel))
 
 
 def reconstruction_error(h: int, idx) -> float:

@@ -59,7 +59,7 @@ struct Carve {
 // Offsets of every workspace region for a description (sizes only).
 struct Layout {
   size_t f0, g0, f, g, mask0, mask, part, qpart, npart, Q, e1, e2, w, q64, q32, z32, c1, c2, c3, ups,
-      st, idx, obj, scal, pick, quad, ap64, gram, scratch, total;
+      st, idx, obj, scal, pick, quad, ap64, gram, bexp, scratch, total;
   size_t scratch_bytes;
   size_t qbuf;  // padded stream length of q32 / z32 / q64
   StreamGeo geo;
@@ -124,6 +124,9 @@ bool make_layout(const gcss_desc *d, int num_cu, Layout *L) {
   L->quad = c.take<double>(k + 8);
   L->ap64 = c.take<double>(L->ldq);
   L->gram = d->self_target ? c.take<float>((size_t)L->ldq * m) : 0;
+  // binary32 copy of a bfloat16 target (the values every B-reading kernel
+  // takes), leading dimension ldq
+  L->bexp = r > 0 ? c.take<float>((size_t)L->ldq * r) : 0;
   // transient scratch: split-K partials, or the reconstruction-error buffers
   size_t s = 0;
   if (d->self_target) s = std::max(s, gram_scratch_bytes(m, n, L->ldq, num_cu));
@@ -179,8 +182,11 @@ struct gcss_ctx {
   std::vector<int64_t> bcol_off;
   int bk = -1;
   hipGraphExec_t bgraph = nullptr;
-  const float *B = nullptr;
+  const float *B = nullptr;  // the target as binary32 (the caller's, or the copy of a BF16 one)
   int64_t r = 0, ldb = 0;
+  const void *Braw = nullptr;  // the caller's target as given
+  int b_dtype = GCSS_F32;
+  int64_t ldb_raw = 0;
   // caller's embedding W = Q^T A (row-major k_max x ldw), or none
   float *emb = nullptr;
   int64_t ldw = 0;
@@ -471,12 +477,13 @@ void gcss_destroy(gcss_ctx *h) {
   delete h;
 }
 
-gcss_status gcss_set_target(gcss_ctx *h, const float *b, int64_t r, int64_t ldb) {
+gcss_status gcss_set_target(gcss_ctx *h, const void *b, int32_t b_dtype, int64_t r,
+                            int64_t ldb) {
   if (check_ctx(h)) return GCSS_ERR_ARG;
-  h->q_from_select = false;
   const int64_t m = h->d.m;
   if (b == nullptr && r == 0) {
     if (!h->d.self_target) return fail(GCSS_ERR_STATE, "self target not reserved at creation");
+    h->q_from_select = false;
     float *C = h->at<float>(h->L.gram);
     HIPCHK(launch_gram(h->A, C, h->L.ldq, h->at<void>(h->L.scratch), h->num_cu, h->stream));
     HIPCHK(launch_init_gram(C, h->L.ldq, h->A, h->at<double>(h->L.f0), h->at<double>(h->L.g0),
@@ -486,19 +493,38 @@ gcss_status gcss_set_target(gcss_ctx *h, const float *b, int64_t r, int64_t ldb)
     h->B = nullptr;
     h->r = 0;
     h->ldb = 0;
+    h->Braw = nullptr;
+    h->b_dtype = GCSS_F32;
+    h->ldb_raw = 0;
   } else {
     if (!b) return fail(GCSS_ERR_ARG, "null B with r = %lld", (long long)r);
+    if (b_dtype != GCSS_F32 && b_dtype != GCSS_BF16)
+      return fail(GCSS_ERR_ARG, "b_dtype must be GCSS_F32 or GCSS_BF16");
     if (r < 1 || r > h->d.r_max) return fail(GCSS_ERR_ARG, "r = %lld outside [1, r_max = %lld]", (long long)r, (long long)h->d.r_max);
-    if (ldb < m || (ldb * 4) % 16) return fail(GCSS_ERR_ARG, "ldb must be >= m and a multiple of 4");
+    const int64_t es = b_dtype == GCSS_F32 ? 4 : 2;
+    if (ldb < m || (ldb * es) % 16) return fail(GCSS_ERR_ARG, "ldb must be >= m and ldb * element size a multiple of 16 bytes");
     if (((uintptr_t)b) % 16) return fail(GCSS_ERR_ARG, "B must be 16-byte aligned");
-    HIPCHK(launch_init_factor(b, ldb, r, h->A, h->at<double>(h->L.f0), h->at<double>(h->L.g0),
+    h->q_from_select = false;
+    const float *bf = (const float *)b;
+    int64_t ldbf = ldb;
+    if (b_dtype == GCSS_BF16) {
+      // the bfloat16 values, exactly, as binary32 for the kernels that read B
+      float *x = h->at<float>(h->L.bexp);
+      HIPCHK(launch_bf16_to_f32(b, m, r, ldb, x, h->L.ldq, h->stream));
+      bf = x;
+      ldbf = h->L.ldq;
+    }
+    HIPCHK(launch_init_factor(bf, ldbf, r, h->A, h->at<double>(h->L.f0), h->at<double>(h->L.g0),
                               h->at<uint8_t>(h->L.mask0), h->stream));
     // (the step buffer for upsilon, r_max + 8 doubles, is free here)
-    HIPCHK(launch_sumsq_f32(b, m, r, ldb, h->F0(), h->at<double>(h->L.ups), h->stream));
+    HIPCHK(launch_sumsq_f32(bf, m, r, ldbf, h->F0(), h->at<double>(h->L.ups), h->stream));
     h->target = 1;
-    h->B = b;
+    h->B = bf;
     h->r = r;
-    h->ldb = ldb;
+    h->ldb = ldbf;
+    h->Braw = b;
+    h->b_dtype = b_dtype;
+    h->ldb_raw = ldb;
   }
   h->basis_valid = false;
   drop_graph(h);
@@ -507,15 +533,26 @@ gcss_status gcss_set_target(gcss_ctx *h, const float *b, int64_t r, int64_t ldb)
   return GCSS_OK;
 }
 
-gcss_status gcss_project_target(gcss_ctx *h, const float *omega, int64_t r, float *b_out,
-                                int64_t ldb) {
+gcss_status gcss_project_target(gcss_ctx *h, const float *omega, int64_t r, void *b_out,
+                                int32_t b_dtype, int64_t ldb) {
   if (check_ctx(h)) return GCSS_ERR_ARG;
   if (!omega || !b_out) return fail(GCSS_ERR_ARG, "null omega or b_out");
   if (r < 1 || r > h->d.r_max) return fail(GCSS_ERR_ARG, "r outside [1, r_max]");
-  if (ldb < h->d.m || (ldb * 4) % 16) return fail(GCSS_ERR_ARG, "ldb must be >= m and a multiple of 4");
+  if (b_dtype != GCSS_F32 && b_dtype != GCSS_BF16)
+    return fail(GCSS_ERR_ARG, "b_dtype must be GCSS_F32 or GCSS_BF16");
+  const int64_t es = b_dtype == GCSS_F32 ? 4 : 2;
+  if (ldb < h->d.m || (ldb * es) % 16) return fail(GCSS_ERR_ARG, "ldb must be >= m and ldb * element size a multiple of 16 bytes");
   if (((uintptr_t)omega) % 16 || ((uintptr_t)b_out) % 16) return fail(GCSS_ERR_ARG, "omega and b_out must be 16-byte aligned");
-  HIPCHK(launch_project(h->A, omega, r, b_out, ldb, h->at<void>(h->L.scratch), h->num_cu, h->stream));
-  return gcss_set_target(h, b_out, r, ldb);
+  if (b_dtype == GCSS_F32) {
+    HIPCHK(launch_project(h->A, omega, r, (float *)b_out, ldb, h->at<void>(h->L.scratch), h->num_cu, h->stream));
+  } else {
+    // binary32 product into the target copy, rounded once (nearest, ties
+    // to even) into the caller's bfloat16 buffer, which becomes the target
+    float *x = h->at<float>(h->L.bexp);
+    HIPCHK(launch_project(h->A, omega, r, x, h->L.ldq, h->at<void>(h->L.scratch), h->num_cu, h->stream));
+    HIPCHK(launch_quantize(x, h->d.m, r, h->L.ldq, GCSS_BF16, b_out, ldb, nullptr, h->stream));
+  }
+  return gcss_set_target(h, b_out, b_dtype, r, ldb);
 }
 
 gcss_status gcss_project_sign(gcss_ctx *h, uint64_t seed, double density, int64_t r,
@@ -528,7 +565,7 @@ gcss_status gcss_project_sign(gcss_ctx *h, uint64_t seed, double density, int64_
   if (((uintptr_t)b_out) % 16) return fail(GCSS_ERR_ARG, "b_out must be 16-byte aligned");
   HIPCHK(launch_project_sign(h->A, seed, density, r, b_out, ldb, h->at<void>(h->L.scratch),
                              h->L.scratch_bytes, h->stream));
-  return gcss_set_target(h, b_out, r, ldb);
+  return gcss_set_target(h, b_out, GCSS_F32, r, ldb);
 }
 
 gcss_status gcss_select(gcss_ctx *h, int32_t k, int64_t *idx, double *objective,
@@ -1165,7 +1202,7 @@ gcss_status gcss_select_batched(gcss_ctx *h, int32_t nblocks, const int64_t *col
   gcss_ctx *sub = nullptr;
   st = gcss_create(&sd, base + B.sub, sub_bytes, &sub);
   if (st != GCSS_OK) return st;
-  st = gcss_set_target(sub, h->B, h->r, h->ldb);
+  st = gcss_set_target(sub, h->B, GCSS_F32, h->r, h->ldb);
   std::vector<int64_t> loc(km, -1);
   std::vector<double> obj(km + 1, 0.0);
   int32_t ns = 0;
@@ -1320,8 +1357,9 @@ gcss_status scratch_for_current_device(void **ptr) {
 
 extern "C" {
 
-gcss_status gcss_select_static(const gcss_desc *d, const float *b, int64_t r, int64_t ldb,
-                               int32_t k, int64_t *d_idx, double *d_obj, int32_t *d_nsel) {
+gcss_status gcss_select_static(const gcss_desc *d, const void *b, int32_t b_dtype, int64_t r,
+                               int64_t ldb, int32_t k, int64_t *d_idx, double *d_obj,
+                               int32_t *d_nsel) {
   if (!d || !d_idx) return fail(GCSS_ERR_ARG, "null descriptor or d_idx");
   if (k < 1 || k > d->k_max) return fail(GCSS_ERR_ARG, "k = %d outside [1, k_max = %d]", k, d->k_max);
   size_t need = 0;
@@ -1336,7 +1374,7 @@ gcss_status gcss_select_static(const gcss_desc *d, const float *b, int64_t r, in
   if ((st = scratch_for_current_device(&ws)) != GCSS_OK) return st;
   gcss_ctx h;  // host state only, released on return; the device work keeps running
   if ((st = init_ctx(&h, d, ws, (size_t)GCSS_STATIC_SCRATCH_BYTES)) != GCSS_OK) return st;
-  if ((st = gcss_set_target(&h, b, r, ldb)) != GCSS_OK) return st;
+  if ((st = gcss_set_target(&h, b, b_dtype, r, ldb)) != GCSS_OK) return st;
   // the loop of gcss_select_async, enqueued directly (no graph, no events)
   hipError_t e = enqueue_begin(&h, k);
   for (int i = 0; !e && i < k + kSpareSlots; ++i) e = enqueue_step(&h);

@@ -204,6 +204,9 @@ hipError_t launch_obj_from_quad(const double *F0, const double *quad, const DevS
 // ---- launchers (k_quant.hip) ----
 hipError_t launch_quantize(const float *a, int64_t m, int64_t n, int64_t lda, int dtype,
                            void *out, int64_t ldo, float *scales, hipStream_t s);
+// out (m x n binary32, ldo) = the bfloat16 matrix in (ldi), exactly
+hipError_t launch_bf16_to_f32(const void *in, int64_t m, int64_t n, int64_t ldi, float *out,
+                              int64_t ldo, hipStream_t s);
 // ---- launchers (k_sign.hip, k_mfma.hip): B = A Omega, random sign Omega ----
 // threshold of sign_entry for a density in (0, 1] (round(d 2^31), >= 1)
 uint32_t sign_threshold(double density);

@@ -56,6 +56,27 @@ __global__ __launch_bounds__(256) void k_quantize(const float *__restrict__ a, i
   for (int64_t j = lane; j < ldo; j += 64) dst[j] = j < m ? fp8_rne_sat(src[j] / s) : (uint8_t)0;
 }
 
+// out[j + c*ldo] = the bfloat16 value in[j + c*ldi] as binary32 (exact),
+// rows m..ldo-1 set to zero.  One wavefront per column.
+__global__ __launch_bounds__(256) void k_bf16_to_f32(const uint16_t *__restrict__ in, int64_t m,
+                                                     int64_t n, int64_t ldi,
+                                                     float *__restrict__ out, int64_t ldo) {
+  const int lane = threadIdx.x & 63;
+  const int64_t col = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (col >= n) return;
+  const uint16_t *src = in + col * ldi;
+  float *dst = out + col * ldo;
+  for (int64_t j = lane; j < ldo; j += 64)
+    dst[j] = j < m ? __uint_as_float((uint32_t)src[j] << 16) : 0.f;
+}
+
+hipError_t launch_bf16_to_f32(const void *in, int64_t m, int64_t n, int64_t ldi, float *out,
+                              int64_t ldo, hipStream_t s) {
+  hipLaunchKernelGGL(k_bf16_to_f32, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s,
+                     (const uint16_t *)in, m, n, ldi, out, ldo);
+  return hipGetLastError();
+}
+
 hipError_t launch_quantize(const float *a, int64_t m, int64_t n, int64_t lda, int dtype,
                            void *out, int64_t ldo, float *scales, hipStream_t s) {
   hipLaunchKernelGGL(k_quantize, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, a, m, n, lda,

@@ -156,7 +156,7 @@ WORKLOADS = {
     # fp8 stream
     "gcss_fp8_8192x262144_r512_k500": dict(m=8192, n=262144, kind="spectral", rank=2048,
                                            decay=0.5, noise=1e-3, target="proj", r=512,
-                                           k=500),
+                                           k=500, b_dtype="bf16"),
 }
 
 

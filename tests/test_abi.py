@@ -95,7 +95,7 @@ def test_null_context_calls_fail_cleanly():
     lib = g.load()
     idx = (ctypes.c_int64 * 4)()
     assert lib.gcss_select(None, 4, idx, None, None) == g.ERR_ARG
-    assert lib.gcss_set_target(None, None, 0, 0) == g.ERR_ARG
+    assert lib.gcss_set_target(None, None, 0, 0, 0) == g.ERR_ARG
     err = ctypes.c_double()
     assert lib.gcss_reconstruction_error(None, idx, 1, ctypes.byref(err)) == g.ERR_ARG
     lib.gcss_destroy(None)  # NULL-safe
@@ -139,12 +139,12 @@ def test_static_selection_checks_arguments_before_the_device():
     descriptor or a bad k is an argument error, a problem whose workspace
     exceeds the static array is unsupported, all without touching a device."""
     lib = g.load()
-    assert lib.gcss_select_static(None, None, 0, 0, 1, 0x1000, None, None) == g.ERR_ARG
+    assert lib.gcss_select_static(None, None, 0, 0, 0, 1, 0x1000, None, None) == g.ERR_ARG
     d = _desc()
-    assert lib.gcss_select_static(ctypes.byref(d), None, 0, 0, 0, 0x1000, None, None) == g.ERR_ARG
-    assert lib.gcss_select_static(ctypes.byref(d), None, 0, 0, 11, 0x1000, None, None) == g.ERR_ARG
+    assert lib.gcss_select_static(ctypes.byref(d), None, 0, 0, 0, 0, 0x1000, None, None) == g.ERR_ARG
+    assert lib.gcss_select_static(ctypes.byref(d), None, 0, 0, 0, 11, 0x1000, None, None) == g.ERR_ARG
     big = _desc(n=4_000_000, m=64, lda=64)
     assert g.workspace_size(big) > g.STATIC_SCRATCH_BYTES
-    st = lib.gcss_select_static(ctypes.byref(big), None, 0, 0, 8, 0x1000, None, None)
+    st = lib.gcss_select_static(ctypes.byref(big), None, 0, 0, 0, 8, 0x1000, None, None)
     assert st == g.ERR_UNSUPPORTED
     assert "static scratch" in g.last_error()

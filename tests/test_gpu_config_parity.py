@@ -9,11 +9,12 @@ configurations (Algorithms 1, 3 and 4), not only on the small cases:
   kernel as the full size): A 4096 x 8192 of the 4096 x 65536 B = A workload
   (k = 200), A 2048 x 131072 of the 2048 x 2^20 projection workload in
   binary32 and bfloat16 (r = 256, k = 100), A 8192 x 16384 of the FP8 E4M3
-  workload (r = 512, k = 500).
+  workload (r = 512 stored in bfloat16 as configured, k = 500).
 
 The oracle runs on the stored values (decoded bfloat16 / E4M3 codes from its
-own quantizer, which must equal the GPU's codes) and on the same binary32
-target B, formed on the host in FP64 as A_s Omega_s and rounded once.
+own quantizer, which must equal the GPU's codes) and on the same target B,
+formed on the host in FP64 as A_s Omega_s and rounded once to binary32
+(then to bfloat16 where the workload stores B so).
 Checks (the benchmark spec tolerances, binary32 arithmetic on the GPU):
   * A1: identical picks up to the first step whose oracle score gap
     (s1 - s2)/s1 is below 1e-4;
@@ -82,14 +83,19 @@ def _stored_host(A32, m, dt, sl):
     return oracle.decode_columns(codes, m, "fp8", scl), dcodes, dsc
 
 
-def _target(Acs, m, Om, ldb):
-    """B = A Omega in FP64 (oracle definition), rounded once to binary32:
-    host values (r, m) float64 and the GPU column store (r, ldb) float32."""
+def _target(Acs, m, Om, ldb, bdt="f32"):
+    """B = A Omega in FP64 (oracle definition), rounded once to binary32 (and,
+    for a bfloat16 target, from there to bfloat16 by the oracle's encoder):
+    host values (r, m) float64 and the GPU column store (r, ldb)."""
     import torch
     B64 = dense.project(Acs, m, Om.astype(np.float64), chunk=16384)       # m x r
     B32 = B64.astype(np.float32)
     Bcs = np.zeros((B32.shape[1], ldb), dtype=np.float32)
     Bcs[:, :m] = B32.T
+    if bdt == "bf16":
+        codes = oracle.quantize_bf16(Bcs, m, ldo=ldb)
+        vals = oracle.decode_columns(codes, m, "bf16")
+        return vals, torch.from_numpy(codes.view(np.int16)).cuda().view(torch.bfloat16)
     return np.ascontiguousarray(B32.T.astype(np.float64)), torch.from_numpy(Bcs).cuda()
 
 
@@ -132,7 +138,7 @@ def test_config_slice_matches_oracle(gpu, name, dt, ns):
     else:
         Om = synth.omega_gauss_torch(n, w["r"], seed=1)[sl].cpu().numpy()
         del A32
-        Bh, Bdev = _target(Acs, m, Om, synth.lda_for(m, 4))
+        Bh, Bdev = _target(Acs, m, Om, synth.lda_for(m, 4), w.get("b_dtype", "f32"))
         s = gpu.Selector(Adev, m, k_max=k, r_max=w["r"], scales=sc)
         s.set_target(Bdev)
     torch.cuda.synchronize()
