@@ -42,6 +42,7 @@ gcss_status fail(gcss_status s, const char *fmt, ...) {
 constexpr int kPlanCU = 256;       // CU count used to size the workspace (MI355X)
 constexpr int kSpareSlots = GCSS_ASYNC_SPARE_STEPS;  // extra steps of a captured loop (rejected picks)
 constexpr double kBasisTau = 1e-13;  // dependence threshold of the basis-only mode
+constexpr size_t kChainLdsMax = 60 * 1024;  // LDS the chain's row kernels may take
 
 inline size_t up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 inline int64_t ld_for(int64_t m) { return (int64_t)up((size_t)m, 64); }
@@ -59,7 +60,9 @@ struct Carve {
 // Offsets of every workspace region for a description (sizes only).
 struct Layout {
   size_t f0, g0, f, g, mask0, mask, part, qpart, npart, Q, e1, e2, w, q64, q32, z32, c1, c2, c3, ups,
-      st, idx, obj, scal, pick, quad, ap64, gram, bexp, scratch, total;
+      st, idx, obj, scal, pick, quad, ap64, gram, bexp, V, P, Pn, Pu, scratch, total;
+  int64_t lp;      // row stride of the dot partials of the per-step chain
+  bool chain;      // the per-step chain kernels fit (their LDS holds r_max + k_max + 1 doubles)
   size_t scratch_bytes;
   size_t qbuf;  // padded stream length of q32 / z32 / q64
   StreamGeo geo;
@@ -127,6 +130,14 @@ bool make_layout(const gcss_desc *d, int num_cu, Layout *L) {
   // binary32 copy of a bfloat16 target (the values every B-reading kernel
   // takes), leading dimension ldq
   L->bexp = r > 0 ? c.take<float>((size_t)L->ldq * r) : 0;
+  // the per-step chain: w history V (as Q), dot partials per row block of
+  // 1024 rows, and one norm and one u2 partial per 32-row workgroup
+  L->chain = chain_lds_bytes(r, (int)k) <= kChainLdsMax;
+  L->lp = (int64_t)up((size_t)(r + k + 1), 4);
+  L->V = c.take<double>((size_t)L->ldq * (k + 1));
+  L->P = c.take<double>((size_t)chain_row_blocks(m) * L->lp);
+  L->Pn = c.take<double>(chain_row_groups(m));
+  L->Pu = c.take<double>(chain_row_groups(m));
   // transient scratch: split-K partials, or the reconstruction-error buffers
   size_t s = 0;
   if (d->self_target) s = std::max(s, gram_scratch_bytes(m, n, L->ldq, num_cu));
@@ -203,9 +214,13 @@ struct gcss_ctx {
   gcss_profile prof{};
   // launch settings of the streaming passes
   gcss_tuning tune{};
-  // captured loop
+  // per-step work by the six-kernel chain (else the general cols / rows kernels)
+  bool use_chain = false;
+  // captured loops: select_async's (with its output copy) and select's
   hipGraphExec_t graph = nullptr;
   int graph_k = -1;
+  hipGraphExec_t sgraph = nullptr;
+  int sgraph_k = -1;
   void *graph_out[3] = {nullptr, nullptr, nullptr};
 
   template <typename T>
@@ -237,7 +252,11 @@ void drop_graph(gcss_ctx *h) {
   if (h->graph) (void)hipGraphExecDestroy(h->graph);
   h->graph = nullptr;
   h->graph_k = -1;
+  if (h->sgraph) (void)hipGraphExecDestroy(h->sgraph);
+  h->sgraph = nullptr;
+  h->sgraph_k = -1;
 }
+
 
 const char *tuning_error(const gcss_tuning &t) {
   if (t.stream_pd != 1 && t.stream_pd != 2) return "stream_pd must be 1 or 2";
@@ -296,8 +315,46 @@ hipError_t record(gcss_ctx *h) {
   return hipEventRecord(e, h->stream);
 }
 
-// One greedy step: basis update, target ops, fused stream.
-hipError_t enqueue_step(gcss_ctx *h) {
+// The per-step chain of six kernels (k_chain.hip): basis update, target ops.
+hipError_t enqueue_chain(gcss_ctx *h) {
+  ChainArgs ca{};
+  ca.st = h->at<DevState>(h->L.st);
+  ca.Q = h->at<double>(h->L.Q);
+  ca.ldq = h->L.ldq;
+  ca.V = h->at<double>(h->L.V);
+  ca.a = h->at<double>(h->L.ap64);
+  ca.e1 = h->at<double>(h->L.e1);
+  ca.e2 = h->at<double>(h->L.e2);
+  ca.P = h->at<double>(h->L.P);
+  ca.lp = h->L.lp;
+  ca.Pn = h->at<double>(h->L.Pn);
+  ca.Pu = h->at<double>(h->L.Pu);
+  if (h->target == 2) {
+    ca.B = h->at<float>(h->L.gram);
+    ca.ldb = h->L.ldq;
+    ca.r = 0;
+    ca.gram = 1;
+  } else {
+    ca.B = h->Braw;
+    ca.ldb = h->ldb_raw;
+    ca.r = h->r;
+    ca.b_bf16 = h->b_dtype == GCSS_BF16;
+  }
+  ca.q64 = h->at<double>(h->L.q64);
+  ca.q32 = h->at<float>(h->L.q32);
+  ca.z32 = h->at<float>(h->L.z32);
+  ca.g0 = h->at<double>(h->L.g0);
+  ca.mask = h->at<uint8_t>(h->L.mask);
+  ca.idx = h->at<int64_t>(h->L.idx);
+  ca.obj = h->at<double>(h->L.obj);
+  ca.m = h->d.m;
+  ca.kmax = h->d.k_max;
+  return launch_chain(ca, h->stream);
+}
+
+// Basis update and target ops of one step with the general column-dot and
+// row-update kernels (k_gemv.hip): eight launches.
+hipError_t enqueue_general(gcss_ctx *h) {
   const StepBufs sb = h->bufs();
   const int64_t m = h->d.m, ldq = h->L.ldq;
   const int kmax = h->d.k_max;
@@ -320,16 +377,22 @@ hipError_t enqueue_step(gcss_ctx *h) {
     if ((e = launch_cols(Q, nullptr, ldq, m, 1, 1, kmax + 1, VEC_F64, w, h->A, c3, CF_GRAM_U2, sb, s))) return e;
   }
   // z = w - Q_{t-1} c3 ; record the pick
-  if ((e = launch_rows(Q, nullptr, ldq, m, 1, 0, VEC_F64, w, h->A, c3, nullptr, h->at<float>(h->L.z32), RF_Z, sb, s))) return e;
+  return launch_rows(Q, nullptr, ldq, m, 1, 0, VEC_F64, w, h->A, c3, nullptr, h->at<float>(h->L.z32), RF_Z, sb, s);
+}
+
+// One greedy step: basis update and target ops, then the fused stream.
+hipError_t enqueue_step(gcss_ctx *h) {
+  hipError_t e = h->use_chain ? enqueue_chain(h) : enqueue_general(h);
+  if (e) return e;
   if (h->profiling && (e = record(h))) return e;
   // Gram target: the pass also returns the exact decrease ||A^T q||^2
   const bool ex = h->target == 2;
   if ((e = launch_stream(h->L.geo, h->A, h->at<float>(h->L.q32), h->at<double>(h->L.q64),
                          h->at<float>(h->L.z32), h->at<double>(h->L.f), h->at<double>(h->L.g),
                          h->at<double>(h->L.g0), h->at<uint8_t>(h->L.mask),
-                         h->at<ArgPart>(h->L.part), sb.st, h->at<double>(h->L.ap64), 0,
-                         ex ? h->at<double>(h->L.qpart) : nullptr,
-                         ex ? h->at<double>(h->L.quad) : nullptr, h->emb, h->ldw, s)))
+                         h->at<ArgPart>(h->L.part), h->at<DevState>(h->L.st),
+                         h->at<double>(h->L.ap64), 0, ex ? h->at<double>(h->L.qpart) : nullptr,
+                         ex ? h->at<double>(h->L.quad) : nullptr, h->emb, h->ldw, h->stream)))
     return e;
   if (h->profiling && (e = record(h))) return e;
   return hipSuccess;
@@ -357,6 +420,37 @@ hipError_t enqueue_begin(gcss_ctx *h, int k) {
                        h->at<double>(h->L.g0), h->at<uint8_t>(h->L.mask),
                        h->at<ArgPart>(h->L.part), sb.st, h->at<double>(h->L.ap64), 1, nullptr,
                        nullptr, nullptr, 0, h->stream);
+}
+
+// Capture begin + k + kSpareSlots steps + the exact objective (and, with
+// outputs given, the copy to them) on the capture stream and instantiate it.
+hipError_t capture_loop(gcss_ctx *h, int k, int64_t *d_idx, double *d_obj, int32_t *d_nsel,
+                        bool finish, hipGraphExec_t *out) {
+  if (!h->cap_stream) {
+    hipError_t e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
+    if (e) return e;
+  }
+  hipStream_t user = h->stream;
+  const bool prof = h->profiling;
+  h->profiling = false;
+  h->stream = h->cap_stream;
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeRelaxed);
+  if (!e) e = enqueue_begin(h, k);
+  for (int i = 0; !e && i < k + kSpareSlots; ++i) e = enqueue_step(h);
+  if (!e) e = enqueue_exact_objective(h);
+  if (!e && finish) e = launch_finish(h->bufs(), k, d_idx, d_obj, d_nsel, h->cap_stream);
+  hipError_t e2 = hipStreamEndCapture(h->cap_stream, &g);
+  h->stream = user;
+  h->profiling = prof;
+  if (e || e2) {
+    if (g) (void)hipGraphDestroy(g);
+    return e ? e : e2;
+  }
+  e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e) *out = nullptr;
+  return e;
 }
 
 gcss_status check_ctx(gcss_ctx *h) {
@@ -433,6 +527,11 @@ gcss_status init_ctx(gcss_ctx *h, const gcss_desc *d, void *workspace, size_t ws
   if (!(h->d.tau > 0.0)) h->d.tau = 1e-4;
   h->L = L;
   h->tune = tune;
+  // GCSS_CHAIN=1 in the environment selects the per-step chain kernels
+  {
+    const char *v = getenv("GCSS_CHAIN");
+    h->use_chain = L.chain && v && atoi(v) == 1;
+  }
   h->ws = (char *)workspace;
   h->ws_bytes = ws_bytes;
   h->A.a = d->a;
@@ -582,24 +681,41 @@ gcss_status gcss_select(gcss_ctx *h, int32_t k, int64_t *idx, double *objective,
     if (!loop0 || !loop1) return fail(GCSS_ERR_DEVICE, "event create failed");
     HIPCHK(hipEventRecord(loop0, h->stream));
   }
-  HIPCHK(enqueue_begin(h, k));
+  // The loop is replayed from a captured graph (begin, k + spare steps, the
+  // exact objective); with profiling on it is enqueued directly, with events.
+  int64_t ran = 0;
+  if (h->profiling) {
+    HIPCHK(enqueue_begin(h, k));
+    for (int i = 0; i < k; ++i) HIPCHK(enqueue_step(h));
+    ran = k;
+  } else {
+    if (!h->sgraph || h->sgraph_k != k) {
+      if (h->sgraph) (void)hipGraphExecDestroy(h->sgraph);
+      h->sgraph = nullptr;
+      hipError_t e = capture_loop(h, k, nullptr, nullptr, nullptr, false, &h->sgraph);
+      if (e) return fail(GCSS_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+      h->sgraph_k = k;
+    }
+    HIPCHK(hipGraphLaunch(h->sgraph, h->stream));
+    ran = k + kSpareSlots;
+  }
   DevState hs;
   // Every step either adds a pick or drops its candidate for good (a pick
   // the basis check rejects), so at most k + n steps end any selection.
-  int slots = k;
-  int64_t ran = 0;
+  bool extra = false;
   for (;;) {
-    for (int i = 0; i < slots; ++i) HIPCHK(enqueue_step(h));
-    ran += slots;
     HIPCHK(hipMemcpyAsync(&hs, h->at<DevState>(h->L.st), sizeof hs, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     if (hs.done) break;
     if (ran > (int64_t)k + h->d.n)
       return fail(GCSS_ERR_DEVICE, "selection did not finish after %lld steps", (long long)ran);
-    slots = k - hs.t;  // picks were rejected: run the missing steps
+    int slots = k - hs.t;  // picks were rejected: run the missing steps
     if (slots < 1) slots = 1;
+    for (int i = 0; i < slots; ++i) HIPCHK(enqueue_step(h));
+    ran += slots;
+    extra = true;
   }
-  HIPCHK(enqueue_exact_objective(h));
+  if (h->profiling || extra) HIPCHK(enqueue_exact_objective(h));
   if (h->profiling) {
     HIPCHK(hipEventRecord(loop1, h->stream));
     HIPCHK(hipEventSynchronize(loop1));
@@ -640,31 +756,11 @@ gcss_status gcss_select_async(gcss_ctx *h, int32_t k, int64_t *d_idx, double *d_
   const bool reuse = h->graph && h->graph_k == k && h->graph_out[0] == (void *)d_idx &&
                      h->graph_out[1] == (void *)d_obj && h->graph_out[2] == (void *)d_nsel;
   if (!reuse) {
-    drop_graph(h);
-    if (!h->cap_stream) HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
-    hipStream_t user = h->stream;
-    const bool prof = h->profiling;
-    h->profiling = false;
-    h->stream = h->cap_stream;
-    hipGraph_t g = nullptr;
-    hipError_t e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeRelaxed);
-    if (!e) e = enqueue_begin(h, k);
-    for (int i = 0; !e && i < k + kSpareSlots; ++i) e = enqueue_step(h);
-    if (!e) e = enqueue_exact_objective(h);
-    if (!e) e = launch_finish(h->bufs(), k, d_idx, d_obj, d_nsel, h->cap_stream);
-    hipError_t e2 = hipStreamEndCapture(h->cap_stream, &g);
-    h->stream = user;
-    h->profiling = prof;
-    if (e || e2) {
-      if (g) (void)hipGraphDestroy(g);
-      return fail(GCSS_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e ? e : e2));
-    }
-    e = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (e) {
-      h->graph = nullptr;
-      return fail(GCSS_ERR_DEVICE, "graph instantiate: %s", hipGetErrorString(e));
-    }
+    if (h->graph) (void)hipGraphExecDestroy(h->graph);
+    h->graph = nullptr;
+    h->graph_k = -1;
+    hipError_t e = capture_loop(h, k, d_idx, d_obj, d_nsel, true, &h->graph);
+    if (e) return fail(GCSS_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
     h->graph_k = k;
     h->graph_out[0] = d_idx;
     h->graph_out[1] = d_obj;

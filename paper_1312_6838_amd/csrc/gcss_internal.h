@@ -176,6 +176,36 @@ hipError_t launch_gram_err(const double *trace, const double *quad, int k, doubl
                            hipStream_t s);
 hipError_t launch_zero_f32(float *p, int64_t n, hipStream_t s);
 
+// ---- the per-step chain of a single problem (k_chain.hip) ----
+struct ChainArgs {
+  DevState *st;
+  double *Q;          // basis, ld ldq, columns < t read, column t written
+  int64_t ldq;
+  double *V;          // w history (m x (kmax + 1)), ld ldq
+  const double *a;    // the pick's column in FP64
+  double *e1, *e2;    // m each
+  double *P;          // dot partials: row blocks x lp
+  int64_t lp;         // >= r + kmax + 1
+  double *Pn, *Pu;    // one double per row workgroup each
+  const void *B;      // explicit target (binary32 or bfloat16), or C = A A^T (binary32)
+  int64_t ldb;
+  int64_t r;          // target width (0 for B = A)
+  int b_bf16;         // explicit target stored as bfloat16
+  int gram;           // B = A through C
+  double *q64;
+  float *q32, *z32;
+  const double *g0;
+  uint8_t *mask;
+  int64_t *idx;
+  double *obj;
+  int64_t m;
+  int kmax;
+};
+int chain_row_blocks(int64_t m);
+int chain_row_groups(int64_t m);
+size_t chain_lds_bytes(int64_t r, int kmax);
+hipError_t launch_chain(const ChainArgs &ca, hipStream_t s);
+
 // ---- launchers (k_mfma.hip) ----
 // f0_i = scale_i^2 * || X^T A_i ||^2 (X: m x R, K-contiguous, ldx), g0_i, mask0_i
 hipError_t launch_init_factor(const float *X, int64_t ldx, int64_t R, const AView &A,
