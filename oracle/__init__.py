@@ -65,7 +65,7 @@ def _configure(lib):
     lib.orc_error.argtypes = [_vp, _i64, _i64, _i64, _vp, _i32, _vp, _i64, _i64, _vp]
     lib.orc_select_distributed.restype = ctypes.c_int
     lib.orc_select_distributed.argtypes = [_vp, _i64, _i64, _i64, _vp, _i64, _i64, _i32,
-                                           _vp, _i32, _i32, _dbl, _vp, _vp, _vp, _vp]
+                                           _vp, _i32, _vp, _i32, _dbl, _vp, _vp, _vp, _vp]
     lib.orc_bf16_decode.restype = ctypes.c_float
     lib.orc_bf16_decode.argtypes = [ctypes.c_uint16]
     lib.orc_bf16_encode.restype = ctypes.c_uint16
@@ -202,8 +202,11 @@ def error(A, m, idx, B=None):
     return float(e[0])
 
 
-def select_distributed(A, m, B, col_off, k_block, k_merge, tau=1e-10):
-    """Algorithm 4 on one machine: per-block Algorithm 3, then the merge."""
+def select_distributed(A, m, B, col_off, k_block, k_merge, tau=1e-10, k_blocks=None):
+    """Algorithm 4 on one machine: per-block Algorithm 3, then the merge.
+
+    k_block: the per-block budget, or with k_blocks (one budget per block,
+    each in [0, k_block]) the row length of idx_block."""
     lib = _load()
     A = _f64(A)
     B = _f64(B)
@@ -211,12 +214,17 @@ def select_distributed(A, m, B, col_off, k_block, k_merge, tau=1e-10):
     r, ldb = B.shape
     col_off = np.ascontiguousarray(np.asarray(col_off, dtype=np.int64))
     nb = col_off.size - 1
+    kbs = None
+    if k_blocks is not None:
+        kbs = np.ascontiguousarray(np.asarray(k_blocks, dtype=np.int32))
+        if kbs.size != nb:
+            raise ValueError("k_blocks needs one budget per block")
     ib = np.full(nb * k_block, -1, dtype=np.int64)
     im = np.full(k_merge, -1, dtype=np.int64)
     om = np.zeros(k_merge + 1)
     nm = _i32(0)
     st = lib.orc_select_distributed(_p(A), m, n, lda, _p(B), r, ldb, nb, _p(col_off),
-                                    k_block, k_merge, tau, _p(ib), _p(im), _p(om),
+                                    k_block, _p(kbs), k_merge, tau, _p(ib), _p(im), _p(om),
                                     ctypes.addressof(nm))
     if st < 0:
         raise RuntimeError(f"orc_select_distributed status {st}")

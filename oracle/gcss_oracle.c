@@ -441,32 +441,39 @@ int orc_error(const double *A, int64_t m, int64_t n, int64_t lda, const int64_t 
 }
 
 /*
- * Algorithm 4 on one machine: Algorithm 3 with (A_(b), B, k_block) on every
+ * Algorithm 4 on one machine: Algorithm 3 with (A_(b), B, l_(b)) on every
  * block b of consecutive columns col_off[b] .. col_off[b+1]-1, then the
  * picked columns are pooled (block order, then pick order within a block)
  * and Algorithm 3 selects k_merge of them against the same B.
  *
+ * Budgets: l_(b) = k_blocks[b] (0 <= l_(b) <= k_block; a block with budget 0
+ * contributes nothing), or k_block for every block when k_blocks is NULL.
  * Outputs: idx_block[b*k_block + j] global index of block b's j-th pick
  * (-1 if none); idx_merge[k_merge] global indices; obj_merge[k_merge+1].
  */
 int orc_select_distributed(const double *A, int64_t m, int64_t n, int64_t lda,
                            const double *B, int64_t r, int64_t ldb, int32_t nblocks,
-                           const int64_t *col_off, int32_t k_block, int32_t k_merge,
-                           double tau, int64_t *idx_block, int64_t *idx_merge,
-                           double *obj_merge, int32_t *n_merge) {
+                           const int64_t *col_off, int32_t k_block, const int32_t *k_blocks,
+                           int32_t k_merge, double tau, int64_t *idx_block,
+                           int64_t *idx_merge, double *obj_merge, int32_t *n_merge) {
   if (!A || !B || nblocks < 1 || !col_off || k_block < 1 || k_merge < 1) return ORC_ERR_ARG;
   if (col_off[0] != 0 || col_off[nblocks] != n) return ORC_ERR_ARG;
-  for (int32_t b = 0; b < nblocks; ++b)
+  for (int32_t b = 0; b < nblocks; ++b) {
     if (col_off[b + 1] <= col_off[b]) return ORC_ERR_ARG;
+    if (k_blocks && (k_blocks[b] < 0 || k_blocks[b] > k_block)) return ORC_ERR_ARG;
+  }
   int64_t npool = 0;
   for (int32_t b = 0; b < nblocks; ++b) {
     int64_t w = col_off[b + 1] - col_off[b];
     int64_t *loc = idx_block + (size_t)b * k_block;
+    const int32_t lb = k_blocks ? k_blocks[b] : k_block;
+    for (int32_t j = 0; j < k_block; ++j) loc[j] = -1;
+    if (lb == 0) continue;
     int32_t ns = 0;
-    int st = orc_select(A + col_off[b] * lda, m, w, lda, B, r, ldb, k_block, tau, loc, NULL,
+    int st = orc_select(A + col_off[b] * lda, m, w, lda, B, r, ldb, lb, tau, loc, NULL,
                         NULL, NULL, NULL, NULL, NULL, NULL, &ns);
     if (st < 0) return st;
-    for (int32_t j = 0; j < k_block; ++j)
+    for (int32_t j = 0; j < lb; ++j)
       if (loc[j] >= 0) {
         loc[j] += col_off[b];
         ++npool;

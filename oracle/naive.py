@@ -3,37 +3,25 @@
 Each block of columns selects against itself (Algorithm 1 on A_(b), the C
 oracle's select with B = A_(b)); the picks are pooled; an optional second
 selection runs Algorithm 1 on the pooled columns A_{:L}.  Budgets: uniform
-l/c (remainder to the first blocks) or adaptive l ||A_(b)||^2 / ||A||^2
-rounded by largest remainders, capped by the block widths.
+l/c or adaptive l ||A_(b)||^2 / ||A||^2, both rounded by largest remainders
+within the block widths.
 A is a dense m x n array.
 """
 from __future__ import annotations
 
-import math
-
 import numpy as np
 
 import oracle
+from oracle import budgets as budget_rules
 
 
 def budgets(A, col_off, l, policy):
+    """Budgets of the naive approach: "uniform" is l / c and "adaptive" is
+    l ||A_(b)||^2 / ||A||^2, both rounded by largest remainders within the
+    block widths (oracle/budgets.py)."""
     widths = [col_off[b + 1] - col_off[b] for b in range(len(col_off) - 1)]
-    c = len(widths)
-    l = min(l, sum(widths))
-    if policy == "uniform":
-        share = [l / c] * c
-    else:
-        nb = [float(np.sum(A[:, col_off[b]:col_off[b + 1]] ** 2)) for b in range(c)]
-        tot = sum(nb)
-        share = [l * x / tot for x in nb]
-    out = [min(int(math.floor(x)), w) for x, w in zip(share, widths)]
-    while sum(out) < l:
-        best, bi = -1.0, -1
-        for b in range(c):
-            if out[b] < widths[b] and share[b] - out[b] > best:
-                best, bi = share[b] - out[b], b
-        out[bi] += 1
-    return out
+    norms = [float(np.sum(A[:, col_off[b]:col_off[b + 1]] ** 2)) for b in range(len(widths))]
+    return budget_rules.budgets(norms, widths, l, {"uniform": "even", "adaptive": "norm"}[policy])
 
 
 def naive_select(A, col_off, l, k_merge=0, policy="uniform"):
