@@ -42,7 +42,7 @@ gcss_status fail(gcss_status s, const char *fmt, ...) {
 constexpr int kPlanCU = 256;       // CU count used to size the workspace (MI355X)
 constexpr int kSpareSlots = GCSS_ASYNC_SPARE_STEPS;  // extra steps of a captured loop (rejected picks)
 constexpr double kBasisTau = 1e-13;  // dependence threshold of the basis-only mode
-constexpr size_t kChainLdsMax = 60 * 1024;  // LDS the chain's row kernels may take
+constexpr size_t kChainLdsMax = 44 * 1024;  // dynamic LDS the chain's row kernels may take
 
 inline size_t up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 inline int64_t ld_for(int64_t m) { return (int64_t)up((size_t)m, 64); }
@@ -131,9 +131,10 @@ bool make_layout(const gcss_desc *d, int num_cu, Layout *L) {
   // takes), leading dimension ldq
   L->bexp = r > 0 ? c.take<float>((size_t)L->ldq * r) : 0;
   // the per-step chain: w history V (as Q), dot partials per row block of
-  // 1024 rows, and one norm and one u2 partial per 32-row workgroup
-  L->chain = chain_lds_bytes(r, (int)k) <= kChainLdsMax;
-  L->lp = (int64_t)up((size_t)(r + k + 1), 4);
+  // 1024 rows (B = A: also C e2, m entries), and one norm and one q . w
+  // partial per 32-row workgroup
+  L->chain = chain_fits(m, r, (int)k, kChainLdsMax);
+  L->lp = (int64_t)up((size_t)(std::max<int64_t>(r, d->self_target ? m : 0) + k + 1), 4);
   L->V = c.take<double>((size_t)L->ldq * (k + 1));
   L->P = c.take<double>((size_t)chain_row_blocks(m) * L->lp);
   L->Pn = c.take<double>(chain_row_groups(m));
@@ -527,10 +528,12 @@ gcss_status init_ctx(gcss_ctx *h, const gcss_desc *d, void *workspace, size_t ws
   if (!(h->d.tau > 0.0)) h->d.tau = 1e-4;
   h->L = L;
   h->tune = tune;
-  // GCSS_CHAIN=1 in the environment selects the per-step chain kernels
+  // per-step work: the six-kernel chain where it fits, else the general
+  // column-dot / row-update kernels (GCSS_CHAIN=0 in the environment keeps
+  // the general kernels, for comparisons)
   {
     const char *v = getenv("GCSS_CHAIN");
-    h->use_chain = L.chain && v && atoi(v) == 1;
+    h->use_chain = L.chain && !(v && atoi(v) == 0);
   }
   h->ws = (char *)workspace;
   h->ws_bytes = ws_bytes;

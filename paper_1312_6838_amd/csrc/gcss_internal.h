@@ -185,7 +185,7 @@ struct ChainArgs {
   const double *a;    // the pick's column in FP64
   double *e1, *e2;    // m each
   double *P;          // dot partials: row blocks x lp
-  int64_t lp;         // >= r + kmax + 1
+  int64_t lp;         // >= r + kmax + 1 (B = A: m + kmax + 1)
   double *Pn, *Pu;    // one double per row workgroup each
   const void *B;      // explicit target (binary32 or bfloat16), or C = A A^T (binary32)
   int64_t ldb;
@@ -204,6 +204,8 @@ struct ChainArgs {
 int chain_row_blocks(int64_t m);
 int chain_row_groups(int64_t m);
 size_t chain_lds_bytes(int64_t r, int kmax);
+// the chain serves the shape: m within its row blocks, r + kmax + 1 doubles of LDS
+bool chain_fits(int64_t m, int64_t r, int kmax, size_t lds_max);
 hipError_t launch_chain(const ChainArgs &ca, hipStream_t s);
 
 // ---- launchers (k_mfma.hip) ----

@@ -45,16 +45,11 @@ def _run(gpu, A, m, k, *, general, B=None, scales=None, self_target=False, r_max
 
 
 def _planted(m, n, k, seed):
-    """k planted columns c_j u_j (c_j = 1.5^-j, orthonormal u_j) at random
-    positions over a small background: the greedy picks are the planted
-    columns in order, with score gaps far above rounding."""
-    rng = np.random.default_rng(seed)
-    A = 1e-4 * rng.standard_normal((m, n))
-    U, _ = np.linalg.qr(rng.standard_normal((m, k)))
-    pos = rng.choice(n, size=k, replace=False)
-    for j in range(k):
-        A[:, pos[j]] = 1.5 ** (-j) * U[:, j]
-    return A, pos
+    """k planted columns c_j u_j (c_j = 1.05^-j, orthonormal u_j) at random
+    positions over a background of 1e-4 N(0,1)/sqrt(m): the greedy picks are
+    the planted columns in order, consecutive scores 10% apart and every
+    planted score far above the background's."""
+    return synth.planted_dense(m, n, k, 1.05, seed=seed)
 
 
 def _check_pair(a, b, k):
