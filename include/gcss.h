@@ -302,7 +302,10 @@ gcss_status gcss_rank_k(gcss_ctx *h, const float *w, int64_t ldw, int32_t l, int
  * selects k_block columns against the shared explicit target B (all blocks
  * advance together, one batched launch per phase of a step); the picks are
  * pooled in block order, then pick order, and k_merge columns are selected
- * from the pool against B.
+ * from the pool against B.  Both phases run on the device as one captured
+ * graph (replayed while the block layout and budgets stay the same); the
+ * host only reads the results back, plus extra steps for a block or merge
+ * whose basis check rejected more picks than the graph's spare steps.
  * idx_block: host, nblocks*k_block global indices (-1 for picks not made).
  * idx_merge: host, k_merge global indices.  obj_merge: host, k_merge+1 (may
  * be NULL).  n_merge: host (may be NULL).
@@ -315,10 +318,59 @@ gcss_status gcss_select_batched(gcss_ctx *h, int32_t nblocks, const int64_t *col
                                 int32_t k_block, int32_t k_merge, int64_t *idx_block,
                                 int64_t *idx_merge, double *obj_merge, int32_t *n_merge);
 
+/* Rules for the per-block budgets l_(b) of Algorithm 4 (Section 5.2, the
+ * paragraph after Algorithm 4, and the naive distributed selection). */
+typedef enum {
+  GCSS_BUDGET_UNIFORM = 0, /* floor(l / c) for each of the c blocks (the paper's)  */
+  GCSS_BUDGET_EVEN = 1,    /* l / c, rounded by largest remainders                 */
+  GCSS_BUDGET_NORM = 2     /* l ||A_(b)||_F^2 / ||A||_F^2, by largest remainders    */
+} gcss_budget_policy;
+
+/*
+ * Per-block budgets for Algorithm 4 (Section 5.2, after Algorithm 4).
+ * col_off: host, nblocks+1 entries as for gcss_select_batched.  l: the
+ * total number of picks wanted (l >= 0).  Every budget is at most its
+ * block's width.  UNIFORM: floor(l / c), the remainder unused.  EVEN and
+ * NORM: the shares (l / c, or l ||A_(b)||^2 / ||A||^2, l / c for a zero A)
+ * are rounded down and capped at the widths, then the columns missing to
+ * min(l, n) go one at a time to the block with the largest share minus
+ * budget among those with room, the lower block first on equal
+ * remainders.  norms2: host, nblocks squared Frobenius norms of the blocks,
+ * or NULL to take them from the context (the FP64 column norms of the
+ * stored A, summed per block in a fixed order; needs a target, and h may
+ * then not be NULL; synchronizes the context's stream).  h may be NULL when
+ * norms2 is given or the policy is not NORM.  k_blocks: host, nblocks
+ * outputs.  Errors: GCSS_ERR_ARG (policy, col_off, a negative or non-finite
+ * norm), GCSS_ERR_STATE (norms from a context without a target),
+ * GCSS_ERR_UNSUPPORTED (more blocks than the context's scratch holds),
+ * GCSS_ERR_DEVICE.
+ */
+gcss_status gcss_block_budgets(gcss_ctx *h, int32_t nblocks, const int64_t *col_off,
+                               const double *norms2, int32_t l, int32_t policy,
+                               int32_t *k_blocks);
+
+/*
+ * Algorithm 4 with a budget per block: as gcss_select_batched, with block b
+ * selecting k_blocks[b] columns (host, nblocks entries, 0 <= k_blocks[b] <=
+ * the block's width, at least one positive).  The pool holds
+ * nblocks * kmax slots, kmax the largest budget; idx_block is laid out the
+ * same way (host, nblocks * kmax, block b's picks at b * kmax, -1 past its
+ * last).  The pool is pooled in block order, then pick order, as in
+ * gcss_select_batched; empty slots are zero columns, never picked.
+ * Requires k_merge <= nblocks * kmax and a workspace sized by
+ * gcss_batched_workspace_size with k_block = kmax.  Errors as for
+ * gcss_select_batched.  Synchronizes the stream.
+ */
+gcss_status gcss_select_batched_budgets(gcss_ctx *h, int32_t nblocks, const int64_t *col_off,
+                                        const int32_t *k_blocks, int32_t k_merge,
+                                        int64_t *idx_block, int64_t *idx_merge, double *obj_merge,
+                                        int32_t *n_merge);
+
 /*
  * Bytes of workspace gcss_select_batched needs beyond gcss_workspace_size,
- * for the given block layout and budgets; pass the total to gcss_create
- * (the batched state is carved from the end of the same workspace).
+ * for the given block layout and budgets (k_block: the largest budget);
+ * pass the total to gcss_create (the batched state is carved from the end
+ * of the same workspace).
  */
 gcss_status gcss_batched_workspace_size(const gcss_desc *d, int32_t nblocks, int32_t k_block,
                                         int32_t k_merge, size_t *bytes);

@@ -20,7 +20,8 @@ from ._abi import (  # noqa: F401
     select, select_async, select_batched, set_target, version, workspace_size,
     set_profiling, get_profile, set_embedding, qless_r, rank_k, project_sign, top_eig,
     gather_columns, get_tuning, set_tuning, autotune_select, autotune_batched, hbm_probe,
-    PROBE_SINK_FLOATS,
+    PROBE_SINK_FLOATS, BUDGET_UNIFORM, BUDGET_EVEN, BUDGET_NORM, block_budgets,
+    select_batched_budgets,
 )
 
 __all__ = ["Selector", "quantize_tensor", "qless_r_tensor", "hbm_probe_tensor",
@@ -213,6 +214,12 @@ class Selector:
 
     def select_batched(self, col_off, k_block, k_merge):
         return select_batched(self.h, col_off, int(k_block), int(k_merge))
+
+    def select_batched_budgets(self, col_off, k_blocks, k_merge):
+        return select_batched_budgets(self.h, col_off, k_blocks, int(k_merge))
+
+    def block_budgets(self, col_off, l, policy, norms2=None):
+        return block_budgets(self.h, col_off, int(l), policy, norms2)
 
     def read(self, item, count, np_dtype):
         import numpy as np

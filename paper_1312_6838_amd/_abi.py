@@ -35,8 +35,12 @@ EXPORTS = [
     "gcss_last_error", "gcss_version", "gcss_set_profiling", "gcss_get_profile",
     "gcss_set_embedding", "gcss_qless_r", "gcss_rank_k", "gcss_project_sign", "gcss_top_eig",
     "gcss_gather_columns", "gcss_get_tuning", "gcss_set_tuning", "gcss_autotune_select",
-    "gcss_autotune_batched", "gcss_hbm_probe", "gcss_select_static",
+    "gcss_autotune_batched", "gcss_hbm_probe", "gcss_select_static", "gcss_block_budgets",
+    "gcss_select_batched_budgets",
 ]
+
+BUDGET_UNIFORM, BUDGET_EVEN, BUDGET_NORM = 0, 1, 2
+_BUDGET = {"uniform": BUDGET_UNIFORM, "even": BUDGET_EVEN, "norm": BUDGET_NORM}
 
 STATIC_SCRATCH_BYTES = 64 << 20
 
@@ -105,6 +109,10 @@ def load():
     lib.gcss_reconstruction_error.restype = st
     lib.gcss_select_batched.argtypes = [_vp, _i32, _vp, _i32, _i32, _vp, _vp, _vp, _vp]
     lib.gcss_select_batched.restype = st
+    lib.gcss_select_batched_budgets.argtypes = [_vp, _i32, _vp, _vp, _i32, _vp, _vp, _vp, _vp]
+    lib.gcss_select_batched_budgets.restype = st
+    lib.gcss_block_budgets.argtypes = [_vp, _i32, _vp, _vp, _i32, _i32, _vp]
+    lib.gcss_block_budgets.restype = st
     lib.gcss_batched_workspace_size.argtypes = [_P(Desc), _i32, _i32, _i32, _P(_sz)]
     lib.gcss_batched_workspace_size.restype = st
     lib.gcss_quantize.argtypes = [_vp, _i64, _i64, _i64, _i32, _vp, _i64, _vp, _vp]
@@ -242,6 +250,41 @@ def select_batched(h: int, col_off, k_block: int, k_merge: int):
                                           ib.ctypes.data, im.ctypes.data, om.ctypes.data,
                                           ctypes.byref(nm)), allow=(OK, WARN_EXHAUSTED))
     return ib.reshape(nb, k_block), im, om, nm.value, s
+
+
+def select_batched_budgets(h: int, col_off, k_blocks, k_merge: int):
+    """Algorithm 4 with budget k_blocks[b] for block b.  Returns
+    (idx_block (nblocks, max budget), idx_merge, obj_merge, n_merge, status)."""
+    col_off = np.ascontiguousarray(np.asarray(col_off, dtype=np.int64))
+    kb = np.ascontiguousarray(np.asarray(k_blocks, dtype=np.int32))
+    nb = col_off.size - 1
+    if kb.size != nb:
+        raise ValueError("one budget per block")
+    kmax = int(kb.max()) if kb.size else 0
+    ib = np.full(nb * max(kmax, 1), -1, dtype=np.int64)
+    im = np.full(max(k_merge, 1), -1, dtype=np.int64)
+    om = np.zeros(max(k_merge, 1) + 1, dtype=np.float64)
+    nm = _i32(0)
+    s = _check(load().gcss_select_batched_budgets(h, nb, col_off.ctypes.data, kb.ctypes.data,
+                                                  k_merge, ib.ctypes.data, im.ctypes.data,
+                                                  om.ctypes.data, ctypes.byref(nm)),
+               allow=(OK, WARN_EXHAUSTED))
+    return ib.reshape(nb, max(kmax, 1)), im[:k_merge], om[:k_merge + 1], nm.value, s
+
+
+def block_budgets(h, col_off, l: int, policy: str, norms2=None):
+    """Per-block budgets of Algorithm 4 (policy 'uniform', 'even' or 'norm');
+    norms2 None takes the block norms from context h.  Returns int32 array."""
+    col_off = np.ascontiguousarray(np.asarray(col_off, dtype=np.int64))
+    nb = col_off.size - 1
+    out = np.zeros(max(nb, 1), dtype=np.int32)
+    nrm = None
+    if norms2 is not None:
+        nrm = np.ascontiguousarray(np.asarray(norms2, dtype=np.float64))
+    _check(load().gcss_block_budgets(h, nb, col_off.ctypes.data,
+                                     nrm.ctypes.data if nrm is not None else None, int(l),
+                                     _BUDGET[policy], out.ctypes.data))
+    return out[:nb]
 
 
 def quantize(a_ptr: int, m: int, n: int, lda: int, dtype: int, out_ptr: int, ldo: int,

@@ -192,8 +192,12 @@ struct gcss_ctx {
   std::vector<GroupEnt> bgroups;
   std::vector<int64_t> bgfirst;
   std::vector<int64_t> bcol_off;
-  int bk = -1;
+  std::vector<int32_t> bkb;  // per-block budgets of the captured graph
+  int bkm = -1;              // its k_merge
   hipGraphExec_t bgraph = nullptr;
+  // the merge selection's context (over the pooled columns, in the batched
+  // region of the workspace), kept with the captured graph
+  gcss_ctx *msub = nullptr;
   const float *B = nullptr;  // the target as binary32 (the caller's, or the copy of a BF16 one)
   int64_t r = 0, ldb = 0;
   const void *Braw = nullptr;  // the caller's target as given
@@ -423,6 +427,17 @@ hipError_t enqueue_begin(gcss_ctx *h, int k) {
                        nullptr, nullptr, 0, h->stream);
 }
 
+// Begin + k + kSpareSlots steps + the exact objective (and, with finish, the
+// copy to the outputs) on the context's stream.
+hipError_t enqueue_loop(gcss_ctx *h, int k, int64_t *d_idx, double *d_obj, int32_t *d_nsel,
+                        bool finish) {
+  hipError_t e = enqueue_begin(h, k);
+  for (int i = 0; !e && i < k + kSpareSlots; ++i) e = enqueue_step(h);
+  if (!e) e = enqueue_exact_objective(h);
+  if (!e && finish) e = launch_finish(h->bufs(), k, d_idx, d_obj, d_nsel, h->stream);
+  return e;
+}
+
 // Capture begin + k + kSpareSlots steps + the exact objective (and, with
 // outputs given, the copy to them) on the capture stream and instantiate it.
 hipError_t capture_loop(gcss_ctx *h, int k, int64_t *d_idx, double *d_obj, int32_t *d_nsel,
@@ -437,10 +452,7 @@ hipError_t capture_loop(gcss_ctx *h, int k, int64_t *d_idx, double *d_obj, int32
   h->stream = h->cap_stream;
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeRelaxed);
-  if (!e) e = enqueue_begin(h, k);
-  for (int i = 0; !e && i < k + kSpareSlots; ++i) e = enqueue_step(h);
-  if (!e) e = enqueue_exact_objective(h);
-  if (!e && finish) e = launch_finish(h->bufs(), k, d_idx, d_obj, d_nsel, h->cap_stream);
+  if (!e) e = enqueue_loop(h, k, d_idx, d_obj, d_nsel, finish);
   hipError_t e2 = hipStreamEndCapture(h->cap_stream, &g);
   h->stream = user;
   h->profiling = prof;
@@ -574,6 +586,7 @@ void gcss_destroy(gcss_ctx *h) {
   if (!h) return;
   drop_graph(h);
   if (h->bgraph) (void)hipGraphExecDestroy(h->bgraph);
+  if (h->msub) gcss_destroy(h->msub);
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   delete h;
@@ -1012,7 +1025,7 @@ namespace {
 // Per-block buffers of the batched selection, carved after the context's own.
 struct BLayout {
   size_t st, Q, ap64, e1, e2, w, q64, q32, z32, c1, c2, c3, ups, idx, obj, npart, groups, gfirst,
-      gpart, bcnt, pick, a0, sc0, sub, total;
+      gpart, bcnt, kb, pick, a0, sc0, mloc, mobj, mns, mglob, sub, total;
   int64_t sQ, sQ32, sIO, sC, sUps, ngroups_max;
 };
 
@@ -1055,10 +1068,17 @@ bool make_blayout(const gcss_desc *d, const Layout &L, int nblocks, int kb, int 
   B->gfirst = c.take<int64_t>(nblocks + 1);
   B->gpart = c.take<ArgPart>(B->ngroups_max);
   B->bcnt = c.take<uint32_t>(64);
+  B->kb = c.take<int32_t>(nblocks);
+  // the pool: nblocks * kb slots (block-major), gathered into a0
   const int64_t P = (int64_t)nblocks * kb;
   B->pick = c.take<int64_t>(P);
   B->a0 = c.take<uint8_t>((size_t)P * d->lda * dtype_bytes(d->a_dtype));
   B->sc0 = c.take<float>(P);
+  // the merge's outputs: local picks, objective, count, global picks
+  B->mloc = c.take<int64_t>(km + 8);
+  B->mobj = c.take<double>(km + 8);
+  B->mns = c.take<int32_t>(64);
+  B->mglob = c.take<int64_t>(km + 8);
   if (km > P) return false;
   gcss_desc sd = sub_desc(d, P, km);
   Layout SL;
@@ -1113,6 +1133,148 @@ hipError_t enqueue_batched_step(gcss_ctx *h, const BLayout &B, char *base, int n
 
 }  // namespace
 
+namespace {
+
+// Tail of Algorithm 4 after the block phase, on the context's stream: the
+// pool slots, the pooled columns gathered, the merge context's target and
+// initial scores, its selection loop (outputs into the batched region) and
+// the global indices of its picks.  No host involvement: it is captured with
+// the block phase.
+hipError_t enqueue_merge(gcss_ctx *h, const BLayout &B, char *base, int nb, int kbm, int km) {
+  hipStream_t s = h->stream;
+  gcss_ctx *sub = h->msub;
+  const int64_t P = (int64_t)nb * kbm;
+  hipError_t e = launch_pool((const DevState *)(base + B.st), (const int64_t *)(base + B.idx), B.sIO,
+                             kbm, nb, (int64_t *)(base + B.pick), s);
+  if (!e) e = launch_gather_cols(h->A, (const int64_t *)(base + B.pick), P, base + B.a0,
+                                 (float *)(base + B.sc0), s);
+  if (e) return e;
+  hipStream_t own = sub->stream;
+  sub->stream = s;
+  if (gcss_set_target(sub, h->B, GCSS_F32, h->r, h->ldb) != GCSS_OK) e = hipErrorInvalidValue;
+  if (!e) e = enqueue_loop(sub, km, (int64_t *)(base + B.mloc), (double *)(base + B.mobj),
+                           (int32_t *)(base + B.mns), true);
+  sub->stream = own;
+  if (!e) e = launch_merge_map((const int64_t *)(base + B.mloc), (const int64_t *)(base + B.pick), P,
+                               km, (int64_t *)(base + B.mglob), s);
+  return e;
+}
+
+// Block phase of Algorithm 4 on the context's stream: scores and states
+// reset, the score-only pass, then kbm + kSpareSlots lockstep steps (timed:
+// event pairs around the first kbm batched passes, when profiling is on).
+hipError_t enqueue_blocks(gcss_ctx *h, const BLayout &B, char *base, int nb, int kbm, int grid,
+                          bool timed) {
+  hipStream_t s = h->stream;
+  hipError_t e = launch_zero_f32((float *)(base + B.q32), (int64_t)nb * B.sQ32, s);
+  // the stream kernel reads q and z up to the padded length: the padding
+  // (never written by the step kernels) must hold zeros, whatever the
+  // workspace held before
+  if (!e) e = launch_zero_f32((float *)(base + B.z32), (int64_t)nb * B.sQ32, s);
+  if (!e) e = launch_batch_begin(h->at<double>(h->L.f0), h->at<double>(h->L.g0), h->at<uint8_t>(h->L.mask0),
+                                 h->at<double>(h->L.f), h->at<double>(h->L.g), h->at<uint8_t>(h->L.mask), h->d.n,
+                                 (DevState *)(base + B.st), nb, (const int32_t *)(base + B.kb), kbm,
+                                 (int64_t *)(base + B.idx), (double *)(base + B.obj), B.sIO, h->F0(), h->d.tau,
+                                 (uint32_t *)(base + B.bcnt), s);
+  if (!e) e = launch_stream_batched(h->L.geo, grid, h->A, (const GroupEnt *)(base + B.groups), (int64_t)h->bgroups.size(),
+                                    (const float *)(base + B.q32), (const float *)(base + B.z32), B.sQ32,
+                                    h->at<double>(h->L.f), h->at<double>(h->L.g), h->at<double>(h->L.g0),
+                                    h->at<uint8_t>(h->L.mask), (ArgPart *)(base + B.gpart), (const DevState *)(base + B.st),
+                                    (uint32_t *)(base + B.bcnt), 1, s);
+  if (!e) e = launch_block_argmax(h->A, (const ArgPart *)(base + B.gpart), (const int64_t *)(base + B.gfirst), nb,
+                                  (DevState *)(base + B.st), (double *)(base + B.ap64), h->L.ldq, s);
+  // (the spare steps, which return at once when every block is done, are
+  // not timed)
+  for (int i = 0; !e && i < kbm + kSpareSlots; ++i)
+    e = enqueue_batched_step(h, B, base, nb, kbm, grid, timed && i < kbm);
+  return e;
+}
+
+// Budget rounding by largest remainders (the Algorithm 4 budgets other than
+// floor(l / c)): floors of the shares capped at the widths, then the columns
+// missing to min(l, n) one at a time to the block with the largest
+// remainder among those with room, the lower block first on ties.  Every
+// remainder of a block with room lies in [0, 1) after the floors, so this is
+// a round robin over the blocks in that order, skipping full ones.
+void round_budgets(const std::vector<double> &share, const std::vector<int64_t> &width, int64_t l,
+                   int32_t *out) {
+  const int c = (int)share.size();
+  int64_t total = 0, cols = 0;
+  for (int b = 0; b < c; ++b) {
+    const int64_t f = std::min<int64_t>((int64_t)std::floor(share[b]), width[b]);
+    out[b] = (int32_t)f;
+    total += f;
+    cols += width[b];
+  }
+  int64_t missing = std::min<int64_t>(l, cols) - total;
+  std::vector<int> order(c);
+  for (int b = 0; b < c; ++b) order[b] = b;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    return (share[x] - out[x]) > (share[y] - out[y]);
+  });
+  while (missing > 0) {
+    for (int x = 0; x < c && missing > 0; ++x) {
+      const int b = order[x];
+      if (out[b] < width[b]) {
+        ++out[b];
+        --missing;
+      }
+    }
+  }
+}
+
+}  // namespace
+
+gcss_status gcss_block_budgets(gcss_ctx *h, int32_t nblocks, const int64_t *col_off,
+                               const double *norms2, int32_t l, int32_t policy,
+                               int32_t *k_blocks) {
+  if (!col_off || !k_blocks) return fail(GCSS_ERR_ARG, "null col_off or k_blocks");
+  if (nblocks < 1 || l < 0) return fail(GCSS_ERR_ARG, "need nblocks >= 1 and l >= 0");
+  if (policy != GCSS_BUDGET_UNIFORM && policy != GCSS_BUDGET_EVEN && policy != GCSS_BUDGET_NORM)
+    return fail(GCSS_ERR_ARG, "unknown budget policy %d", policy);
+  if (col_off[0] != 0) return fail(GCSS_ERR_ARG, "col_off must start at 0");
+  std::vector<int64_t> width(nblocks);
+  for (int b = 0; b < nblocks; ++b) {
+    if (col_off[b + 1] <= col_off[b]) return fail(GCSS_ERR_ARG, "col_off must be strictly increasing");
+    width[b] = col_off[b + 1] - col_off[b];
+  }
+  if (h && col_off[nblocks] != h->d.n) return fail(GCSS_ERR_ARG, "col_off must run from 0 to n");
+  if (policy == GCSS_BUDGET_UNIFORM) {
+    for (int b = 0; b < nblocks; ++b) k_blocks[b] = (int32_t)std::min<int64_t>(l / nblocks, width[b]);
+    return GCSS_OK;
+  }
+  std::vector<double> share(nblocks, (double)l / nblocks);
+  if (policy == GCSS_BUDGET_NORM) {
+    std::vector<double> nrm(nblocks);
+    if (norms2) {
+      for (int b = 0; b < nblocks; ++b) nrm[b] = norms2[b];
+    } else {
+      // ||A_(b)||_F^2 from the context's FP64 column norms, summed per block
+      // on the device in a fixed order
+      if (check_ctx(h)) return fail(GCSS_ERR_ARG, "no context and no norms2");
+      if (h->target == 0) return fail(GCSS_ERR_STATE, "column norms need a target (gcss_set_target)");
+      const size_t need = up((size_t)(nblocks + 1) * 8, 256) + (size_t)nblocks * 8;
+      if (need > h->L.scratch_bytes) return fail(GCSS_ERR_UNSUPPORTED, "too many blocks for the scratch");
+      char *scr = h->at<char>(h->L.scratch);
+      int64_t *off_d = (int64_t *)scr;
+      double *out_d = (double *)(scr + up((size_t)(nblocks + 1) * 8, 256));
+      HIPCHK(hipMemcpyAsync(off_d, col_off, (size_t)(nblocks + 1) * 8, hipMemcpyHostToDevice, h->stream));
+      HIPCHK(launch_seg_sum(h->at<double>(h->L.g0), off_d, nblocks, out_d, h->stream));
+      HIPCHK(hipMemcpyAsync(nrm.data(), out_d, (size_t)nblocks * 8, hipMemcpyDeviceToHost, h->stream));
+      HIPCHK(hipStreamSynchronize(h->stream));
+    }
+    double tot = 0.0;
+    for (int b = 0; b < nblocks; ++b) {
+      if (!(nrm[b] >= 0.0) || !std::isfinite(nrm[b])) return fail(GCSS_ERR_ARG, "block norm %d not finite and >= 0", b);
+      tot += nrm[b];
+    }
+    if (tot > 0.0)
+      for (int b = 0; b < nblocks; ++b) share[b] = (double)l * nrm[b] / tot;
+  }
+  round_budgets(share, width, l, k_blocks);
+  return GCSS_OK;
+}
+
 gcss_status gcss_batched_workspace_size(const gcss_desc *d, int32_t nblocks, int32_t k_block,
                                         int32_t k_merge, size_t *bytes) {
   gcss_status st = check_desc(d);
@@ -1131,24 +1293,46 @@ gcss_status gcss_select_batched(gcss_ctx *h, int32_t nblocks, const int64_t *col
                                 int32_t k_block, int32_t k_merge, int64_t *idx_block,
                                 int64_t *idx_merge, double *obj_merge, int32_t *n_merge) {
   if (check_ctx(h)) return GCSS_ERR_ARG;
-  if (!col_off || !idx_block || !idx_merge) return fail(GCSS_ERR_ARG, "null argument");
-  if (nblocks < 1 || k_block < 1 || k_merge < 1) return fail(GCSS_ERR_ARG, "bad batched sizes");
-  if ((int64_t)nblocks * k_block < k_merge) return fail(GCSS_ERR_ARG, "k_merge exceeds the pool (nblocks * k_block)");
+  if (nblocks < 1 || k_block < 1) return fail(GCSS_ERR_ARG, "bad batched sizes");
+  std::vector<int32_t> kb(nblocks, k_block);
+  return gcss_select_batched_budgets(h, nblocks, col_off, kb.data(), k_merge, idx_block, idx_merge,
+                                     obj_merge, n_merge);
+}
+
+gcss_status gcss_select_batched_budgets(gcss_ctx *h, int32_t nblocks, const int64_t *col_off,
+                                        const int32_t *k_blocks, int32_t k_merge,
+                                        int64_t *idx_block, int64_t *idx_merge, double *obj_merge,
+                                        int32_t *n_merge) {
+  if (check_ctx(h)) return GCSS_ERR_ARG;
+  if (!col_off || !k_blocks || !idx_block || !idx_merge) return fail(GCSS_ERR_ARG, "null argument");
+  if (nblocks < 1 || k_merge < 1) return fail(GCSS_ERR_ARG, "bad batched sizes");
+  int kbm = 0;
+  for (int b = 0; b < nblocks; ++b) {
+    if (k_blocks[b] < 0) return fail(GCSS_ERR_ARG, "budget of block %d is negative", b);
+    kbm = std::max(kbm, (int)k_blocks[b]);
+  }
+  if (kbm < 1) return fail(GCSS_ERR_ARG, "every block budget is zero");
+  if ((int64_t)nblocks * kbm < k_merge) return fail(GCSS_ERR_ARG, "k_merge exceeds the pool (nblocks * max budget)");
   if (h->target != 1) return fail(GCSS_ERR_STATE, "batched selection needs an explicit target B");
   if (col_off[0] != 0 || col_off[nblocks] != h->d.n) return fail(GCSS_ERR_ARG, "col_off must run from 0 to n");
-  for (int b = 0; b < nblocks; ++b)
+  for (int b = 0; b < nblocks; ++b) {
     if (col_off[b + 1] <= col_off[b]) return fail(GCSS_ERR_ARG, "col_off must be strictly increasing");
+    if (k_blocks[b] > col_off[b + 1] - col_off[b]) return fail(GCSS_ERR_ARG, "budget of block %d exceeds its width", b);
+  }
   BLayout B;
-  if (!make_blayout(&h->d, h->L, nblocks, k_block, k_merge, &B)) return fail(GCSS_ERR_UNSUPPORTED, "batched layout");
+  if (!make_blayout(&h->d, h->L, nblocks, kbm, k_merge, &B)) return fail(GCSS_ERR_UNSUPPORTED, "batched layout");
   h->q_from_select = false;
   char *base = (char *)up((uintptr_t)(h->ws + h->L.total), 256);
   if ((size_t)(base - h->ws) + B.total > h->ws_bytes)
     return fail(GCSS_ERR_WORKSPACE, "workspace lacks the batched region (gcss_batched_workspace_size)");
   hipStream_t s = h->stream;
+  const int64_t P = (int64_t)nblocks * kbm;
 
-  // group table: groups of up to G consecutive columns, never across blocks
+  // group table (groups of up to G consecutive columns, never across
+  // blocks), budgets and the merge context: set up once per block layout
   std::vector<int64_t> off(col_off, col_off + nblocks + 1);
-  const bool same = h->bgraph && h->bk == k_block && off == h->bcol_off;
+  std::vector<int32_t> kbv(k_blocks, k_blocks + nblocks);
+  const bool same = h->bgraph && h->msub && h->bkb == kbv && h->bkm == k_merge && off == h->bcol_off;
   if (!same) {
     const int G = h->L.geo.g;
     h->bgroups.clear();
@@ -1162,38 +1346,41 @@ gcss_status gcss_select_batched(gcss_ctx *h, int32_t nblocks, const int64_t *col
     if ((int64_t)h->bgroups.size() > B.ngroups_max) return fail(GCSS_ERR_UNSUPPORTED, "too many column groups");
     HIPCHK(hipMemcpyAsync(base + B.groups, h->bgroups.data(), sizeof(GroupEnt) * h->bgroups.size(), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(base + B.gfirst, h->bgfirst.data(), sizeof(int64_t) * h->bgfirst.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(base + B.kb, kbv.data(), sizeof(int32_t) * nblocks, hipMemcpyHostToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
     if (h->bgraph) (void)hipGraphExecDestroy(h->bgraph);
     h->bgraph = nullptr;
+    if (h->msub) gcss_destroy(h->msub);
+    h->msub = nullptr;
     h->bcol_off = off;
-    h->bk = k_block;
+    h->bkb = kbv;
+    h->bkm = k_merge;
+    // the merge context over the pool slots (fixed addresses in the batched region)
+    gcss_desc sd = sub_desc(&h->d, P, k_merge);
+    sd.a = base + B.a0;
+    sd.a_scale = h->d.a_dtype == GCSS_FP8_E4M3 ? (const float *)(base + B.sc0) : nullptr;
+    sd.tau = h->d.tau;
+    sd.stream = (void *)s;
+    size_t sub_bytes = 0;
+    gcss_status st = gcss_workspace_size(&sd, &sub_bytes);
+    if (st != GCSS_OK) return st;
+    st = gcss_create(&sd, base + B.sub, sub_bytes, &h->msub);
+    if (st != GCSS_OK) {
+      h->msub = nullptr;
+      return st;
+    }
   }
   int grid = 1;
   HIPCHK(batched_stream_grid(h->L.geo, h->d.a_dtype, h->num_cu, (int64_t)h->bgroups.size(),
                              h->tune.batch_wg_per_cu, &grid));
 
-  // lockstep loop of all blocks, captured once and replayed; with profiling
-  // on it is enqueued directly, with events around every batched stream pass
+  // Block phase and merge: one captured graph, replayed; with profiling on
+  // they are enqueued directly, with events around every batched pass
   if (h->profiling) {
     h->ev_used = 0;
-    hipError_t e = launch_zero_f32((float *)(base + B.q32), (int64_t)nblocks * B.sQ32, s);
-    if (!e) e = launch_zero_f32((float *)(base + B.z32), (int64_t)nblocks * B.sQ32, s);
-    if (!e) e = launch_batch_begin(h->at<double>(h->L.f0), h->at<double>(h->L.g0), h->at<uint8_t>(h->L.mask0),
-                                   h->at<double>(h->L.f), h->at<double>(h->L.g), h->at<uint8_t>(h->L.mask), h->d.n,
-                                   (DevState *)(base + B.st), nblocks, k_block, (int64_t *)(base + B.idx),
-                                   (double *)(base + B.obj), B.sIO, h->F0(), h->d.tau, (uint32_t *)(base + B.bcnt), s);
-    if (!e) e = launch_stream_batched(h->L.geo, grid, h->A, (const GroupEnt *)(base + B.groups), (int64_t)h->bgroups.size(),
-                                      (const float *)(base + B.q32), (const float *)(base + B.z32), B.sQ32,
-                                      h->at<double>(h->L.f), h->at<double>(h->L.g), h->at<double>(h->L.g0),
-                                      h->at<uint8_t>(h->L.mask), (ArgPart *)(base + B.gpart), (const DevState *)(base + B.st),
-                                      (uint32_t *)(base + B.bcnt), 1, s);
-    if (!e) e = launch_block_argmax(h->A, (const ArgPart *)(base + B.gpart), (const int64_t *)(base + B.gfirst), nblocks,
-                                    (DevState *)(base + B.st), (double *)(base + B.ap64), h->L.ldq, s);
-    // (the spare steps, which return at once when every block is done, are
-    // not timed)
-    for (int i = 0; !e && i < k_block + kSpareSlots; ++i)
-      e = enqueue_batched_step(h, B, base, nblocks, k_block, grid, i < k_block);
-    if (e) return fail(GCSS_ERR_DEVICE, "batched loop: %s", hipGetErrorString(e));
+    hipError_t e = enqueue_blocks(h, B, base, nblocks, kbm, grid, true);
+    if (!e) e = enqueue_merge(h, B, base, nblocks, kbm, k_merge);
+    if (e) return fail(GCSS_ERR_DEVICE, "batched selection: %s", hipGetErrorString(e));
     HIPCHK(hipStreamSynchronize(s));
     float ms = 0.f;
     for (size_t x = 0; x + 1 < h->ev_used; x += 2) {
@@ -1203,56 +1390,55 @@ gcss_status gcss_select_batched(gcss_ctx *h, int32_t nblocks, const int64_t *col
     }
     h->prof.selects += 1;
   } else {
-  if (!h->bgraph) {
-    if (!h->cap_stream) HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
-    hipStream_t user = h->stream;
-    h->stream = h->cap_stream;
-    hipGraph_t g = nullptr;
-    hipError_t e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeRelaxed);
-    // the stream kernel reads q and z up to the padded length: the padding
-    // (never written by the step kernels) must hold zeros, whatever the
-    // workspace held before
-    if (!e) e = launch_zero_f32((float *)(base + B.q32), (int64_t)nblocks * B.sQ32, h->cap_stream);
-    if (!e) e = launch_zero_f32((float *)(base + B.z32), (int64_t)nblocks * B.sQ32, h->cap_stream);
-    if (!e) e = launch_batch_begin(h->at<double>(h->L.f0), h->at<double>(h->L.g0), h->at<uint8_t>(h->L.mask0),
-                                   h->at<double>(h->L.f), h->at<double>(h->L.g), h->at<uint8_t>(h->L.mask), h->d.n,
-                                   (DevState *)(base + B.st), nblocks, k_block, (int64_t *)(base + B.idx),
-                                   (double *)(base + B.obj), B.sIO, h->F0(), h->d.tau, (uint32_t *)(base + B.bcnt),
-                                   h->cap_stream);
-    if (!e) e = launch_stream_batched(h->L.geo, grid, h->A, (const GroupEnt *)(base + B.groups), (int64_t)h->bgroups.size(),
-                                      (const float *)(base + B.q32), (const float *)(base + B.z32), B.sQ32,
-                                      h->at<double>(h->L.f), h->at<double>(h->L.g), h->at<double>(h->L.g0),
-                                      h->at<uint8_t>(h->L.mask), (ArgPart *)(base + B.gpart), (const DevState *)(base + B.st),
-                                      (uint32_t *)(base + B.bcnt), 1, h->cap_stream);
-    if (!e) e = launch_block_argmax(h->A, (const ArgPart *)(base + B.gpart), (const int64_t *)(base + B.gfirst), nblocks,
-                                    (DevState *)(base + B.st), (double *)(base + B.ap64), h->L.ldq, h->cap_stream);
-    for (int i = 0; !e && i < k_block + kSpareSlots; ++i) e = enqueue_batched_step(h, B, base, nblocks, k_block, grid);
-    hipError_t e2 = hipStreamEndCapture(h->cap_stream, &g);
-    h->stream = user;
-    if (e || e2) {
-      if (g) (void)hipGraphDestroy(g);
-      return fail(GCSS_ERR_DEVICE, "batched capture failed: %s", hipGetErrorString(e ? e : e2));
+    if (!h->bgraph) {
+      if (!h->cap_stream) HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+      drop_graph(h->msub);
+      hipStream_t user = h->stream;
+      h->stream = h->cap_stream;
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeRelaxed);
+      if (!e) e = enqueue_blocks(h, B, base, nblocks, kbm, grid, false);
+      if (!e) e = enqueue_merge(h, B, base, nblocks, kbm, k_merge);
+      hipError_t e2 = hipStreamEndCapture(h->cap_stream, &g);
+      h->stream = user;
+      if (e || e2) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(GCSS_ERR_DEVICE, "batched capture failed: %s", hipGetErrorString(e ? e : e2));
+      }
+      e = hipGraphInstantiate(&h->bgraph, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e) {
+        h->bgraph = nullptr;
+        return fail(GCSS_ERR_DEVICE, "batched graph instantiate: %s", hipGetErrorString(e));
+      }
     }
-    e = hipGraphInstantiate(&h->bgraph, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (e) {
-      h->bgraph = nullptr;
-      return fail(GCSS_ERR_DEVICE, "batched graph instantiate: %s", hipGetErrorString(e));
-    }
-  }
-  HIPCHK(hipGraphLaunch(h->bgraph, s));
+    HIPCHK(hipGraphLaunch(h->bgraph, s));
   }
 
-  // per-block picks back to the host
-  std::vector<int64_t> bidx((size_t)nblocks * B.sIO);
+  // results: the pool slots (every block's picks), the block states, the
+  // merge's picks, objective and state
+  std::vector<int64_t> slots(P);
   std::vector<DevState> bst(nblocks);
-  HIPCHK(hipMemcpyAsync(bidx.data(), base + B.idx, sizeof(int64_t) * bidx.size(), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(bst.data(), base + B.st, sizeof(DevState) * nblocks, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  // blocks whose basis check rejected more picks than the captured loop has
+  std::vector<int64_t> mg(k_merge);
+  std::vector<double> mo(k_merge + 1);
+  int32_t mns = 0;
+  DevState mst;
+  auto fetch = [&]() -> hipError_t {
+    hipError_t e = hipMemcpyAsync(slots.data(), base + B.pick, sizeof(int64_t) * P, hipMemcpyDeviceToHost, s);
+    if (!e) e = hipMemcpyAsync(bst.data(), base + B.st, sizeof(DevState) * nblocks, hipMemcpyDeviceToHost, s);
+    if (!e) e = hipMemcpyAsync(mg.data(), base + B.mglob, sizeof(int64_t) * k_merge, hipMemcpyDeviceToHost, s);
+    if (!e) e = hipMemcpyAsync(mo.data(), base + B.mobj, sizeof(double) * (k_merge + 1), hipMemcpyDeviceToHost, s);
+    if (!e) e = hipMemcpyAsync(&mns, base + B.mns, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (!e) e = hipMemcpyAsync(&mst, h->msub->at<DevState>(h->msub->L.st), sizeof mst, hipMemcpyDeviceToHost, s);
+    if (!e) e = hipStreamSynchronize(s);
+    return e;
+  };
+  HIPCHK(fetch());
+  // Blocks whose basis check rejected more picks than the captured loop has
   // spare steps for: more lockstep steps (finished blocks skip them) until
-  // every block has its k_block picks or has run out of candidates; each
-  // step adds a pick or drops a candidate, so this ends
+  // every block has its budget or has run out of candidates (each step adds
+  // a pick or drops a candidate, so this ends), then the merge again.
+  bool redo = false;
   {
     int64_t wmax = 0;
     for (int b = 0; b < nblocks; ++b) wmax = std::max<int64_t>(wmax, off[b + 1] - off[b]);
@@ -1260,61 +1446,50 @@ gcss_status gcss_select_batched(gcss_ctx *h, int32_t nblocks, const int64_t *col
     for (;;) {
       int need = 0;
       for (int b = 0; b < nblocks; ++b)
-        if (!bst[b].done) need = std::max(need, std::max(1, k_block - bst[b].t));
+        if (!bst[b].done) need = std::max(need, std::max(1, k_blocks[b] - bst[b].t));
       if (need == 0) break;
-      if (ran > (int64_t)k_block + wmax)
+      if (ran > (int64_t)kbm + wmax)
         return fail(GCSS_ERR_DEVICE, "batched selection did not finish after %lld extra steps", (long long)ran);
-      for (int i = 0; i < need; ++i) HIPCHK(enqueue_batched_step(h, B, base, nblocks, k_block, grid));
+      for (int i = 0; i < need; ++i) HIPCHK(enqueue_batched_step(h, B, base, nblocks, kbm, grid));
       ran += need;
-      HIPCHK(hipMemcpyAsync(bidx.data(), base + B.idx, sizeof(int64_t) * bidx.size(), hipMemcpyDeviceToHost, s));
       HIPCHK(hipMemcpyAsync(bst.data(), base + B.st, sizeof(DevState) * nblocks, hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
+      redo = true;
     }
   }
-  std::vector<int64_t> pool;
-  for (int b = 0; b < nblocks; ++b)
-    for (int j = 0; j < k_block; ++j) {
-      const int64_t v = j < bst[b].t ? bidx[(size_t)b * B.sIO + j] : -1;
-      idx_block[(size_t)b * k_block + j] = v;
-      if (v >= 0) pool.push_back(v);
+  if (redo) {
+    hipError_t e = enqueue_merge(h, B, base, nblocks, kbm, k_merge);
+    if (e) return fail(GCSS_ERR_DEVICE, "merge: %s", hipGetErrorString(e));
+    HIPCHK(fetch());
+  }
+  // a merge whose basis check rejected more picks than its spare steps: the
+  // missing steps, then its outputs again
+  if (!mst.done) {
+    gcss_ctx *sub = h->msub;
+    int64_t ran = 0;
+    while (!mst.done) {
+      if (ran > (int64_t)k_merge + P)
+        return fail(GCSS_ERR_DEVICE, "merge selection did not finish after %lld extra steps", (long long)ran);
+      const int need = std::max(1, k_merge - mst.t);
+      for (int i = 0; i < need; ++i) HIPCHK(enqueue_step(sub));
+      ran += need;
+      HIPCHK(hipMemcpyAsync(&mst, sub->at<DevState>(sub->L.st), sizeof mst, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
     }
+    HIPCHK(enqueue_exact_objective(sub));
+    HIPCHK(launch_finish(sub->bufs(), k_merge, (int64_t *)(base + B.mloc), (double *)(base + B.mobj),
+                         (int32_t *)(base + B.mns), s));
+    HIPCHK(launch_merge_map((const int64_t *)(base + B.mloc), (const int64_t *)(base + B.pick), P, k_merge,
+                            (int64_t *)(base + B.mglob), s));
+    HIPCHK(fetch());
+  }
+  for (int64_t x = 0; x < P; ++x) idx_block[x] = slots[x];
+  for (int j = 0; j < k_merge; ++j) idx_merge[j] = mg[j];
+  if (obj_merge)
+    for (int j = 0; j <= k_merge; ++j) obj_merge[j] = mo[j];
+  if (n_merge) *n_merge = mns;
   h->basis_valid = false;
-  for (int j = 0; j < k_merge; ++j) idx_merge[j] = -1;
-  if (pool.empty()) {
-    if (n_merge) *n_merge = 0;
-    return GCSS_WARN_EXHAUSTED;
-  }
-
-  // second phase: selection over the pooled columns against the same B
-  const int64_t P = (int64_t)pool.size();
-  HIPCHK(hipMemcpyAsync(base + B.pick, pool.data(), sizeof(int64_t) * P, hipMemcpyHostToDevice, s));
-  HIPCHK(launch_gather_cols(h->A, (const int64_t *)(base + B.pick), P, base + B.a0, (float *)(base + B.sc0), s));
-  const int32_t km = (int32_t)std::min<int64_t>(k_merge, P);
-  gcss_desc sd = sub_desc(&h->d, P, km);
-  sd.a = base + B.a0;
-  sd.a_scale = h->d.a_dtype == GCSS_FP8_E4M3 ? (const float *)(base + B.sc0) : nullptr;
-  sd.tau = h->d.tau;
-  sd.stream = (void *)s;
-  size_t sub_bytes = 0;
-  gcss_status st = gcss_workspace_size(&sd, &sub_bytes);
-  if (st != GCSS_OK) return st;
-  gcss_ctx *sub = nullptr;
-  st = gcss_create(&sd, base + B.sub, sub_bytes, &sub);
-  if (st != GCSS_OK) return st;
-  st = gcss_set_target(sub, h->B, GCSS_F32, h->r, h->ldb);
-  std::vector<int64_t> loc(km, -1);
-  std::vector<double> obj(km + 1, 0.0);
-  int32_t ns = 0;
-  if (st == GCSS_OK) st = gcss_select(sub, km, loc.data(), obj.data(), &ns);
-  gcss_destroy(sub);
-  if (st < 0) return st;
-  for (int j = 0; j < km; ++j) idx_merge[j] = loc[j] >= 0 ? pool[loc[j]] : -1;
-  if (obj_merge) {
-    for (int j = 0; j <= km; ++j) obj_merge[j] = obj[j];
-    for (int j = km + 1; j <= k_merge; ++j) obj_merge[j] = obj[km];
-  }
-  if (n_merge) *n_merge = ns;
-  return (ns < k_merge) ? GCSS_WARN_EXHAUSTED : GCSS_OK;
+  return (mns < k_merge) ? GCSS_WARN_EXHAUSTED : GCSS_OK;
 }
 
 gcss_status gcss_gather_columns(gcss_ctx *h, const int64_t *idx, int64_t count, void *out,

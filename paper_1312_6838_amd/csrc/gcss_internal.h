@@ -317,10 +317,22 @@ hipError_t launch_stream_batched(const StreamGeo &geo, int grid, const AView &A,
 hipError_t launch_block_argmax(const AView &A, const ArgPart *gpart, const int64_t *gfirst,
                                int nprob, DevState *stb, double *ap64, int64_t apstride,
                                hipStream_t s);
+// kb: device, the picks each problem wants (0: done from the start); kbm:
+// entries of idx / obj per problem that are cleared
 hipError_t launch_batch_begin(const double *f0, const double *g0, const uint8_t *mask0,
                               double *f, double *g, uint8_t *mask, int64_t n, DevState *stb,
-                              int nprob, int k, int64_t *idx, double *obj, int64_t iostride,
-                              const double *F0, double tau, uint32_t *bcnt, hipStream_t s);
+                              int nprob, const int32_t *kb, int kbm, int64_t *idx, double *obj,
+                              int64_t iostride, const double *F0, double tau, uint32_t *bcnt,
+                              hipStream_t s);
+// pick[b * kbm + j] = problem b's j-th pick, -1 past its last
+hipError_t launch_pool(const DevState *stb, const int64_t *idx, int64_t iostride, int kbm,
+                       int nprob, int64_t *pick, hipStream_t s);
+// out[j] = pick[loc[j]] for j < km (-1 for a missing pick)
+hipError_t launch_merge_map(const int64_t *loc, const int64_t *pick, int64_t npick, int km,
+                            int64_t *out, hipStream_t s);
+// out[b] = sum of x[off[b] .. off[b+1]) in a fixed order, b < nseg (off on the device)
+hipError_t launch_seg_sum(const double *x, const int64_t *off, int nseg, double *out,
+                          hipStream_t s);
 hipError_t launch_gather_cols(const AView &A, const int64_t *pick, int64_t npick, void *a0,
                               float *scale0, hipStream_t s);
 

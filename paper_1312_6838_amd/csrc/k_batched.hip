@@ -281,12 +281,14 @@ __global__ __launch_bounds__(256) void k_block_argmax(AView A, const ArgPart *__
 }
 
 // Start of a batched selection: scores reset from the initial ones, every
-// block's state cleared, outputs cleared.
+// block's state cleared (block b wants kb[b] picks; a block with none is done
+// from the start), outputs cleared (kbm entries per block).
 __global__ void k_batch_begin(const double *__restrict__ f0, const double *__restrict__ g0,
                               const uint8_t *__restrict__ mask0, double *__restrict__ f,
                               double *__restrict__ g, uint8_t *__restrict__ mask, int64_t n,
-                              DevState *stb, int nprob, int k, int64_t *idx, double *obj,
-                              int64_t iostride, const double *F0, double tau, uint32_t *bcnt) {
+                              DevState *stb, int nprob, const int32_t *__restrict__ kb, int kbm,
+                              int64_t *idx, double *obj, int64_t iostride, const double *F0,
+                              double tau, uint32_t *bcnt) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
     f[i] = f0[i];
@@ -295,9 +297,10 @@ __global__ void k_batch_begin(const double *__restrict__ f0, const double *__res
   }
   if (i < nprob) {
     DevState *st = stb + i;
+    const int k = kb[i];
     st->t = 0;
     st->k = k;
-    st->done = 0;
+    st->done = k < 1;
     st->exhausted = 0;
     st->skip = 0;
     st->n_reject = 0;
@@ -309,13 +312,34 @@ __global__ void k_batch_begin(const double *__restrict__ f0, const double *__res
     st->enorm2 = 0.0;
     st->tau = tau;
     for (int x = 0; x < 16; ++x) st->cnt[x] = 0;
-    for (int x = 0; x < k; ++x) idx[i * iostride + x] = -1;
-    for (int x = 0; x <= k; ++x) obj[i * iostride + x] = *F0;
+    for (int x = 0; x < kbm; ++x) idx[i * iostride + x] = -1;
+    for (int x = 0; x <= kbm; ++x) obj[i * iostride + x] = *F0;
   }
   if (i == 0) {
     bcnt[0] = 0;
     bcnt[1] = 0;
   }
+}
+
+// The pool of Algorithm 4's second phase as fixed slots: slot b * kbm + j
+// holds block b's j-th pick, or -1 past its last one.  Empty slots become
+// zero columns in the gathered matrix, which are never candidates, so the
+// merge sees the picks in block order, then pick order, as if compacted.
+__global__ void k_pool(const DevState *__restrict__ stb, const int64_t *__restrict__ idx,
+                       int64_t iostride, int kbm, int nprob, int64_t *__restrict__ pick) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= (int64_t)nprob * kbm) return;
+  const int b = (int)(x / kbm), j = (int)(x % kbm);
+  pick[x] = j < stb[b].t ? idx[b * iostride + j] : -1;
+}
+
+// Global index of each merge pick: out[j] = pick[loc[j]] (-1 stays -1).
+__global__ void k_merge_map(const int64_t *__restrict__ loc, const int64_t *__restrict__ pick,
+                            int64_t npick, int km, int64_t *__restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= km) return;
+  const int64_t l = loc[j];
+  out[j] = (l >= 0 && l < npick) ? pick[l] : -1;
 }
 
 // Pooled matrix of Algorithm 4's second phase: A0[:, j] = A[:, pick[j]] (and
@@ -420,11 +444,29 @@ hipError_t launch_block_argmax(const AView &A, const ArgPart *gpart, const int64
 
 hipError_t launch_batch_begin(const double *f0, const double *g0, const uint8_t *mask0,
                               double *f, double *g, uint8_t *mask, int64_t n, DevState *stb,
-                              int nprob, int k, int64_t *idx, double *obj, int64_t iostride,
-                              const double *F0, double tau, uint32_t *bcnt, hipStream_t s) {
+                              int nprob, const int32_t *kb, int kbm, int64_t *idx, double *obj,
+                              int64_t iostride, const double *F0, double tau, uint32_t *bcnt,
+                              hipStream_t s) {
   const int64_t total = n > nprob ? n : nprob;
   hipLaunchKernelGGL(k_batch_begin, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, f0, g0,
-                     mask0, f, g, mask, n, stb, nprob, k, idx, obj, iostride, F0, tau, bcnt);
+                     mask0, f, g, mask, n, stb, nprob, kb, kbm, idx, obj, iostride, F0, tau, bcnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_pool(const DevState *stb, const int64_t *idx, int64_t iostride, int kbm,
+                       int nprob, int64_t *pick, hipStream_t s) {
+  const int64_t total = (int64_t)nprob * kbm;
+  if (total < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_pool, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, stb, idx,
+                     iostride, kbm, nprob, pick);
+  return hipGetLastError();
+}
+
+hipError_t launch_merge_map(const int64_t *loc, const int64_t *pick, int64_t npick, int km,
+                            int64_t *out, hipStream_t s) {
+  if (km < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_merge_map, dim3((unsigned)((km + 255) / 256)), dim3(256), 0, s, loc, pick,
+                     npick, km, out);
   return hipGetLastError();
 }
 

@@ -435,6 +435,23 @@ __global__ __launch_bounds__(256) void k_sum_f64(const double *__restrict__ x, i
   if (threadIdx.x == 0) *out = red[0];
 }
 
+// out[b] = fixed-order sum of x[off[b] .. off[b + 1]), one workgroup per segment
+__global__ __launch_bounds__(256) void k_seg_sum(const double *__restrict__ x,
+                                                 const int64_t *__restrict__ off,
+                                                 double *__restrict__ out) {
+  __shared__ double red[256];
+  const int64_t b0 = off[blockIdx.x], b1 = off[blockIdx.x + 1];
+  double s = 0.0;
+  for (int64_t i = b0 + threadIdx.x; i < b1; i += 256) s += x[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
 // part[b] = fixed-order sum of x[b * chunk .. (b + 1) * chunk)
 __global__ __launch_bounds__(256) void k_sum_chunks(const double *__restrict__ x, int64_t n,
                                                     int64_t chunk, double *__restrict__ part) {
@@ -643,6 +660,13 @@ hipError_t launch_sum_f64(const double *x, int64_t n, double *out, double *part,
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(256), 0, s, part, nb, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_seg_sum(const double *x, const int64_t *off, int nseg, double *out,
+                          hipStream_t s) {
+  if (nseg < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_seg_sum, dim3((unsigned)nseg), dim3(256), 0, s, x, off, out);
   return hipGetLastError();
 }
 

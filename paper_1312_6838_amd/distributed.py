@@ -15,24 +15,14 @@ import numpy as np
 
 
 def block_budgets(norms2, widths, l, policy="uniform"):
-    """Integer budgets summing to min(l, sum of widths), each <= its block width."""
-    c = len(widths)
+    """Integer budgets summing to min(l, sum of widths), each <= its block
+    width: the library's largest-remainder rounding of l / c ('uniform') or
+    of the norm shares ('adaptive')."""
+    from . import _abi
     widths = np.asarray(widths, dtype=np.int64)
-    l = int(min(l, int(widths.sum())))
-    if policy == "uniform":
-        share = np.full(c, l / c)
-    elif policy == "adaptive":
-        w = np.asarray(norms2, dtype=np.float64)
-        share = l * w / w.sum() if w.sum() > 0 else np.full(c, l / c)
-    else:
-        raise ValueError(policy)
-    b = np.minimum(np.floor(share).astype(np.int64), widths)
-    # hand out what is left by largest remainder (then block order), within capacity
-    while b.sum() < l:
-        frac = share - b
-        frac[b >= widths] = -np.inf
-        b[int(np.argmax(frac))] += 1
-    return b
+    col_off = np.concatenate([[0], np.cumsum(widths)]).astype(np.int64)
+    pol = {"uniform": "even", "adaptive": "norm"}[policy]
+    return _abi.block_budgets(None, col_off, int(l), pol, norms2).astype(np.int64)
 
 
 def naive_select(A, m, col_off, l, k_merge=0, policy="uniform", scales=None, tau=0.0):
