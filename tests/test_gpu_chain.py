@@ -4,8 +4,8 @@ row-update kernels (k_gemv.hip), and both against the FP64 oracle.
 Both compute the same step of Theorem 4 in the q/z form (Gram-Schmidt with
 one re-orthogonalisation, upsilon = B^T q, w = B upsilon, z = w - Q Q^T w)
 with different summation orders, so on inputs with separated score gaps the
-picks are identical and every objective agrees to FP64 rounding (relative
-1e-12).  GCSS_CHAIN=0 in the environment at context creation selects the
+picks are identical and every objective agrees to FP64 rounding (1e-12 of
+F_0).  GCSS_CHAIN=0 in the environment at context creation selects the
 general kernels.  Shapes cover: the Gram target (B = A), explicit binary32
 and bfloat16 targets, FP8 storage, a ragged m (row blocks and 32-row groups
 with a tail), m = 8192 (eight row blocks, the chain's maximum), more than
@@ -57,8 +57,11 @@ def _check_pair(a, b, k):
     ib, ob, nb, fb = b
     assert na == nb == k
     np.testing.assert_array_equal(ia, ib)
+    # F_t = F_0 minus the captured part: both orders round the captured part
+    # to a few ulps of F_0, so the bound is on |F_t - F_t'| / F_0 (a small
+    # F_t carries F_0's rounding relative to itself)
     for j in range(k + 1):
-        assert rel(oa[j], ob[j]) < 1e-12, (j, oa[j], ob[j])
+        assert abs(oa[j] - ob[j]) <= 1e-12 * oa[0], (j, oa[j], ob[j])
     assert fa["finished"] and fb["finished"]
 
 
@@ -101,7 +104,7 @@ def test_explicit_target_chain_equals_general(gpu, m, n, r, k, bdt):
         _check_pair(a, b, k)
     else:
         for j in range(pre + 1):
-            assert rel(a[1][j], b[1][j]) < 1e-12
+            assert abs(a[1][j] - b[1][j]) <= 1e-12 * a[1][0]
     # the chain's objective is the explicit error of its picks
     e = oracle.error(f64cs(A64), m, a[0][:k], B=f64cs(Bval))
     assert rel(a[1][k], e) < 1e-5
