@@ -43,6 +43,17 @@ _vp = ctypes.c_void_p
 EXHAUSTED = 1
 
 
+def build_sanitized(out_path: str) -> str:
+    """Compile the oracle under AddressSanitizer and UndefinedBehaviorSanitizer
+    with the ROCm toolchain's clang (its shared runtime, which the caller
+    preloads, is the one the library's sanitized host code uses too)."""
+    cmd = ["/opt/rocm/llvm/bin/clang", "-O1", "-g", "-fno-omit-frame-pointer",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-shared-libasan",
+           "-fopenmp", "-fPIC", "-shared", "-std=c11", "-Wall", "-o", out_path, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    return out_path
+
+
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (-O2, OpenMP)."""
     if force or not os.path.exists(_LIB):
@@ -88,6 +99,12 @@ def _configure(lib):
 def _load():
     global _lib
     if _lib is None:
+        # GCSS_ORACLE_LIBRARY: another build of the same source (the
+        # sanitizer test's), loaded as is
+        other = os.environ.get("GCSS_ORACLE_LIBRARY")
+        if other:
+            _lib = _configure(ctypes.CDLL(other))
+            return _lib
         if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build(force=True)
         _lib = _configure(ctypes.CDLL(_LIB))

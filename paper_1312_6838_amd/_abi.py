@@ -10,7 +10,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libgcss.so")
+# GCSS_LIBRARY names another build of the same library (e.g. a host-sanitizer
+# build for the CPU tests)
+LIB_PATH = os.environ.get("GCSS_LIBRARY") or os.path.join(_HERE, "libgcss.so")
 
 OK = 0
 WARN_EXHAUSTED = 1
