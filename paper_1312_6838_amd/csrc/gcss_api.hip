@@ -146,6 +146,7 @@ bool make_layout(const gcss_desc *d, int num_cu, Layout *L) {
   const size_t err_bytes = up((size_t)std::max<int64_t>(r, 1) * 8, 256) +
                            up((size_t)L->ldq * k * 4, 256) + 3 * up((size_t)(k + 8) * 8, 256);
   s = std::max(s, err_bytes);
+  if (r > 0) s = std::max(s, err_scratch_bytes(m, (int)k, r, num_cu));
   if (d->self_target) s = std::max(s, qta_scratch_bytes(n, (int)k));
   if (k <= kRankMaxL) s = std::max(s, rank_plan((int)k, n).bytes);
   if (d->self_target) {
@@ -827,9 +828,8 @@ gcss_status gcss_reconstruction_error(gcss_ctx *h, const int64_t *idx, int32_t k
   const double *Q = h->at<double>(h->L.Q);
   char *scr = h->at<char>(h->L.scratch);
   if (h->target == 1) {
-    double *colerr = (double *)scr;
-    HIPCHK(launch_err_factor(Q, ldq, m, kb, h->B, h->ldb, h->r, colerr, s));
-    HIPCHK(launch_sum_f64(colerr, h->r, h->err_dev(), nullptr, 0, s));
+    HIPCHK(launch_err_tiled(Q, ldq, m, kb, h->B, h->ldb, h->r, scr, h->L.scratch_bytes, h->num_cu,
+                            h->err_dev(), s));
   } else if (kb == 0) {
     HIPCHK(launch_sum_f64(h->F0(), 1, h->err_dev(), nullptr, 0, s));
   } else {

@@ -166,8 +166,12 @@ hipError_t launch_sumsq_f32(const float *B, int64_t m, int64_t r, int64_t ldb, d
                             double *part, hipStream_t s);
 // Residual of an explicit target on basis Q (k columns):
 //   colerr[c] = || B_c - Q (Q^T B_c) ||^2, FP64
-hipError_t launch_err_factor(const double *Q, int64_t ldq, int64_t m, int k, const float *B,
-                             int64_t ldb, int64_t r, double *colerr, hipStream_t s);
+// err = || B - Q (Q^T B) ||_F^2 (Q: m x k FP64 basis, B: m x r binary32),
+// tiled FP64 passes in the scratch (err_scratch_bytes); err on the device
+size_t err_scratch_bytes(int64_t m, int k, int64_t r, int num_cu);
+hipError_t launch_err_tiled(const double *Q, int64_t ldq, int64_t m, int k, const float *B,
+                            int64_t ldb, int64_t r, void *scratch, size_t scratch_bytes,
+                            int num_cu, double *err, hipStream_t s);
 hipError_t launch_q_to_f32(const double *Q, int64_t ldq, int64_t m, int k, float *Q32,
                            int64_t ld32, hipStream_t s);
 hipError_t launch_copy_i64(const int64_t *src, int64_t *dst, int64_t n, hipStream_t s);

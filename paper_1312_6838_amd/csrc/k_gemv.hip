@@ -488,39 +488,6 @@ __global__ __launch_bounds__(256) void k_sumsq_cols(const float *__restrict__ B,
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-// One workgroup per target column c: colerr[c] = || B_c - Q (Q^T B_c) ||^2.
-__global__ __launch_bounds__(256) void k_err_factor(const double *__restrict__ Q, int64_t ldq,
-                                                    int64_t m, int k,
-                                                    const float *__restrict__ B, int64_t ldb,
-                                                    double *__restrict__ colerr) {
-  extern __shared__ double ys[];
-  __shared__ double red[256];
-  const int64_t c = blockIdx.x;
-  const float *b = B + c * ldb;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int s = wave; s < k; s += 4) {
-    const double *q = Q + (int64_t)s * ldq;
-    double acc = 0.0;
-    for (int64_t j = lane; j < m; j += 64) acc = fma(q[j], (double)b[j], acc);
-    acc = wave_sum(acc);
-    if (lane == 0) ys[s] = acc;
-  }
-  __syncthreads();
-  double e = 0.0;
-  for (int64_t j = threadIdx.x; j < m; j += 256) {
-    double r = (double)b[j];
-    for (int s = 0; s < k; ++s) r = fma(-Q[j + (int64_t)s * ldq], ys[s], r);
-    e = fma(r, r, e);
-  }
-  red[threadIdx.x] = e;
-  __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
-    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) colerr[c] = red[0];
-}
-
 __global__ void k_q_to_f32(const double *__restrict__ Q, int64_t ldq, int64_t m, int k,
                            float *__restrict__ Q32, int64_t ld32) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -677,14 +644,6 @@ hipError_t launch_sumsq_f32(const float *B, int64_t m, int64_t r, int64_t ldb, d
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(256), 0, s, part, r, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_err_factor(const double *Q, int64_t ldq, int64_t m, int k, const float *B,
-                             int64_t ldb, int64_t r, double *colerr, hipStream_t s) {
-  const size_t shm = sizeof(double) * (size_t)(k > 0 ? k : 1);
-  hipLaunchKernelGGL(k_err_factor, dim3((unsigned)r), dim3(256), shm, s, Q, ldq, m, k, B, ldb,
-                     colerr);
   return hipGetLastError();
 }
 
