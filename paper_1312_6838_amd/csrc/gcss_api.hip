@@ -222,6 +222,7 @@ struct gcss_ctx {
   gcss_tuning tune{};
   // per-step work by the six-kernel chain (else the general cols / rows kernels)
   bool use_chain = false;
+  bool chain_ok = true;  // the chain is allowed (GCSS_CHAIN=0 turns it off)
   // captured loops: select_async's (with its output copy) and select's
   hipGraphExec_t graph = nullptr;
   int graph_k = -1;
@@ -546,7 +547,8 @@ gcss_status init_ctx(gcss_ctx *h, const gcss_desc *d, void *workspace, size_t ws
   // the general kernels, for comparisons)
   {
     const char *v = getenv("GCSS_CHAIN");
-    h->use_chain = L.chain && !(v && atoi(v) == 0);
+    h->chain_ok = !(v && atoi(v) == 0);
+    h->use_chain = L.chain && h->chain_ok;
   }
   h->ws = (char *)workspace;
   h->ws_bytes = ws_bytes;
@@ -1025,8 +1027,10 @@ namespace {
 // Per-block buffers of the batched selection, carved after the context's own.
 struct BLayout {
   size_t st, Q, ap64, e1, e2, w, q64, q32, z32, c1, c2, c3, ups, idx, obj, npart, groups, gfirst,
-      gpart, bcnt, kb, pick, a0, sc0, mloc, mobj, mns, mglob, sub, total;
+      gpart, bcnt, kb, V, P, Pn, Pu, pick, a0, sc0, mloc, mobj, mns, mglob, sub, total;
   int64_t sQ, sQ32, sIO, sC, sUps, ngroups_max;
+  int64_t lp, sP, sPn;  // the per-step chain's partials per block
+  bool chain;           // per-step work by the chain kernels, all blocks at once
 };
 
 gcss_desc sub_desc(const gcss_desc *d, int64_t npool, int32_t k_merge) {
@@ -1069,6 +1073,15 @@ bool make_blayout(const gcss_desc *d, const Layout &L, int nblocks, int kb, int 
   B->gpart = c.take<ArgPart>(B->ngroups_max);
   B->bcnt = c.take<uint32_t>(64);
   B->kb = c.take<int32_t>(nblocks);
+  // the chain's w history (as Q), dot partials and per-workgroup partials
+  B->chain = chain_fits(m, r, kb, kChainLdsMax);
+  B->lp = (int64_t)up((size_t)(r + kb + 1), 4);
+  B->sP = (int64_t)chain_row_blocks(m) * B->lp;
+  B->sPn = chain_row_groups(m);
+  B->V = B->chain ? c.take<double>((size_t)nblocks * B->sQ) : 0;
+  B->P = B->chain ? c.take<double>((size_t)nblocks * B->sP) : 0;
+  B->Pn = B->chain ? c.take<double>((size_t)nblocks * B->sPn) : 0;
+  B->Pu = B->chain ? c.take<double>((size_t)nblocks * B->sPn) : 0;
   // the pool: nblocks * kb slots (block-major), gathered into a0
   const int64_t P = (int64_t)nblocks * kb;
   B->pick = c.take<int64_t>(P);
@@ -1115,6 +1128,42 @@ hipError_t enqueue_batched_step(gcss_ctx *h, const BLayout &B, char *base, int n
   hipStream_t s = h->stream;
   hipError_t e;
   const AView &A = h->A;
+  if (B.chain && h->chain_ok) {
+    // the six chain kernels with every block along gridDim.z
+    ChainArgs ca{};
+    ca.st = sb.st;
+    ca.Q = Q;
+    ca.ldq = ldq;
+    ca.V = (double *)at(B.V);
+    ca.a = ap;
+    ca.e1 = e1;
+    ca.e2 = e2;
+    ca.P = (double *)at(B.P);
+    ca.lp = B.lp;
+    ca.Pn = (double *)at(B.Pn);
+    ca.Pu = (double *)at(B.Pu);
+    ca.B = h->Braw;
+    ca.ldb = h->ldb_raw;
+    ca.r = r;
+    ca.b_bf16 = h->b_dtype == GCSS_BF16;
+    ca.q64 = q64;
+    ca.q32 = q32;
+    ca.z32 = z32;
+    ca.g0 = sb.g0;
+    ca.mask = sb.mask;
+    ca.idx = sb.idx;
+    ca.obj = sb.obj;
+    ca.m = m;
+    ca.kmax = kb;
+    ca.nprob = nb;
+    ca.s_q = B.sQ;
+    ca.s_vec = ldq;
+    ca.s_p = B.sP;
+    ca.s_pn = B.sPn;
+    ca.s_q32 = B.sQ32;
+    ca.s_io = B.sIO;
+    if ((e = launch_chain(ca, s))) return e;
+  } else {
   if ((e = launch_cols(Q, nullptr, ldq, m, 1, 0, kb, VEC_F64, ap, A, c1, CF_NONE, sb, s, nb, bs, ArgStride{B.sQ, ldq, B.sC, 0}))) return e;
   if ((e = launch_rows(Q, nullptr, ldq, m, 1, 0, VEC_F64, ap, A, c1, e1, nullptr, RF_NONE, sb, s, nb, bs, ArgStride{B.sQ, ldq, ldq, B.sC}))) return e;
   if ((e = launch_cols(Q, nullptr, ldq, m, 1, 0, kb, VEC_F64, e1, A, c2, CF_NONE, sb, s, nb, bs, ArgStride{B.sQ, ldq, B.sC, 0}))) return e;
@@ -1123,6 +1172,7 @@ hipError_t enqueue_batched_step(gcss_ctx *h, const BLayout &B, char *base, int n
   if ((e = launch_rows(nullptr, h->B, h->ldb, m, 0, (int)r, -1, nullptr, A, ups, w, nullptr, RF_NONE, sb, s, nb, bs, ArgStride{0, 0, ldq, B.sUps}))) return e;
   if ((e = launch_cols(Q, nullptr, ldq, m, 1, 0, kb, VEC_F64, w, A, c3, CF_NONE, sb, s, nb, bs, ArgStride{B.sQ, ldq, B.sC, 0}))) return e;
   if ((e = launch_rows(Q, nullptr, ldq, m, 1, 0, VEC_F64, w, A, c3, nullptr, z32, RF_Z, sb, s, nb, bs, ArgStride{B.sQ, ldq, 0, B.sC}))) return e;
+  }
   if (timed && h->profiling && (e = record(h))) return e;
   if ((e = launch_stream_batched(h->L.geo, grid, A, (const GroupEnt *)at(B.groups), (int64_t)h->bgroups.size(), q32, z32, B.sQ32,
                                  h->at<double>(h->L.f), h->at<double>(h->L.g), h->at<double>(h->L.g0), h->at<uint8_t>(h->L.mask),

@@ -204,6 +204,16 @@ struct ChainArgs {
   double *obj;
   int64_t m;
   int kmax;
+  // several problems at once (Algorithm 4's blocks): problem b's state is
+  // st + b and its buffers sit at these strides from problem 0's; B, g0 and
+  // mask are shared (the blocks' columns are disjoint).  One problem: 1, 0s.
+  int nprob;
+  int64_t s_q;    // Q and V (doubles)
+  int64_t s_vec;  // a, e1, e2, q64 (doubles)
+  int64_t s_p;    // P (doubles)
+  int64_t s_pn;   // Pn and Pu (doubles)
+  int64_t s_q32;  // q32 and z32 (floats)
+  int64_t s_io;   // idx and obj
 };
 int chain_row_blocks(int64_t m);
 int chain_row_groups(int64_t m);

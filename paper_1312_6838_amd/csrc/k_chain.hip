@@ -1,5 +1,6 @@
-// The steps of one greedy pick between two streaming passes, for a single
-// selection problem: six kernels.
+// The steps of one greedy pick between two streaming passes: six kernels,
+// for one selection problem or, along gridDim.z, for several at once (the
+// blocks of Algorithm 4, each with its own state and buffers).
 //
 // With Q the orthonormal FP64 basis of the t picks so far, a the pick's
 // column (decoded to FP64 by the previous streaming pass), V = [w_1 .. w_t]
@@ -84,8 +85,16 @@ __global__ __launch_bounds__(256) void k_dots(const T1 *__restrict__ M1, int64_t
                                               const double *__restrict__ M2, int64_t ld2,
                                               const double *__restrict__ x, int64_t m,
                                               double *__restrict__ P, int64_t lp,
-                                              const DevState *st) {
+                                              const DevState *st, int64_t s_m2, int64_t s_x,
+                                              int64_t s_p) {
   __shared__ double red[4][kDotCols];
+  {  // problem blockIdx.z (M1 is shared)
+    const int b = blockIdx.z;
+    M2 += b * s_m2;
+    x += b * s_x;
+    P += b * s_p;
+    st += b;
+  }
   if (st->done || st->skip) return;
   const int ncols = nfix + st->t;
   const int c0 = blockIdx.x * kDotCols;
@@ -173,9 +182,19 @@ __global__ __launch_bounds__(1024) void k_rows_sub(const double *__restrict__ Q,
                                                    const double *__restrict__ P, int64_t lp,
                                                    int nrb, double *__restrict__ out,
                                                    double *__restrict__ Pn, int64_t m,
-                                                   const DevState *st) {
+                                                   const DevState *st, int64_t s_q,
+                                                   int64_t s_vec, int64_t s_p, int64_t s_pn) {
   extern __shared__ double cs[];  // t coefficients
   __shared__ double red[kRowGroups][kRowRB + 1];
+  {  // problem blockIdx.z
+    const int b = blockIdx.z;
+    Q += b * s_q;
+    v += b * s_vec;
+    P += b * s_p;
+    out += b * s_vec;
+    if (NORM) Pn += b * s_pn;
+    st += b;
+  }
   if (st->done || st->skip) return;
   const int t = st->t;
   const int r = threadIdx.x & (kRowRB - 1), g = threadIdx.x / kRowRB;
@@ -227,6 +246,7 @@ struct ZArgs {
   int64_t *idx;
   double *obj;
   int64_t m;
+  int64_t s_q, s_vec, s_p, s_pn, s_q32, s_io;  // per-problem strides (see ChainArgs)
 };
 
 // TB: element type of the explicit target (float or bfloat16 bits); GRAM:
@@ -238,6 +258,21 @@ __global__ __launch_bounds__(1024) void k_rows_z(ZArgs za, DevState *st) {
   __shared__ double redz[kRowGroups][kRowRB + 1];
   __shared__ double wsum[kRowThreads / 64];
   __shared__ double wrow[kRowRB];
+  {  // problem blockIdx.z (B, g0 and mask are shared)
+    const int64_t b = blockIdx.z;
+    za.Q += b * za.s_q;
+    za.V += b * za.s_q;
+    za.e2 += b * za.s_vec;
+    za.q64 += b * za.s_vec;
+    za.P += b * za.s_p;
+    za.Pn += b * za.s_pn;
+    if (za.Pu) za.Pu += b * za.s_pn;
+    za.q32 += b * za.s_q32;
+    za.z32 += b * za.s_q32;
+    za.idx += b * za.s_io;
+    za.obj += b * za.s_io;
+    st += b;
+  }
   if (st->done || st->skip) return;
   const int t = st->t;
   const int64_t p = st->p;
@@ -350,28 +385,34 @@ hipError_t launch_chain(const ChainArgs &ca, hipStream_t s) {
   if (nrb > kMaxRB) return hipErrorInvalidValue;
   const unsigned qdots = (unsigned)((ca.kmax + kDotCols - 1) / kDotCols);
   const size_t lds_t = (size_t)(ca.kmax + 1) * sizeof(double);
+  const unsigned np = (unsigned)(ca.nprob > 0 ? ca.nprob : 1);
   // K1: c1 partials
-  hipLaunchKernelGGL((k_dots<float>), dim3(qdots, nrb), dim3(256), 0, s, (const float *)nullptr,
-                     (int64_t)0, 0, ca.Q, ca.ldq, ca.a, m, ca.P, ca.lp, ca.st);
+  hipLaunchKernelGGL((k_dots<float>), dim3(qdots, nrb, np), dim3(256), 0, s, (const float *)nullptr,
+                     (int64_t)0, 0, ca.Q, ca.ldq, ca.a, m, ca.P, ca.lp, ca.st, ca.s_q, ca.s_vec,
+                     ca.s_p);
   // K2: e1 = a - Q c1
-  hipLaunchKernelGGL((k_rows_sub<false>), dim3(nrg), dim3(kRowThreads), lds_t, s, ca.Q, ca.ldq,
-                     ca.a, ca.P, ca.lp, nrb, ca.e1, (double *)nullptr, m, ca.st);
+  hipLaunchKernelGGL((k_rows_sub<false>), dim3(nrg, 1, np), dim3(kRowThreads), lds_t, s, ca.Q,
+                     ca.ldq, ca.a, ca.P, ca.lp, nrb, ca.e1, (double *)nullptr, m, ca.st, ca.s_q,
+                     ca.s_vec, ca.s_p, ca.s_pn);
   // K3: c2 partials
-  hipLaunchKernelGGL((k_dots<float>), dim3(qdots, nrb), dim3(256), 0, s, (const float *)nullptr,
-                     (int64_t)0, 0, ca.Q, ca.ldq, ca.e1, m, ca.P, ca.lp, ca.st);
+  hipLaunchKernelGGL((k_dots<float>), dim3(qdots, nrb, np), dim3(256), 0, s, (const float *)nullptr,
+                     (int64_t)0, 0, ca.Q, ca.ldq, ca.e1, m, ca.P, ca.lp, ca.st, ca.s_q, ca.s_vec,
+                     ca.s_p);
   // K4: e2 = e1 - Q c2, norm partials
-  hipLaunchKernelGGL((k_rows_sub<true>), dim3(nrg), dim3(kRowThreads), lds_t, s, ca.Q, ca.ldq,
-                     ca.e1, ca.P, ca.lp, nrb, ca.e2, ca.Pn, m, ca.st);
+  hipLaunchKernelGGL((k_rows_sub<true>), dim3(nrg, 1, np), dim3(kRowThreads), lds_t, s, ca.Q,
+                     ca.ldq, ca.e1, ca.P, ca.lp, nrb, ca.e2, ca.Pn, m, ca.st, ca.s_q, ca.s_vec,
+                     ca.s_p, ca.s_pn);
   // K5: [B^T e2 ; V^T e2] partials (B = A: [C e2 ; V^T e2])
   const int nfix = ca.gram ? (int)m : (int)ca.r;
   const unsigned tdots = (unsigned)((nfix + ca.kmax + kDotCols - 1) / kDotCols);
   if (ca.b_bf16 && !ca.gram)
-    hipLaunchKernelGGL((k_dots<uint16_t>), dim3(tdots, nrb), dim3(256), 0, s,
+    hipLaunchKernelGGL((k_dots<uint16_t>), dim3(tdots, nrb, np), dim3(256), 0, s,
                        (const uint16_t *)ca.B, ca.ldb, nfix, ca.V, ca.ldq, ca.e2, m, ca.P, ca.lp,
-                       ca.st);
+                       ca.st, ca.s_q, ca.s_vec, ca.s_p);
   else
-    hipLaunchKernelGGL((k_dots<float>), dim3(tdots, nrb), dim3(256), 0, s, (const float *)ca.B,
-                       ca.ldb, nfix, ca.V, ca.ldq, ca.e2, m, ca.P, ca.lp, ca.st);
+    hipLaunchKernelGGL((k_dots<float>), dim3(tdots, nrb, np), dim3(256), 0, s, (const float *)ca.B,
+                       ca.ldb, nfix, ca.V, ca.ldq, ca.e2, m, ca.P, ca.lp, ca.st, ca.s_q, ca.s_vec,
+                       ca.s_p);
   // K6
   ZArgs za{};
   za.Q = ca.Q;
@@ -396,14 +437,20 @@ hipError_t launch_chain(const ChainArgs &ca, hipStream_t s) {
   za.idx = ca.idx;
   za.obj = ca.obj;
   za.m = m;
+  za.s_q = ca.s_q;
+  za.s_vec = ca.s_vec;
+  za.s_p = ca.s_p;
+  za.s_pn = ca.s_pn;
+  za.s_q32 = ca.s_q32;
+  za.s_io = ca.s_io;
   const size_t lds_z = (size_t)(za.r + ca.kmax + 1) * sizeof(double);
+  const dim3 gz(nrg, 1, np);
   if (ca.gram)
-    hipLaunchKernelGGL((k_rows_z<float, true>), dim3(nrg), dim3(kRowThreads), lds_z, s, za, ca.st);
+    hipLaunchKernelGGL((k_rows_z<float, true>), gz, dim3(kRowThreads), lds_z, s, za, ca.st);
   else if (ca.b_bf16)
-    hipLaunchKernelGGL((k_rows_z<uint16_t, false>), dim3(nrg), dim3(kRowThreads), lds_z, s, za,
-                       ca.st);
+    hipLaunchKernelGGL((k_rows_z<uint16_t, false>), gz, dim3(kRowThreads), lds_z, s, za, ca.st);
   else
-    hipLaunchKernelGGL((k_rows_z<float, false>), dim3(nrg), dim3(kRowThreads), lds_z, s, za, ca.st);
+    hipLaunchKernelGGL((k_rows_z<float, false>), gz, dim3(kRowThreads), lds_z, s, za, ca.st);
   return hipGetLastError();
 }
 

@@ -1452,7 +1452,12 @@ __global__ __launch_bounds__(kG2Threads, 1) void k_proj_x3(AView A, const float 
   // of Omega, for k = k0 + k8 .. k0 + k8 + 7
   const int op = tid >> 8, task = tid & 255;
   const int q0 = x3_task_row(task), k8 = x3_task_k(task);
+  // the loads of a stage are kept raw (BF16 / E4M3 codes of A as bits, Omega
+  // and the FP8 column scales unmultiplied) and decoded only when the stage
+  // goes to LDS, so the next stage's loads stay in flight through this
+  // stage's matrix products instead of being waited for where they are issued
   float4 reg[8];
+  float scl[8];
   // (m and r are multiples of 4: four rows or columns are in or out together)
   auto gload = [&](int64_t k0) {
     const int64_t q = (op == 0 ? i0 : j0) + q0;
@@ -1461,6 +1466,7 @@ __global__ __launch_bounds__(kG2Threads, 1) void k_proj_x3(AView A, const float 
     for (int e = 0; e < 8; ++e) {
       const int64_t k = k0 + k8 + e;
       float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      float sk = 0.f;
       if (inq && k < ke) {
         if (op == 0) {
           const char *src = abase + (k * A.lda + q) * ES;
@@ -1468,33 +1474,44 @@ __global__ __launch_bounds__(kG2Threads, 1) void k_proj_x3(AView A, const float 
             v = *(const float4 *)src;
           } else if constexpr (DT == DT_BF16) {
             const uint2 w = *(const uint2 *)src;
-            v = make_float4(bf16_lo(w.x), bf16_hi(w.x), bf16_lo(w.y), bf16_hi(w.y));
+            v.x = __uint_as_float(w.x);
+            v.y = __uint_as_float(w.y);
           } else {
-            float d[4];
-            fp8x4_decode(*(const uint32_t *)src, d);
-            v = make_float4(d[0], d[1], d[2], d[3]);
+            v.x = __uint_as_float(*(const uint32_t *)src);
           }
         } else {
           v = *(const float4 *)(Om + k * r + q);
-          if constexpr (DT == DT_FP8) {
-            const float sk = A.scale[k];
-            v.x *= sk;
-            v.y *= sk;
-            v.z *= sk;
-            v.w *= sk;
-          }
+          if constexpr (DT == DT_FP8) sk = A.scale[k];
         }
       }
       reg[e] = v;
+      scl[e] = sk;
     }
+  };
+  // element (row / column q0 + rr, k k8 + e) of the stage as a binary32 value
+  auto elem = [&](int e, int rr) -> float {
+    const float4 v = reg[e];
+    if (op == 0) {
+      if constexpr (DT == DT_BF16) {
+        const uint32_t w = __float_as_uint(rr < 2 ? v.x : v.y);
+        return (rr & 1) ? bf16_hi(w) : bf16_lo(w);
+      } else if constexpr (DT == DT_FP8) {
+        float d[4];
+        fp8x4_decode(__float_as_uint(v.x), d);
+        return d[rr];
+      }
+    }
+    const float x = rr == 0 ? v.x : rr == 1 ? v.y : rr == 2 ? v.z : v.w;
+    if constexpr (DT == DT_FP8)
+      if (op == 1) return x * scl[e];
+    return x;
   };
   auto lstore = [&]() {
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) {
       float x[8];
 #pragma unroll
-      for (int e = 0; e < 8; ++e)
-        x[e] = rr == 0 ? reg[e].x : rr == 1 ? reg[e].y : rr == 2 ? reg[e].z : reg[e].w;
+      for (int e = 0; e < 8; ++e) x[e] = elem(e, rr);
       const int off = (q0 + rr) * kX3RP + k8;
       if (op == 1 || AP == 3) {
         bf16x8 h, md, lo;

@@ -64,7 +64,8 @@ def _quantized(gpu, A32, m, dt):
     return Adev, sc, Aval
 
 
-@pytest.mark.parametrize("m,n,r,dt", [(300, 1000, 256, "bf16"), (520, 700, 200, "fp8")])
+@pytest.mark.parametrize("m,n,r,dt", [(300, 1000, 256, "bf16"), (520, 700, 200, "fp8"),
+                                        (516, 900, 260, "bf16"), (1028, 1500, 512, "fp8")])
 def test_projection_quantized_storage(gpu, m, n, r, dt):
     """B = A_hat Omega from BF16 / FP8 codes (large-tile path), entry by entry."""
     A32 = colstore32(synth.gauss_lowrank_dense(m, n, 10, 0.1, seed=m + 1))
