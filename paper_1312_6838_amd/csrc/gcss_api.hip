@@ -223,6 +223,10 @@ struct gcss_ctx {
   // per-step work by the six-kernel chain (else the general cols / rows kernels)
   bool use_chain = false;
   bool chain_ok = true;  // the chain is allowed (GCSS_CHAIN=0 turns it off)
+  // per-step kernels of the batched block phase: 0 the fastest that fits,
+  // 1 one workgroup per block, 2 the six chain kernels, 3 the general
+  // kernels (GCSS_BATCH_STEP=block / chain / general, for comparisons)
+  int batch_step = 0;
   // captured loops: select_async's (with its output copy) and select's
   hipGraphExec_t graph = nullptr;
   int graph_k = -1;
@@ -549,6 +553,8 @@ gcss_status init_ctx(gcss_ctx *h, const gcss_desc *d, void *workspace, size_t ws
     const char *v = getenv("GCSS_CHAIN");
     h->chain_ok = !(v && atoi(v) == 0);
     h->use_chain = L.chain && h->chain_ok;
+    const char *bs = getenv("GCSS_BATCH_STEP");
+    h->batch_step = !bs ? 0 : !strcmp(bs, "block") ? 1 : !strcmp(bs, "chain") ? 2 : !strcmp(bs, "general") ? 3 : 0;
   }
   h->ws = (char *)workspace;
   h->ws_bytes = ws_bytes;
@@ -1128,8 +1134,15 @@ hipError_t enqueue_batched_step(gcss_ctx *h, const BLayout &B, char *base, int n
   hipStream_t s = h->stream;
   hipError_t e;
   const AView &A = h->A;
-  if (B.chain && h->chain_ok) {
-    // the six chain kernels with every block along gridDim.z
+  // one workgroup per block while a block's step is small (and there are
+  // blocks enough to spread over the chip), else the six chain kernels with
+  // every block along gridDim.z, else the general kernels
+  const bool fits_block = B.chain && chain_block_fits(m, r, kb, kChainLdsMax);
+  int mode = h->batch_step;
+  if (mode == 0) mode = !h->chain_ok ? 3 : (fits_block && nb >= 16 && kb <= 64) ? 1 : B.chain ? 2 : 3;
+  if (mode == 1 && !fits_block) mode = B.chain ? 2 : 3;
+  if (mode == 2 && !B.chain) mode = 3;
+  if (mode != 3) {
     ChainArgs ca{};
     ca.st = sb.st;
     ca.Q = Q;
@@ -1162,7 +1175,7 @@ hipError_t enqueue_batched_step(gcss_ctx *h, const BLayout &B, char *base, int n
     ca.s_pn = B.sPn;
     ca.s_q32 = B.sQ32;
     ca.s_io = B.sIO;
-    if ((e = launch_chain(ca, s))) return e;
+    if ((e = mode == 1 ? launch_chain_block(ca, s) : launch_chain(ca, s))) return e;
   } else {
   if ((e = launch_cols(Q, nullptr, ldq, m, 1, 0, kb, VEC_F64, ap, A, c1, CF_NONE, sb, s, nb, bs, ArgStride{B.sQ, ldq, B.sC, 0}))) return e;
   if ((e = launch_rows(Q, nullptr, ldq, m, 1, 0, VEC_F64, ap, A, c1, e1, nullptr, RF_NONE, sb, s, nb, bs, ArgStride{B.sQ, ldq, ldq, B.sC}))) return e;

@@ -221,6 +221,11 @@ size_t chain_lds_bytes(int64_t r, int kmax);
 // the chain serves the shape: m within its row blocks, r + kmax + 1 doubles of LDS
 bool chain_fits(int64_t m, int64_t r, int kmax, size_t lds_max);
 hipError_t launch_chain(const ChainArgs &ca, hipStream_t s);
+// The same step with one workgroup per problem (small problems: m <= 2048,
+// explicit target; ca.nprob problems at the strides of ChainArgs)
+size_t chain_block_lds_bytes(int64_t m, int64_t r, int kmax);
+bool chain_block_fits(int64_t m, int64_t r, int kmax, size_t lds_max);
+hipError_t launch_chain_block(const ChainArgs &ca, hipStream_t s);
 
 // ---- launchers (k_mfma.hip) ----
 // f0_i = scale_i^2 * || X^T A_i ||^2 (X: m x R, K-contiguous, ldx), g0_i, mask0_i

@@ -370,6 +370,186 @@ __global__ __launch_bounds__(1024) void k_rows_z(ZArgs za, DevState *st) {
 }
 
 // ---------------------------------------------------------------------------
+// The whole step of one small problem in one workgroup (blockIdx.x = the
+// problem): for Algorithm 4's blocks, whose m, t and r are small, one
+// workgroup per block does the six kernels' work with barriers in place of
+// kernel boundaries, so a step of all blocks is one launch of nprob
+// workgroups instead of six launches of thousands.  Same operations as
+// K1-K6 (Gram-Schmidt with one re-orthogonalisation, the basis check,
+// upsilon = B^T q, c3 = V^T q, w = B upsilon, z = w - Q c3, the pick's
+// record); dot products are wave sums over the rows, row sums run over the
+// columns in order, so every result has a fixed summation order.
+constexpr int kBlkThreads = 1024;
+constexpr int kBlkWaves = kBlkThreads / 64;
+constexpr int kBlkMaxM = 2048;  // rows held in LDS
+
+// sum over waves (in order) of one double per wave; every thread gets it
+__device__ __forceinline__ double blk_sum(double v, double *wsum) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int x = 0; x < kBlkWaves; ++x) s += wsum[x];
+  __syncthreads();
+  return s;
+}
+
+// out[c] = sum_j M_c[j] x[j] for c < nc (M_c column c, ld ldm, element type
+// T): wave w takes four columns at a time (w * 4 + 64 u ..), lanes stride
+// the rows, sixteen loads in flight per lane.
+template <typename T>
+__device__ __forceinline__ void blk_dots(const T *__restrict__ M, int64_t ldm, int nc,
+                                         const double *x, int64_t m, double *out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int c0 = wave * 4; c0 < nc; c0 += 4 * kBlkWaves) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t j0 = lane; j0 < m; j0 += 256) {
+      double xv[4];
+      T v[4][4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t j = j0 + 64 * u;
+        xv[u] = j < m ? x[j] : 0.0;
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) {
+          const int c = c0 + cc < nc ? c0 + cc : nc - 1;
+          v[cc][u] = M[(int64_t)c * ldm + (j < m ? j : m - 1)];
+        }
+      }
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[cc] = fma(to_f64(v[cc][u]), xv[u], acc[cc]);
+    }
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc) {
+      const double a = wave_sum(acc[cc]);
+      if (lane == 0 && c0 + cc < nc) out[c0 + cc] = a;
+    }
+  }
+}
+
+// sum over s < ns (in order) of M[j + s ldm] * c[s], sixteen loads in flight
+template <typename T>
+__device__ __forceinline__ double blk_row(const T *__restrict__ M, int64_t ldm, int ns, int64_t j,
+                                          const double *c) {
+  double acc = 0.0;
+  int s = 0;
+  for (; s + 16 <= ns; s += 16) {
+    T v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = M[(int64_t)(s + u) * ldm + j];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) acc = fma(to_f64(v[u]), c[s + u], acc);
+  }
+  for (; s < ns; ++s) acc = fma(to_f64(M[(int64_t)s * ldm + j]), c[s], acc);
+  return acc;
+}
+
+template <typename TB>
+__global__ __launch_bounds__(kBlkThreads) void k_chain_block(ChainArgs ca) {
+  extern __shared__ double lds[];  // vec (m), coefficients (kmax + 1), upsilon (r)
+  __shared__ double wsum[kBlkWaves];
+  const int64_t b = blockIdx.x;
+  DevState *st = ca.st + b;
+  if (st->done || st->skip) return;
+  const int t = st->t;
+  const int64_t p = st->p;
+  const int64_t m = ca.m;
+  const int r = (int)ca.r;
+  const double *Q = ca.Q + b * ca.s_q;
+  double *Qw = ca.Q + b * ca.s_q;
+  double *V = ca.V + b * ca.s_q;
+  const double *a = ca.a + b * ca.s_vec;
+  const TB *B = (const TB *)ca.B;
+  double *vec = lds, *cf = lds + m, *ups = cf + (ca.kmax + 1);
+  for (int64_t j = threadIdx.x; j < m; j += kBlkThreads) vec[j] = a[j];
+  __syncthreads();
+  // Gram-Schmidt twice: vec <- vec - Q (Q^T vec)
+  double nrm2 = 0.0;
+  for (int pass = 0; pass < 2; ++pass) {
+    blk_dots(Q, ca.ldq, t, vec, m, cf);
+    __syncthreads();
+    double sq = 0.0;
+    for (int64_t j = threadIdx.x; j < m; j += kBlkThreads) {
+      const double e = vec[j] - blk_row(Q, ca.ldq, t, j, cf);
+      vec[j] = e;
+      sq = fma(e, e, sq);
+    }
+    __syncthreads();
+    if (pass == 1) nrm2 = blk_sum(sq, wsum);
+  }
+  // the basis check (the same rule as the chain's K6)
+  const double thr = st->tau * ca.g0[p];
+  if (!(isfinite(nrm2) && nrm2 > thr)) {
+    if (threadIdx.x == 0) {
+      ca.mask[p] = 2;
+      st->skip = 1;
+      st->n_reject += 1;
+      st->enorm2 = nrm2;
+    }
+    return;
+  }
+  const double inv = 1.0 / sqrt(nrm2);
+  double *q64 = ca.q64 + b * ca.s_vec;
+  float *q32 = ca.q32 + b * ca.s_q32;
+  for (int64_t j = threadIdx.x; j < m; j += kBlkThreads) {
+    const double qv = vec[j] * inv;
+    vec[j] = qv;
+    Qw[(int64_t)t * ca.ldq + j] = qv;
+    q64[j] = qv;
+    q32[j] = (float)qv;
+  }
+  __syncthreads();
+  // upsilon = B^T q, c3 = V^T q
+  blk_dots(B, ca.ldb, r, vec, m, ups);
+  blk_dots((const double *)V, ca.ldq, t, vec, m, cf);
+  __syncthreads();
+  double a2 = 0.0;
+  for (int c = threadIdx.x; c < r; c += kBlkThreads) a2 = fma(ups[c], ups[c], a2);
+  const double u2 = blk_sum(a2, wsum);
+  // w = B upsilon, z = w - Q c3
+  float *z32 = ca.z32 + b * ca.s_q32;
+  for (int64_t j = threadIdx.x; j < m; j += kBlkThreads) {
+    const double wj = blk_row(B, ca.ldb, r, j, ups);
+    const double qc = blk_row(Q, ca.ldq, t, j, cf);
+    V[(int64_t)t * ca.ldq + j] = wj;
+    z32[j] = (float)(wj - qc);
+  }
+  if (threadIdx.x == 0) {
+    const double F = st->F - u2;
+    st->u2 = u2;
+    st->enorm2 = nrm2;
+    st->F = F;
+    ca.obj[b * ca.s_io + t + 1] = F;
+    ca.idx[b * ca.s_io + t] = p;
+    ca.mask[p] = 1;
+    st->t = t + 1;
+    st->dec_pending = 1;
+    if (t + 1 >= st->k) st->done = 1;
+  }
+}
+
+size_t chain_block_lds_bytes(int64_t m, int64_t r, int kmax) {
+  return (size_t)(m + kmax + 1 + r) * sizeof(double);
+}
+
+bool chain_block_fits(int64_t m, int64_t r, int kmax, size_t lds_max) {
+  return m <= kBlkMaxM && chain_block_lds_bytes(m, r, kmax) <= lds_max;
+}
+
+hipError_t launch_chain_block(const ChainArgs &ca, hipStream_t s) {
+  const size_t lds = chain_block_lds_bytes(ca.m, ca.r, ca.kmax);
+  const unsigned np = (unsigned)(ca.nprob > 0 ? ca.nprob : 1);
+  if (ca.b_bf16)
+    hipLaunchKernelGGL((k_chain_block<uint16_t>), dim3(np), dim3(kBlkThreads), lds, s, ca);
+  else
+    hipLaunchKernelGGL((k_chain_block<float>), dim3(np), dim3(kBlkThreads), lds, s, ca);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 int chain_row_blocks(int64_t m) { return (int)((m + kDotRows - 1) / kDotRows); }
 int chain_row_groups(int64_t m) { return (int)((m + kRowRB - 1) / kRowRB); }
 
