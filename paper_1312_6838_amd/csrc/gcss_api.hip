@@ -227,6 +227,9 @@ struct gcss_ctx {
   // 1 one workgroup per block, 2 the six chain kernels, 3 the general
   // kernels (GCSS_BATCH_STEP=block / chain / general, for comparisons)
   int batch_step = 0;
+  // merge of Algorithm 4 over its sub-context even where the pool's Gram
+  // form fits (GCSS_MERGE=sub, for comparisons)
+  bool merge_sub = false;
   // captured loops: select_async's (with its output copy) and select's
   hipGraphExec_t graph = nullptr;
   int graph_k = -1;
@@ -555,6 +558,8 @@ gcss_status init_ctx(gcss_ctx *h, const gcss_desc *d, void *workspace, size_t ws
     h->use_chain = L.chain && h->chain_ok;
     const char *bs = getenv("GCSS_BATCH_STEP");
     h->batch_step = !bs ? 0 : !strcmp(bs, "block") ? 1 : !strcmp(bs, "chain") ? 2 : !strcmp(bs, "general") ? 3 : 0;
+    const char *ms = getenv("GCSS_MERGE");
+    h->merge_sub = ms && !strcmp(ms, "sub");
   }
   h->ws = (char *)workspace;
   h->ws_bytes = ws_bytes;
@@ -1037,7 +1042,13 @@ struct BLayout {
   int64_t sQ, sQ32, sIO, sC, sUps, ngroups_max;
   int64_t lp, sP, sPn;  // the per-step chain's partials per block
   bool chain;           // per-step work by the chain kernels, all blocks at once
+  // the merge over the pool's Gram form (pools of at most kGramMergeMax slots)
+  bool gm;
+  size_t mst, GH, mf, mg, mg0, mex, mW, mU, mpart;
+  int64_t ldgh;
 };
+
+constexpr int64_t kGramMergeMax = 2048;
 
 gcss_desc sub_desc(const gcss_desc *d, int64_t npool, int32_t k_merge) {
   gcss_desc s = *d;
@@ -1098,6 +1109,20 @@ bool make_blayout(const gcss_desc *d, const Layout &L, int nblocks, int kb, int 
   B->mobj = c.take<double>(km + 8);
   B->mns = c.take<int32_t>(64);
   B->mglob = c.take<int64_t>(km + 8);
+  // the Gram form of the merge: G and H (P x (P + r)), scores, histories
+  B->gm = P <= kGramMergeMax;
+  B->ldgh = (int64_t)up((size_t)(P + r), 4);
+  if (B->gm) {
+    B->mst = c.take<DevState>(1);
+    B->GH = c.take<double>((size_t)P * B->ldgh);
+    B->mf = c.take<double>(P);
+    B->mg = c.take<double>(P);
+    B->mg0 = c.take<double>(P);
+    B->mex = c.take<uint8_t>(P);
+    B->mW = c.take<double>((size_t)(km + 1) * P);
+    B->mU = c.take<double>((size_t)(km + 1) * r);
+    B->mpart = c.take<ArgPart>(merge_step_groups(P));
+  }
   if (km > P) return false;
   gcss_desc sd = sub_desc(d, P, km);
   Layout SL;
@@ -1203,6 +1228,41 @@ namespace {
 // initial scores, its selection loop (outputs into the batched region) and
 // the global indices of its picks.  No host involvement: it is captured with
 // the block phase.
+// The merge's arguments for the Gram form (k_merge.hip).
+MergeArgs merge_args(gcss_ctx *h, const BLayout &B, char *base, int64_t P, int km) {
+  MergeArgs a{};
+  a.a0 = base + B.a0;
+  a.sc0 = (const float *)(base + B.sc0);
+  a.lda = h->d.lda;
+  a.m = h->d.m;
+  a.P = P;
+  a.B = h->B;
+  a.ldb = h->ldb;
+  a.r = (int)h->r;
+  a.GH = (double *)(base + B.GH);
+  a.ldgh = B.ldgh;
+  a.f = (double *)(base + B.mf);
+  a.g = (double *)(base + B.mg);
+  a.g0 = (double *)(base + B.mg0);
+  a.excl = (uint8_t *)(base + B.mex);
+  a.W = (double *)(base + B.mW);
+  a.U = (double *)(base + B.mU);
+  a.part = (ArgPart *)(base + B.mpart);
+  a.st = (DevState *)(base + B.mst);
+  a.loc = (int64_t *)(base + B.mloc);
+  a.obj = (double *)(base + B.mobj);
+  a.ns = (int32_t *)(base + B.mns);
+  a.F0 = h->F0();
+  a.tau = h->d.tau;
+  a.k = km;
+  return a;
+}
+
+bool use_gram_merge(const gcss_ctx *h, const BLayout &B, int km) {
+  return B.gm && !h->merge_sub &&
+         merge_gram_lds_bytes(km, (int)h->r) <= 48 * 1024;
+}
+
 hipError_t enqueue_merge(gcss_ctx *h, const BLayout &B, char *base, int nb, int kbm, int km) {
   hipStream_t s = h->stream;
   gcss_ctx *sub = h->msub;
@@ -1212,6 +1272,16 @@ hipError_t enqueue_merge(gcss_ctx *h, const BLayout &B, char *base, int nb, int 
   if (!e) e = launch_gather_cols(h->A, (const int64_t *)(base + B.pick), P, base + B.a0,
                                  (float *)(base + B.sc0), s);
   if (e) return e;
+  if (use_gram_merge(h, B, km)) {
+    // the pool's Gram form: G and H once, then one launch per step (the
+    // first only picks), spare steps for rejected picks
+    const MergeArgs a = merge_args(h, B, base, P, km);
+    e = launch_merge_gram(a, h->A.dtype, s);
+    for (int i = 0; !e && i < km + 1 + kSpareSlots; ++i) e = launch_merge_step(a, s);
+    if (!e) e = launch_merge_map((const int64_t *)(base + B.mloc), (const int64_t *)(base + B.pick), P,
+                                 km, (int64_t *)(base + B.mglob), s);
+    return e;
+  }
   hipStream_t own = sub->stream;
   sub->stream = s;
   if (gcss_set_target(sub, h->B, GCSS_F32, h->r, h->ldb) != GCSS_OK) e = hipErrorInvalidValue;
@@ -1486,13 +1556,15 @@ gcss_status gcss_select_batched_budgets(gcss_ctx *h, int32_t nblocks, const int6
   std::vector<double> mo(k_merge + 1);
   int32_t mns = 0;
   DevState mst;
+  const bool gram = use_gram_merge(h, B, k_merge);
   auto fetch = [&]() -> hipError_t {
     hipError_t e = hipMemcpyAsync(slots.data(), base + B.pick, sizeof(int64_t) * P, hipMemcpyDeviceToHost, s);
     if (!e) e = hipMemcpyAsync(bst.data(), base + B.st, sizeof(DevState) * nblocks, hipMemcpyDeviceToHost, s);
     if (!e) e = hipMemcpyAsync(mg.data(), base + B.mglob, sizeof(int64_t) * k_merge, hipMemcpyDeviceToHost, s);
     if (!e) e = hipMemcpyAsync(mo.data(), base + B.mobj, sizeof(double) * (k_merge + 1), hipMemcpyDeviceToHost, s);
     if (!e) e = hipMemcpyAsync(&mns, base + B.mns, sizeof(int32_t), hipMemcpyDeviceToHost, s);
-    if (!e) e = hipMemcpyAsync(&mst, h->msub->at<DevState>(h->msub->L.st), sizeof mst, hipMemcpyDeviceToHost, s);
+    const DevState *mstp = gram ? (const DevState *)(base + B.mst) : h->msub->at<DevState>(h->msub->L.st);
+    if (!e) e = hipMemcpyAsync(&mst, mstp, sizeof mst, hipMemcpyDeviceToHost, s);
     if (!e) e = hipStreamSynchronize(s);
     return e;
   };
@@ -1527,7 +1599,24 @@ gcss_status gcss_select_batched_budgets(gcss_ctx *h, int32_t nblocks, const int6
   }
   // a merge whose basis check rejected more picks than its spare steps: the
   // missing steps, then its outputs again
-  if (!mst.done) {
+  if (!mst.done && gram) {
+    // the Gram form: more steps until done (each step adds a pick or drops
+    // a candidate)
+    const MergeArgs a = merge_args(h, B, base, P, k_merge);
+    int64_t ran = 0;
+    while (!mst.done) {
+      if (ran > (int64_t)k_merge + P)
+        return fail(GCSS_ERR_DEVICE, "merge selection did not finish after %lld extra steps", (long long)ran);
+      const int need = std::max(1, k_merge - mst.t);
+      for (int i = 0; i < need; ++i) HIPCHK(launch_merge_step(a, s));
+      ran += need;
+      HIPCHK(hipMemcpyAsync(&mst, base + B.mst, sizeof mst, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+    }
+    HIPCHK(launch_merge_map((const int64_t *)(base + B.mloc), (const int64_t *)(base + B.pick), P, k_merge,
+                            (int64_t *)(base + B.mglob), s));
+    HIPCHK(fetch());
+  } else if (!mst.done) {
     gcss_ctx *sub = h->msub;
     int64_t ran = 0;
     while (!mst.done) {

@@ -355,6 +355,36 @@ hipError_t launch_seg_sum(const double *x, const int64_t *off, int nseg, double 
 hipError_t launch_gather_cols(const AView &A, const int64_t *pick, int64_t npick, void *a0,
                               float *scale0, hipStream_t s);
 
+// ---- the merge selection of Algorithm 4 over a small pool (k_merge.hip) ----
+struct MergeArgs {
+  const void *a0;      // pooled columns (stored type, ld lda), P of them
+  const float *sc0;    // their FP8 scales
+  int64_t lda, m, P;
+  const float *B;      // target, binary32, ld ldb, r columns
+  int64_t ldb;
+  int r;
+  double *GH;          // row i: G_i. (P entries) then H_i. (r), ld ldgh
+  int64_t ldgh;
+  double *f, *g, *g0;  // P each
+  uint8_t *excl;       // P: 1 picked, 2 dropped by the basis check
+  double *W;           // k x P, row s = omega^(s)
+  double *U;           // k x r, row s = upsilon^(s)
+  ArgPart *part;       // one per step workgroup
+  DevState *st;
+  int64_t *loc;        // k picks (pool positions), -1 past the last
+  double *obj;         // k + 1
+  int32_t *ns;         // picks made
+  const double *F0;    // ||B||_F^2
+  double tau;
+  int k;
+};
+size_t merge_gram_lds_bytes(int k, int r);
+int merge_step_groups(int64_t P);
+// G, H, the initial scores and the state (dtype: storage type of the pool)
+hipError_t launch_merge_gram(const MergeArgs &a, int dtype, hipStream_t s);
+// one step: the pick's update of every candidate and the next pick
+hipError_t launch_merge_step(const MergeArgs &a, hipStream_t s);
+
 // ---- context facts the autotuner keys its cache on (gcss_api.hip) ----
 struct CtxInfo {
   hipStream_t stream;

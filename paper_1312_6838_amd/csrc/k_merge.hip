@@ -1,0 +1,339 @@
+// Algorithm 4's second phase (the selection over the pooled picks) for a
+// small pool, in the recursive form of Algorithm 3 over the pool's own
+// matrices (Theorem 4):
+//   G = A0^T A0 (P x P) and H = A0^T B (P x r), once, in FP64;
+//   initial scores f_i = ||H_i||^2, g_i = G_ii;
+//   per step, with p the pick and wp_s = omega^(s)_p:
+//     delta_i   = G_pi - sum_s omega^(s)_i wp_s        (residual Gram column)
+//     upsilon_c = (H_pc - sum_s upsilon^(s)_c wp_s) / sqrt(delta_p)
+//     omega_i   = delta_i / sqrt(delta_p)
+//     hu_i      = H_i . upsilon - sum_s omega^(s)_i (upsilon^(s) . upsilon)
+//     f_i      <- f_i - 2 omega_i hu_i + ||upsilon||^2 omega_i^2
+//     g_i      <- g_i - omega_i^2
+//   and the argmax of f_i / g_i for the next pick.
+// A pick with delta_p <= tau g0_p (dependent up to rounding) is dropped and
+// the search repeated, as in the main selection.  The whole step is one
+// launch: every workgroup recomputes the few shared quantities (delta_p,
+// upsilon, ||upsilon||^2, upsilon^(s) . upsilon) with identical code, so all
+// of them see the same bits, updates its slice of candidates, and the last
+// workgroup to finish reduces the argmax and records the pick.  The pool is
+// small (its Gram matrix is read one row per step), so a step costs about
+// one launch instead of a streaming pass plus six chain kernels.
+#include "gcss_device.h"
+
+namespace gcss {
+
+constexpr int kMT = 64;  // Gram tile edge
+constexpr int kMK = 32;  // contraction chunk
+constexpr int kMergeCPW = 32;  // candidates per workgroup of a step (8 lanes each)
+
+// Decoded, scaled element k of pool column c.
+template <int DT>
+__device__ __forceinline__ double pool_elem(const MergeArgs &a, int64_t c, int64_t k) {
+  const double s = DT == DT_FP8 ? (double)a.sc0[c] : 1.0;
+  if constexpr (DT == DT_F32) {
+    return (double)((const float *)a.a0)[c * a.lda + k];
+  } else if constexpr (DT == DT_BF16) {
+    return (double)__uint_as_float((uint32_t)((const uint16_t *)a.a0)[c * a.lda + k] << 16);
+  } else {
+    const uint8_t code = ((const uint8_t *)a.a0)[c * a.lda + k];
+    f32x2 v = __builtin_amdgcn_cvt_pk_f32_fp8((uint32_t)code, false);
+    return s * (double)v[0];
+  }
+}
+
+// GH[i][j] = pool column i . Y_j, Y_j = pool column j (j < P) or target
+// column j - P; 64 x 64 tiles, FP64, fixed summation order (chunks of 32
+// rows in order).  G comes out exactly symmetric: entries (i, j) and (j, i)
+// multiply the same pairs in the same order.
+template <int DT>
+__global__ __launch_bounds__(256) void k_pool_gh(MergeArgs a) {
+  __shared__ double xs[kMK][kMT + 1];
+  __shared__ double ys[kMK][kMT + 1];
+  const int64_t i0 = (int64_t)blockIdx.x * kMT, j0 = (int64_t)blockIdx.y * kMT;
+  const int64_t P = a.P, m = a.m, ncol = a.P + a.r;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int lr = threadIdx.x & 31, lc = threadIdx.x >> 5;
+  double acc[4][4] = {};
+  for (int64_t kb = 0; kb < m; kb += kMK) {
+    const int64_t k = kb + lr;
+#pragma unroll
+    for (int x = 0; x < 8; ++x) {
+      const int cc = lc + 8 * x;
+      const int64_t ci = i0 + cc, cj = j0 + cc;
+      xs[lr][cc] = (k < m && ci < P) ? pool_elem<DT>(a, ci, k) : 0.0;
+      double yv = 0.0;
+      if (k < m && cj < ncol)
+        yv = cj < P ? pool_elem<DT>(a, cj, k) : (double)a.B[(cj - P) * a.ldb + k];
+      ys[lr][cc] = yv;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int kk = 0; kk < kMK; ++kk) {
+      double u[4], v[4];
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        u[x] = xs[kk][ty + 16 * x];
+        v[x] = ys[kk][tx + 16 * x];
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = fma(u[x], v[y], acc[x][y]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int x = 0; x < 4; ++x) {
+    const int64_t i = i0 + ty + 16 * x;
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      const int64_t j = j0 + tx + 16 * y;
+      if (i < P && j < ncol) a.GH[i * a.ldgh + j] = acc[x][y];
+    }
+  }
+}
+
+// Initial scores and state of the merge selection.
+__global__ void k_merge_init(MergeArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < a.P) {
+    const double *row = a.GH + i * a.ldgh;
+    double f = 0.0;
+    for (int c = 0; c < a.r; ++c) f = fma(row[a.P + c], row[a.P + c], f);
+    a.f[i] = f;
+    a.g[i] = row[i];
+    a.g0[i] = row[i];
+    a.excl[i] = 0;
+  }
+  if (blockIdx.x == 0) {
+    const double F = *a.F0;
+    for (int x = threadIdx.x; x < a.k; x += blockDim.x) a.loc[x] = -1;
+    for (int x = threadIdx.x; x <= a.k; x += blockDim.x) a.obj[x] = F;
+    if (threadIdx.x == 0) {
+      DevState *st = a.st;
+      st->t = 0;
+      st->k = a.k;
+      st->done = a.k < 1;
+      st->exhausted = 0;
+      st->skip = 0;
+      st->n_reject = 0;
+      st->pos = 0;
+      st->dec_pending = 0;
+      st->p = -1;
+      st->F = F;
+      st->u2 = 0.0;
+      st->enorm2 = 0.0;
+      st->tau = a.tau;
+      for (int x = 0; x < 16; ++x) st->cnt[x] = 0;
+      *a.ns = 0;
+    }
+  }
+}
+
+// sum over s = gl, gl + 8, ... < t of W[s][i] c[s], then the eight lanes of
+// the group added by a butterfly (every lane of the group gets the same bits)
+__device__ __forceinline__ double group_sum(double v) {
+  v += __shfl_xor(v, 4, kWave);
+  v += __shfl_xor(v, 2, kWave);
+  v += __shfl_xor(v, 1, kWave);
+  return v;
+}
+
+__device__ __forceinline__ double hist_dot(const double *__restrict__ W, int64_t P, int64_t i,
+                                           const double *c, int t, int gl) {
+  double d = 0.0;
+  for (int s = gl; s < t; s += 8) d = fma(W[(int64_t)s * P + i], c[s], d);
+  return group_sum(d);
+}
+
+// One step of the merge selection (see the file comment); grid: ceil(P / 32)
+// workgroups of 256 threads, 8 lanes per candidate.
+__global__ __launch_bounds__(256) void k_merge_step(MergeArgs a) {
+  extern __shared__ double sh[];  // wp (k), upsilon (r), y (k)
+  __shared__ double wred[4];
+  __shared__ double dps;
+  __shared__ double bs[4];
+  __shared__ int64_t bi_s[4];
+  DevState *st = a.st;
+  if (st->done) return;
+  const int t = st->t;
+  const int64_t p = st->p;
+  const double tau = st->tau;
+  const int64_t P = a.P;
+  const int r = a.r;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int grp = threadIdx.x >> 3, gl = threadIdx.x & 7;
+  double *wp = sh, *ups = sh + a.k, *y = ups + r;
+  bool upd = false, rej = false;
+  double un = 0.0, sq = 1.0;
+  const double *Gp = a.GH + (p >= 0 ? p : 0) * a.ldgh;  // row p: G_p., then H_p.
+  if (p >= 0) {
+    for (int s = threadIdx.x; s < t; s += blockDim.x) wp[s] = a.W[(int64_t)s * P + p];
+    __syncthreads();
+    if (grp == 0) {
+      const double d = hist_dot(a.W, P, p, wp, t, gl);
+      if (gl == 0) dps = Gp[p] - d;
+    }
+    __syncthreads();
+    const double dp = dps;
+    if (!(isfinite(dp) && dp > tau * a.g0[p])) {
+      rej = true;
+    } else {
+      upd = true;
+      sq = sqrt(dp);
+      for (int c = threadIdx.x; c < r; c += blockDim.x) {
+        double v = Gp[P + c];
+        for (int s = 0; s < t; ++s) v -= wp[s] * a.U[(int64_t)s * r + c];
+        ups[c] = v / sq;
+      }
+      __syncthreads();
+      // ||upsilon||^2 and y_s = upsilon^(s) . upsilon, fixed orders
+      double q = 0.0;
+      for (int c = threadIdx.x; c < r; c += blockDim.x) q = fma(ups[c], ups[c], q);
+      q = wave_sum(q);
+      if (lane == 0) wred[wave] = q;
+      for (int s = wave; s < t; s += 4) {
+        double v = 0.0;
+        for (int c = lane; c < r; c += 64) v = fma(a.U[(int64_t)s * r + c], ups[c], v);
+        v = wave_sum(v);
+        if (lane == 0) y[s] = v;
+      }
+      __syncthreads();
+      un = ((wred[0] + wred[1]) + wred[2]) + wred[3];
+      if (blockIdx.x == 0)
+        for (int c = threadIdx.x; c < r; c += blockDim.x) a.U[(int64_t)t * r + c] = ups[c];
+    }
+  }
+  // this workgroup's candidates
+  const int64_t i = (int64_t)blockIdx.x * kMergeCPW + grp;
+  double best = -INFINITY;
+  int64_t bi = kNoIdx;
+  if (i < P) {
+    double f = a.f[i], g = a.g[i];
+    const double g0 = a.g0[i];
+    int ex = a.excl[i];
+    if (upd) {
+      const double d = hist_dot(a.W, P, i, wp, t, gl);
+      const double w = (Gp[i] - d) / sq;
+      const double *Hi = a.GH + i * a.ldgh + P;
+      double h1 = 0.0;
+      for (int c = gl; c < r; c += 8) h1 = fma(Hi[c], ups[c], h1);
+      h1 = group_sum(h1);
+      const double h2 = hist_dot(a.W, P, i, y, t, gl);
+      const double hu = h1 - h2;
+      f = f - 2.0 * w * hu + un * w * w;
+      g = g - w * w;
+      if (i == p) ex = 1;
+      if (gl == 0) {
+        a.f[i] = f;
+        a.g[i] = g;
+        a.W[(int64_t)t * P + i] = w;
+        if (i == p) a.excl[i] = 1;
+      }
+    }
+    if (rej && i == p) {
+      ex = 2;
+      if (gl == 0) a.excl[i] = 2;
+    }
+    if (gl == 0 && ex == 0 && g0 > 0.0 && isfinite(f) && isfinite(g) && g > tau * g0) {
+      best = f / g;
+      bi = i;
+    }
+  }
+  wave_argmax(best, bi);
+  if (lane == 0) {
+    bs[wave] = best;
+    bi_s[wave] = bi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double b = bs[0];
+    int64_t x = bi_s[0];
+    for (int w = 1; w < 4; ++w)
+      if (better(bs[w], bi_s[w], b, x)) {
+        b = bs[w];
+        x = bi_s[w];
+      }
+    a.part[blockIdx.x].score = b;
+    a.part[blockIdx.x].idx = x;
+  }
+  if (!last_block_arrive(&st->cnt[0])) return;
+  // last workgroup: the next pick over all workgroups, and this step's record
+  best = -INFINITY;
+  bi = kNoIdx;
+  for (int x = threadIdx.x; x < (int)gridDim.x; x += blockDim.x) {
+    const double s = a.part[x].score;
+    const int64_t ix = a.part[x].idx;
+    if (better(s, ix, best, bi)) {
+      best = s;
+      bi = ix;
+    }
+  }
+  wave_argmax(best, bi);
+  __syncthreads();
+  if (lane == 0) {
+    bs[wave] = best;
+    bi_s[wave] = bi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double b = bs[0];
+    int64_t x = bi_s[0];
+    for (int w = 1; w < 4; ++w)
+      if (better(bs[w], bi_s[w], b, x)) {
+        b = bs[w];
+        x = bi_s[w];
+      }
+    int tn = t;
+    if (upd) {
+      const double F = st->F - un;
+      st->F = F;
+      st->u2 = un;
+      a.obj[t + 1] = F;
+      a.loc[t] = p;
+      tn = t + 1;
+      st->t = tn;
+      *a.ns = tn;
+    }
+    if (rej) st->n_reject += 1;
+    if (tn >= st->k) {
+      st->done = 1;
+    } else if (x == kNoIdx) {
+      st->p = -1;
+      st->exhausted = 1;
+      st->done = 1;
+    } else {
+      st->p = x;
+    }
+    st->cnt[0] = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+size_t merge_gram_lds_bytes(int k, int r) { return (size_t)(2 * k + r) * sizeof(double); }
+
+hipError_t launch_merge_gram(const MergeArgs &a, int dtype, hipStream_t s) {
+  const dim3 tiles((unsigned)((a.P + kMT - 1) / kMT), (unsigned)((a.P + a.r + kMT - 1) / kMT));
+  switch (dtype) {
+    case DT_F32: hipLaunchKernelGGL(k_pool_gh<DT_F32>, tiles, dim3(256), 0, s, a); break;
+    case DT_BF16: hipLaunchKernelGGL(k_pool_gh<DT_BF16>, tiles, dim3(256), 0, s, a); break;
+    case DT_FP8: hipLaunchKernelGGL(k_pool_gh<DT_FP8>, tiles, dim3(256), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e) return e;
+  const int64_t nthr = a.P > a.k + 1 ? a.P : a.k + 1;
+  hipLaunchKernelGGL(k_merge_init, dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+int merge_step_groups(int64_t P) { return (int)((P + kMergeCPW - 1) / kMergeCPW); }
+
+hipError_t launch_merge_step(const MergeArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_merge_step, dim3((unsigned)merge_step_groups(a.P)), dim3(256),
+                     merge_gram_lds_bytes(a.k, a.r), s, a);
+  return hipGetLastError();
+}
+
+}  // namespace gcss
