@@ -19,7 +19,8 @@ the line also carries two legs of the same comparison:
   * "batched": Algorithm 4 on one GPU (m = 1024, 64 column blocks of uneven
     width, one shared B = A Omega with r = 128, 20 picks per block, merge
     of 100), against the same blocks solved one after another, with the
-    roofline of the batched streaming pass and its own CPU baseline.
+    roofline of the batched streaming pass and its own CPU baseline;
+  * "batched_bf16": the same with the matrix stored as bfloat16.
 """
 from __future__ import annotations
 
@@ -643,6 +644,11 @@ def main():
     if legs:
         out["batched"] = run_batched(args, BATCHED, "f32", args.steps, args.warmup,
                                      cpu=not args.no_cpu_baseline)
+        # the same batched workload stored as bfloat16 (its CPU baseline is
+        # the binary32 leg's: the oracle runs on FP64 either way)
+        bb = run_batched(args, BATCHED, "bf16", args.steps, args.warmup, cpu=False)
+        bb["speedup_vs_f32"] = round(out["batched"]["ms_per_step"] / bb["ms_per_step"], 4)
+        out["batched_bf16"] = bb
     line = json.dumps(out)
     print(line, flush=True)
     if args.out:
