@@ -131,8 +131,8 @@ __global__ void k_merge_init(MergeArgs a) {
   }
 }
 
-// sum over s = gl, gl + 8, ... < t of W[s][i] c[s], then the eight lanes of
-// the group added by a butterfly (every lane of the group gets the same bits)
+// The eight lanes of a candidate's group added by a butterfly (every lane of
+// the group gets the same bits).
 __device__ __forceinline__ double group_sum(double v) {
   v += __shfl_xor(v, 4, kWave);
   v += __shfl_xor(v, 2, kWave);
@@ -140,17 +140,45 @@ __device__ __forceinline__ double group_sum(double v) {
   return v;
 }
 
-__device__ __forceinline__ double hist_dot(const double *__restrict__ W, int64_t P, int64_t i,
-                                           const double *c, int t, int gl) {
+constexpr int kMPre = 16;  // history / target entries per lane held in registers
+
+// A lane's share of a candidate's history: W[s][i] for s = gl + 8 u (u <
+// kMPre), loaded at once; later entries are read when used.
+struct HistRow {
+  double v[kMPre];
+};
+
+__device__ __forceinline__ void hist_load(const double *__restrict__ W, int64_t P, int64_t i,
+                                          int t, int gl, HistRow &h) {
+#pragma unroll
+  for (int u = 0; u < kMPre; ++u) {
+    const int s = gl + 8 * u;
+    h.v[u] = s < t ? W[(int64_t)s * P + i] : 0.0;
+  }
+}
+
+// sum over s < t of W[s][i] c[s]: lane gl takes s = gl, gl + 8, ... in order
+// (the first kMPre of them from h), then the group's butterfly
+__device__ __forceinline__ double hist_dot(const HistRow &h, const double *__restrict__ W,
+                                           int64_t P, int64_t i, const double *c, int t,
+                                           int gl) {
   double d = 0.0;
-  for (int s = gl; s < t; s += 8) d = fma(W[(int64_t)s * P + i], c[s], d);
+#pragma unroll
+  for (int u = 0; u < kMPre; ++u) {
+    const int s = gl + 8 * u;
+    if (s < t) d = fma(h.v[u], c[s], d);
+  }
+  for (int s = gl + 8 * kMPre; s < t; s += 8) d = fma(W[(int64_t)s * P + i], c[s], d);
   return group_sum(d);
 }
 
 // One step of the merge selection (see the file comment); grid: ceil(P / 32)
-// workgroups of 256 threads, 8 lanes per candidate.
+// workgroups of 256 threads, 8 lanes per candidate.  Every load that does
+// not depend on this step's upsilon (the candidates' histories, rows of H
+// and G, scores) is issued at the start, so the step costs a few dependent
+// rounds: the pick's history, delta_p, upsilon, its products, the argmax.
 __global__ __launch_bounds__(256) void k_merge_step(MergeArgs a) {
-  extern __shared__ double sh[];  // wp (k), upsilon (r), y (k)
+  extern __shared__ double sh[];  // wp (k), upsilon (r), y (k), upsilon halves (2r)
   __shared__ double wred[4];
   __shared__ double dps;
   __shared__ double bs[4];
@@ -164,15 +192,43 @@ __global__ __launch_bounds__(256) void k_merge_step(MergeArgs a) {
   const int r = a.r;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int grp = threadIdx.x >> 3, gl = threadIdx.x & 7;
-  double *wp = sh, *ups = sh + a.k, *y = ups + r;
+  double *wp = sh, *ups = sh + a.k, *y = ups + r, *uh = y + a.k;
+  const double *Gp = a.GH + (p >= 0 ? p : 0) * a.ldgh;  // row p: G_p., then H_p.
+
+  // this workgroup's candidate (8 lanes each) and its loads
+  const int64_t i = (int64_t)blockIdx.x * kMergeCPW + grp;
+  const int64_t ic = i < P ? i : P - 1;
+  double f = a.f[ic], g = a.g[ic];
+  const double g0 = a.g0[ic];
+  int ex = a.excl[ic];
+  HistRow hw;
+  double hv[kMPre];
+  double gpi = 0.0;
+  if (p >= 0) {
+    hist_load(a.W, P, ic, t, gl, hw);
+    const double *Hi = a.GH + ic * a.ldgh + P;
+#pragma unroll
+    for (int u = 0; u < kMPre; ++u) {
+      const int c = gl + 8 * u;
+      hv[u] = c < r ? Hi[c] : 0.0;
+    }
+    gpi = Gp[ic];
+  }
+
   bool upd = false, rej = false;
   double un = 0.0, sq = 1.0;
-  const double *Gp = a.GH + (p >= 0 ? p : 0) * a.ldgh;  // row p: G_p., then H_p.
   if (p >= 0) {
-    for (int s = threadIdx.x; s < t; s += blockDim.x) wp[s] = a.W[(int64_t)s * P + p];
+    for (int s2 = threadIdx.x; s2 < t; s2 += blockDim.x) wp[s2] = a.W[(int64_t)s2 * P + p];
     __syncthreads();
     if (grp == 0) {
-      const double d = hist_dot(a.W, P, p, wp, t, gl);
+      // delta_p, with the same lanes and order as the candidate p's own delta
+      HistRow hp;
+#pragma unroll
+      for (int u = 0; u < kMPre; ++u) {
+        const int s2 = gl + 8 * u;
+        hp.v[u] = s2 < t ? wp[s2] : 0.0;
+      }
+      const double d = hist_dot(hp, a.W, P, p, wp, t, gl);
       if (gl == 0) dps = Gp[p] - d;
     }
     __syncthreads();
@@ -182,22 +238,47 @@ __global__ __launch_bounds__(256) void k_merge_step(MergeArgs a) {
     } else {
       upd = true;
       sq = sqrt(dp);
-      for (int c = threadIdx.x; c < r; c += blockDim.x) {
-        double v = Gp[P + c];
-        for (int s = 0; s < t; ++s) v -= wp[s] * a.U[(int64_t)s * r + c];
-        ups[c] = v / sq;
+      // upsilon_c = (H_pc - sum_s U[s][c] wp[s]) / sqrt(delta_p): two threads
+      // per c, each a half of the s range (sixteen loads in flight), halves
+      // added in order
+      const int half = (t + 1) / 2;
+      for (int x = threadIdx.x; x < 2 * r; x += blockDim.x) {
+        const int c = x % r, hh = x / r;
+        const int s0 = hh * half, s1 = hh ? t : half;
+        double v = 0.0;
+        int s2 = s0;
+        for (; s2 + 16 <= s1; s2 += 16) {
+          double uv[16];
+#pragma unroll
+          for (int u = 0; u < 16; ++u) uv[u] = a.U[(int64_t)(s2 + u) * r + c];
+#pragma unroll
+          for (int u = 0; u < 16; ++u) v = fma(wp[s2 + u], uv[u], v);
+        }
+        for (; s2 < s1; ++s2) v = fma(wp[s2], a.U[(int64_t)s2 * r + c], v);
+        uh[hh * r + c] = v;
       }
       __syncthreads();
-      // ||upsilon||^2 and y_s = upsilon^(s) . upsilon, fixed orders
+      for (int c = threadIdx.x; c < r; c += blockDim.x) ups[c] = (Gp[P + c] - (uh[c] + uh[r + c])) / sq;
+      __syncthreads();
+      // ||upsilon||^2, and y_s = upsilon^(s) . upsilon by eight lanes per s
       double q = 0.0;
       for (int c = threadIdx.x; c < r; c += blockDim.x) q = fma(ups[c], ups[c], q);
       q = wave_sum(q);
       if (lane == 0) wred[wave] = q;
-      for (int s = wave; s < t; s += 4) {
+      for (int s2 = grp; s2 < t; s2 += blockDim.x / 8) {
+        const double *Us = a.U + (int64_t)s2 * r;
         double v = 0.0;
-        for (int c = lane; c < r; c += 64) v = fma(a.U[(int64_t)s * r + c], ups[c], v);
-        v = wave_sum(v);
-        if (lane == 0) y[s] = v;
+        int c = gl;
+        for (; c + 8 * 7 < r; c += 8 * 8) {
+          double uv[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) uv[u] = Us[c + 8 * u];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) v = fma(uv[u], ups[c + 8 * u], v);
+        }
+        for (; c < r; c += 8) v = fma(Us[c], ups[c], v);
+        v = group_sum(v);
+        if (gl == 0) y[s2] = v;
       }
       __syncthreads();
       un = ((wred[0] + wred[1]) + wred[2]) + wred[3];
@@ -206,21 +287,22 @@ __global__ __launch_bounds__(256) void k_merge_step(MergeArgs a) {
     }
   }
   // this workgroup's candidates
-  const int64_t i = (int64_t)blockIdx.x * kMergeCPW + grp;
   double best = -INFINITY;
   int64_t bi = kNoIdx;
   if (i < P) {
-    double f = a.f[i], g = a.g[i];
-    const double g0 = a.g0[i];
-    int ex = a.excl[i];
     if (upd) {
-      const double d = hist_dot(a.W, P, i, wp, t, gl);
-      const double w = (Gp[i] - d) / sq;
+      const double d = hist_dot(hw, a.W, P, i, wp, t, gl);
+      const double w = (gpi - d) / sq;
       const double *Hi = a.GH + i * a.ldgh + P;
       double h1 = 0.0;
-      for (int c = gl; c < r; c += 8) h1 = fma(Hi[c], ups[c], h1);
+#pragma unroll
+      for (int u = 0; u < kMPre; ++u) {
+        const int c = gl + 8 * u;
+        if (c < r) h1 = fma(hv[u], ups[c], h1);
+      }
+      for (int c = gl + 8 * kMPre; c < r; c += 8) h1 = fma(Hi[c], ups[c], h1);
       h1 = group_sum(h1);
-      const double h2 = hist_dot(a.W, P, i, y, t, gl);
+      const double h2 = hist_dot(hw, a.W, P, i, y, t, gl);
       const double hu = h1 - h2;
       f = f - 2.0 * w * hu + un * w * w;
       g = g - w * w;
@@ -263,10 +345,10 @@ __global__ __launch_bounds__(256) void k_merge_step(MergeArgs a) {
   best = -INFINITY;
   bi = kNoIdx;
   for (int x = threadIdx.x; x < (int)gridDim.x; x += blockDim.x) {
-    const double s = a.part[x].score;
+    const double sc = a.part[x].score;
     const int64_t ix = a.part[x].idx;
-    if (better(s, ix, best, bi)) {
-      best = s;
+    if (better(sc, ix, best, bi)) {
+      best = sc;
       bi = ix;
     }
   }
@@ -311,7 +393,7 @@ __global__ __launch_bounds__(256) void k_merge_step(MergeArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-size_t merge_gram_lds_bytes(int k, int r) { return (size_t)(2 * k + r) * sizeof(double); }
+size_t merge_gram_lds_bytes(int k, int r) { return (size_t)(2 * k + 3 * r) * sizeof(double); }
 
 hipError_t launch_merge_gram(const MergeArgs &a, int dtype, hipStream_t s) {
   const dim3 tiles((unsigned)((a.P + kMT - 1) / kMT), (unsigned)((a.P + a.r + kMT - 1) / kMT));
