@@ -432,8 +432,11 @@ gcss_status gcss_read_state(gcss_ctx *h, int32_t item, void *host, size_t bytes,
  * instead of replaying its graph; the graph-replayed gcss_select_async is not
  * instrumented. */
 typedef struct {
-  int64_t stream_launches;  /* fused streaming passes (step 4 of the loop) timed */
-  double stream_ms;         /* their summed duration, milliseconds                */
+  int64_t stream_launches;  /* fused streaming passes (step 4 of the loop) timed  */
+  double stream_ms;         /* their summed duration, milliseconds; passes that
+                               read no column (after the last pick, a rescore
+                               after a rejected pick: under a quarter of the
+                               longest pass of the call) are not counted        */
   int64_t selects;          /* gcss_select calls timed                            */
   double loop_ms;           /* summed duration of their k-step loops, ms          */
 } gcss_profile;
