@@ -415,6 +415,14 @@ def run_batched(args, name, dtype, steps, warmup, cpu=True):
     t2 = time.perf_counter()
     ms_b = (t1 - t0) / steps * 1e3
     ms_s = (t2 - t1) / steps * 1e3
+    # the selection alone (both phases of Algorithm 4, target already set)
+    sel.project_target(Om)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    for _ in range(steps):
+        sel.select_batched(off, kb, km)
+    torch.cuda.synchronize()
+    ms_loop = (time.perf_counter() - t3) / steps * 1e3
     # the batched streaming pass's duration: the same call with event timing,
     # which enqueues the block loop directly instead of replaying its graph
     sel.profile(True)
@@ -457,6 +465,8 @@ def run_batched(args, name, dtype, steps, warmup, cpu=True):
                    "k_merge": km, "target": f"B = A Omega, r = {r}", "a_storage": dtype},
         "roofline": roof,
         "roofline_note": "event-timed in profiled calls right after the timed ones",
+        "loop_only": {"score_updates_per_s": updates / (ms_loop / 1e3), "ms": round(ms_loop, 3),
+                      "what": "gcss_select_batched alone (block phase and merge), target set"},
         "tuning": tuning,
         "naive_distributed": naive,
         "block_sequential": {"ms_per_step": round(ms_s, 3),

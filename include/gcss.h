@@ -433,10 +433,13 @@ gcss_status gcss_read_state(gcss_ctx *h, int32_t item, void *host, size_t bytes,
  * instrumented. */
 typedef struct {
   int64_t stream_launches;  /* fused streaming passes (step 4 of the loop) timed  */
-  double stream_ms;         /* their summed duration, milliseconds; passes that
-                               read no column (after the last pick, a rescore
-                               after a rejected pick: under a quarter of the
-                               longest pass of the call) are not counted        */
+  double stream_ms;         /* their summed duration, milliseconds.  Passes that
+                               read no column are not counted: the pass after
+                               the last pick (explicit target, no embedding;
+                               the last block step of a batched call) is not
+                               timed, and a pass under a quarter of the call's
+                               longest (a rescore after a rejected pick) is
+                               left out                                         */
   int64_t selects;          /* gcss_select calls timed                            */
   double loop_ms;           /* summed duration of their k-step loops, ms          */
 } gcss_profile;

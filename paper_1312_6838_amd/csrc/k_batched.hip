@@ -81,17 +81,22 @@ __global__ __launch_bounds__(256) void k_stream_b(AView A, const GroupEnt *__res
     lane_off[j] = abase + ci * 16;
   }
 
-  for (;;) {
-    if (threadIdx.x == 0) sg_s = (int64_t)atomicAdd(&bcnt[1], 1u);
-    __syncthreads();
-    const int64_t sg = sg_s;
-    __syncthreads();
-    if (sg >= nsuper) break;
+  // super-groups come from a shared counter; the next one is claimed while
+  // the current one's epilogue runs
+  if (threadIdx.x == 0) sg_s = (int64_t)atomicAdd(&bcnt[1], 1u);
+  __syncthreads();
+  int64_t sg = sg_s;
+  while (sg < nsuper) {
     const int64_t grp = sg * TEAMS + team;
     int ncol = 0, blk = 0;
     int64_t col0 = 0;
     bool live = false, rescore = true;
     double u2 = 0.0, tau = 0.0;
+    // the epilogue's inputs, loaded before the stream loads (clamped column,
+    // unconditional: waiting for the stream then never waits for these)
+    double fv = 0.0, gv = 0.0, g0v = 0.0;
+    float scv = 1.f;
+    int mk = 1;
     if (grp < ngroups) {
       const GroupEnt ge = groups[grp];
       col0 = ge.col0;
@@ -102,6 +107,14 @@ __global__ __launch_bounds__(256) void k_stream_b(AView A, const GroupEnt *__res
       rescore = score_only || st->skip;
       u2 = st->u2;
       tau = st->tau;
+      if (ws == 0) {
+        const int64_t colc = col0 + (lane < ncol ? lane : 0);
+        fv = f[colc];
+        gv = g[colc];
+        g0v = g0[colc];
+        mk = mask[colc];
+        if constexpr (DT == DT_FP8) scv = A.scale[colc];
+      }
     }
     float mw = 0.f, mz = 0.f;
     if (live && !rescore) {
@@ -176,6 +189,9 @@ __global__ __launch_bounds__(256) void k_stream_b(AView A, const GroupEnt *__res
           for (int j = 0; j < NJ; ++j) cur[u][j] = nxt[u][j];
       }
     }
+    // every thread has read sg_s: claim the next super-group
+    __syncthreads();
+    if (threadIdx.x == 0) sg_s = (int64_t)atomicAdd(&bcnt[1], 1u);
     if constexpr (W > 1) {
       red[0][wave][lane] = mw;
       red[1][wave][lane] = mz;
@@ -197,16 +213,15 @@ __global__ __launch_bounds__(256) void k_stream_b(AView A, const GroupEnt *__res
       int64_t besti = kNoIdx;
       if (live && lane < ncol) {
         const int64_t col = col0 + lane;
-        double fv = f[col], gv = g[col];
         if (!rescore) {
-          const double s = (DT == DT_FP8) ? (double)A.scale[col] : 1.0;
+          const double s = (double)scv;
           const double w = s * (double)mw, y = s * (double)mz;
           fv = fv - 2.0 * w * y + u2 * w * w;
           gv = gv - w * w;
           f[col] = fv;
           g[col] = gv;
         }
-        if (mask[col] == 0 && gv > tau * g0[col] && isfinite(fv) && isfinite(gv)) {
+        if (mk == 0 && gv > tau * g0v && isfinite(fv) && isfinite(gv)) {
           best = fv / gv;
           besti = col;
         }
@@ -217,6 +232,8 @@ __global__ __launch_bounds__(256) void k_stream_b(AView A, const GroupEnt *__res
         gpart[grp].idx = besti;
       }
     }
+    __syncthreads();
+    sg = sg_s;
   }
   if (!last_block_arrive(&bcnt[0])) return;
   if (threadIdx.x == 0) {
