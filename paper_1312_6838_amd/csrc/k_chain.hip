@@ -37,7 +37,7 @@
 
 namespace gcss {
 
-constexpr int kDotRows = 1024;  // rows per block of the dot kernels (4 per thread)
+constexpr int kDotRows = 1024;  // rows per block of the dot kernels (4 consecutive per thread)
 constexpr int kDotCols = 4;     // columns per dot workgroup
 constexpr int kMaxRB = 8;       // row blocks of the dot kernels (m <= 8192)
 constexpr int kRowRB = 32;      // rows per row-kernel workgroup
@@ -76,6 +76,29 @@ __device__ __forceinline__ double block_sum(double v, double *wsum) {
   return s;
 }
 
+// Four consecutive elements as doubles (p aligned to four elements).
+__device__ __forceinline__ void load_quad(const float *p, double (&o)[4]) {
+  const float4 v = *(const float4 *)p;
+  o[0] = v.x;
+  o[1] = v.y;
+  o[2] = v.z;
+  o[3] = v.w;
+}
+__device__ __forceinline__ void load_quad(const uint16_t *p, double (&o)[4]) {  // bfloat16
+  const uint2 w = *(const uint2 *)p;
+  o[0] = (double)__uint_as_float(w.x << 16);
+  o[1] = (double)__uint_as_float(w.x & 0xFFFF0000u);
+  o[2] = (double)__uint_as_float(w.y << 16);
+  o[3] = (double)__uint_as_float(w.y & 0xFFFF0000u);
+}
+__device__ __forceinline__ void load_quad(const double *p, double (&o)[4]) {
+  const double2 a = *(const double2 *)p, b = *(const double2 *)(p + 2);
+  o[0] = a.x;
+  o[1] = a.y;
+  o[2] = b.x;
+  o[3] = b.y;
+}
+
 // P[y * lp + c] = sum over rows j of block y of M_c[j] * x[j] for c < ncols,
 // ncols = nfix + t: column c < nfix is column c of M1 (type T1, ld ld1; the
 // target B, or C for B = A), column c >= nfix is column c - nfix of M2 (FP64,
@@ -99,24 +122,22 @@ __global__ __launch_bounds__(256) void k_dots(const T1 *__restrict__ M1, int64_t
   const int ncols = nfix + st->t;
   const int c0 = blockIdx.x * kDotCols;
   if (c0 >= ncols) return;
-  const int64_t j0 = (int64_t)blockIdx.y * kDotRows + threadIdx.x;
+  // four consecutive rows per thread (one 16- or 32-byte load per column);
+  // a quad past m reads the last quad of the column (every leading
+  // dimension is a multiple of four elements) and its terms are dropped
+  const int64_t jq = (int64_t)blockIdx.y * kDotRows + 4 * threadIdx.x;
+  const int64_t jb = jq < m ? jq : (m - 1) & ~(int64_t)3;
   double xv[4];
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int64_t j = j0 + 256 * u;
-    xv[u] = j < m ? x[j] : 0.0;
-  }
+  load_quad(x + jb, xv);
   // every load issued before the first use
   double mv[kDotCols][4];
 #pragma unroll
   for (int c = 0; c < kDotCols; ++c) {
     const int cc = c0 + c < ncols ? c0 + c : ncols - 1;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int64_t j = j0 + 256 * u;
-      const int64_t jj = j < m ? j : m - 1;
-      mv[c][u] = cc < nfix ? to_f64(M1[(int64_t)cc * ld1 + jj]) : M2[(int64_t)(cc - nfix) * ld2 + jj];
-    }
+    if (cc < nfix)
+      load_quad(M1 + (int64_t)cc * ld1 + jb, mv[c]);
+    else
+      load_quad(M2 + (int64_t)(cc - nfix) * ld2 + jb, mv[c]);
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -124,7 +145,7 @@ __global__ __launch_bounds__(256) void k_dots(const T1 *__restrict__ M1, int64_t
     double a = 0.0;
 #pragma unroll
     for (int u = 0; u < 4; ++u)
-      if (j0 + 256 * u < m) a = fma(mv[c][u], xv[u], a);
+      if (jq + u < m) a = fma(mv[c][u], xv[u], a);
     a = wave_sum(a);
     if (lane == 0) red[wave][c] = a;
   }
