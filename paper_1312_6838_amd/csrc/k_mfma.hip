@@ -1449,92 +1449,10 @@ __global__ __launch_bounds__(kG2Threads, 1) void k_proj_x3(AView A, const float 
   const char *abase = (const char *)A.a;
 
   // load task: op 0 -> rows i0 + q0 .. +3 of A, op 1 -> columns j0 + q0 .. +3
-  // of Omega, for k = k0 + k8 .. k0 + k8 + 7
-  const int op = tid >> 8, task = tid & 255;
+  // of Omega, for k = k0 + k8 .. k0 + k8 + 7 (op is the same in a wave:
+  // waves 0-3 load A, waves 4-7 Omega)
+  const int op = __builtin_amdgcn_readfirstlane(tid >> 8), task = tid & 255;
   const int q0 = x3_task_row(task), k8 = x3_task_k(task);
-  // the loads of a stage are kept raw (BF16 / E4M3 codes of A as bits, Omega
-  // and the FP8 column scales unmultiplied) and decoded only when the stage
-  // goes to LDS, so the next stage's loads stay in flight through this
-  // stage's matrix products instead of being waited for where they are issued
-  float4 reg[8];
-  float scl[8];
-  // (m and r are multiples of 4: four rows or columns are in or out together)
-  auto gload = [&](int64_t k0) {
-    const int64_t q = (op == 0 ? i0 : j0) + q0;
-    const bool inq = q < (op == 0 ? m : r);
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int64_t k = k0 + k8 + e;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      float sk = 0.f;
-      if (inq && k < ke) {
-        if (op == 0) {
-          const char *src = abase + (k * A.lda + q) * ES;
-          if constexpr (DT == DT_F32) {
-            v = *(const float4 *)src;
-          } else if constexpr (DT == DT_BF16) {
-            const uint2 w = *(const uint2 *)src;
-            v.x = __uint_as_float(w.x);
-            v.y = __uint_as_float(w.y);
-          } else {
-            v.x = __uint_as_float(*(const uint32_t *)src);
-          }
-        } else {
-          v = *(const float4 *)(Om + k * r + q);
-          if constexpr (DT == DT_FP8) sk = A.scale[k];
-        }
-      }
-      reg[e] = v;
-      scl[e] = sk;
-    }
-  };
-  // element (row / column q0 + rr, k k8 + e) of the stage as a binary32 value
-  auto elem = [&](int e, int rr) -> float {
-    const float4 v = reg[e];
-    if (op == 0) {
-      if constexpr (DT == DT_BF16) {
-        const uint32_t w = __float_as_uint(rr < 2 ? v.x : v.y);
-        return (rr & 1) ? bf16_hi(w) : bf16_lo(w);
-      } else if constexpr (DT == DT_FP8) {
-        float d[4];
-        fp8x4_decode(__float_as_uint(v.x), d);
-        return d[rr];
-      }
-    }
-    const float x = rr == 0 ? v.x : rr == 1 ? v.y : rr == 2 ? v.z : v.w;
-    if constexpr (DT == DT_FP8)
-      if (op == 1) return x * scl[e];
-    return x;
-  };
-  auto lstore = [&]() {
-#pragma unroll
-    for (int rr = 0; rr < 4; ++rr) {
-      float x[8];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) x[e] = elem(e, rr);
-      const int off = (q0 + rr) * kX3RP + k8;
-      if (op == 1 || AP == 3) {
-        bf16x8 h, md, lo;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          __bf16 xh, xm, xl;
-          split3(x[e], xh, xm, xl);
-          h[e] = xh;
-          md[e] = xm;
-          lo[e] = xl;
-        }
-        __bf16 *base = op == 0 ? &La[0][0] : &Lo[0][0];
-        *(bf16x8 *)(base + off) = h;
-        *(bf16x8 *)(base + kX3Plane + off) = md;
-        *(bf16x8 *)(base + 2 * kX3Plane + off) = lo;
-      } else {
-        bf16x8 h;  // BF16 and E4M3 values are bfloat16 numbers
-#pragma unroll
-        for (int e = 0; e < 8; ++e) h[e] = (__bf16)x[e];
-        *(bf16x8 *)(&La[0][off]) = h;
-      }
-    }
-  };
 
   f32x4 acc[8][4];
 #pragma unroll
@@ -1544,12 +1462,8 @@ __global__ __launch_bounds__(kG2Threads, 1) void k_proj_x3(AView A, const float 
   const int wr = (wave >> 2) * 128, wc = (wave & 3) * 64;
   const int lr = lane & 15, kq = (lane >> 4) * 8;
 
-  if (kb < ke) gload(kb);
-  for (int64_t k0 = kb; k0 < ke; k0 += kX3BK) {
-    __syncthreads();  // the previous stage's operands are consumed
-    lstore();
-    __syncthreads();
-    if (k0 + kX3BK < ke) gload(k0 + kX3BK);
+  // the matrix products of one stage from the LDS planes
+  auto mma = [&]() {
     bf16x8 b[4][3];
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb)
@@ -1577,7 +1491,123 @@ __global__ __launch_bounds__(kG2Threads, 1) void k_proj_x3(AView A, const float 
         acc[rb][nb] = c;
       }
     }
-  }
+  };
+
+  // The k loop, one instance per load role (a wave runs its role's): the
+  // registers a stage is loaded into then belong to one role only, so the
+  // compiler neither merges nor copies them, and a stage's loads stay in
+  // flight until the LDS store that consumes them.  Both instances pass the
+  // same barriers.
+  auto run = [&](auto role) {
+    constexpr int OP = decltype(role)::value;
+    // 32-bit words per loaded element: four binary32 values, or four BF16 /
+    // E4M3 codes of A
+    constexpr int LW = (OP == 1 || DT == DT_F32) ? 4 : (DT == DT_BF16 ? 2 : 1);
+    // the loads of a stage are kept raw (codes of A as bits, Omega and the
+    // FP8 column scales unmultiplied) and decoded only when the stage goes to
+    // LDS, so the next stage's loads stay in flight through this stage's
+    // matrix products instead of being waited for where they are issued
+    uint32_t reg[8][LW];
+    float scl[8];
+    uint32_t okm = 0;  // bit e: element e of the stage is inside the chunk and the matrix
+    // Addresses: a base shared by the wave (the stage's first k) plus a 32-bit
+    // lane offset formed just before each load (the host keeps 32 columns of
+    // A and 32 rows of Omega within 2^31 bytes), so no 64-bit address per
+    // element stays live across the matrix products.  Rows or columns past
+    // the edge and k past the chunk load a clamped in-range element, zeroed
+    // when the stage goes to LDS (m and r are multiples of 4: four rows or
+    // columns are in or out together).
+    const int64_t qn = OP == 0 ? m : r;
+    const int64_t qg = (OP == 0 ? i0 : j0) + q0;
+    const bool inq = qg < qn;
+    const uint32_t qoff = (uint32_t)(inq ? qg : qn - 4);
+    const uint32_t colb = OP == 0 ? (uint32_t)(A.lda * ES) : (uint32_t)(r * 4);  // bytes per k
+    const uint32_t qb = qoff * (OP == 0 ? (uint32_t)ES : 4u);
+    const char *src0 = OP == 0 ? abase : (const char *)Om;
+    auto gload = [&](int64_t k0) {
+      const int64_t kleft = ke - k0;  // > 0
+      const char *base = src0 + k0 * (int64_t)colb;
+      okm = 0;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int kk = k8 + e;
+        const int kc = kk < kleft ? kk : (int)kleft - 1;
+        const char *src = base + ((uint32_t)kc * colb + qb);
+        if constexpr (LW == 4) {
+          const uint4 v = *(const uint4 *)src;
+          reg[e][0] = v.x;
+          reg[e][1] = v.y;
+          reg[e][2] = v.z;
+          reg[e][3] = v.w;
+        } else if constexpr (LW == 2) {
+          const uint2 v = *(const uint2 *)src;
+          reg[e][0] = v.x;
+          reg[e][1] = v.y;
+        } else {
+          reg[e][0] = *(const uint32_t *)src;
+        }
+        if constexpr (OP == 1 && DT == DT_FP8) scl[e] = A.scale[k0 + kc];
+        okm |= (uint32_t)(inq && kk < kleft) << e;
+      }
+    };
+    // element (row / column q0 + rr, k k8 + e) of the stage as a binary32 value
+    auto elem = [&](int e, int rr) -> float {
+      if constexpr (OP == 0 && DT == DT_BF16) {
+        const uint32_t w = reg[e][rr >> 1];
+        return (rr & 1) ? bf16_hi(w) : bf16_lo(w);
+      } else if constexpr (OP == 0 && DT == DT_FP8) {
+        float d[4];
+        fp8x4_decode(reg[e][0], d);
+        return d[rr];
+      } else {
+        const float x = __uint_as_float(reg[e][rr]);
+        if constexpr (OP == 1 && DT == DT_FP8) return x * scl[e];
+        return x;
+      }
+    };
+    auto lstore = [&]() {
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        float x[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) x[e] = (okm >> e) & 1 ? elem(e, rr) : 0.f;
+        const int off = (q0 + rr) * kX3RP + k8;
+        if constexpr (OP == 1 || AP == 3) {
+          bf16x8 h, md, lo;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            __bf16 xh, xm, xl;
+            split3(x[e], xh, xm, xl);
+            h[e] = xh;
+            md[e] = xm;
+            lo[e] = xl;
+          }
+          __bf16 *base = OP == 0 ? &La[0][0] : &Lo[0][0];
+          *(bf16x8 *)(base + off) = h;
+          *(bf16x8 *)(base + kX3Plane + off) = md;
+          *(bf16x8 *)(base + 2 * kX3Plane + off) = lo;
+        } else {
+          bf16x8 h;  // BF16 and E4M3 values are bfloat16 numbers
+#pragma unroll
+          for (int e = 0; e < 8; ++e) h[e] = (__bf16)x[e];
+          *(bf16x8 *)(&La[0][off]) = h;
+        }
+      }
+    };
+
+    if (kb < ke) gload(kb);
+    for (int64_t k0 = kb; k0 < ke; k0 += kX3BK) {
+      __syncthreads();  // the previous stage's operands are consumed
+      lstore();
+      __syncthreads();
+      if (k0 + kX3BK < ke) gload(k0 + kX3BK);
+      mma();
+    }
+  };
+  if (op == 0)
+    run(std::integral_constant<int, 0>{});
+  else
+    run(std::integral_constant<int, 1>{});
 #pragma unroll
   for (int nb = 0; nb < 4; ++nb) {
     const int64_t j = j0 + wc + 16 * nb + lr;
@@ -2225,7 +2255,11 @@ hipError_t launch_project(const AView &A, const float *omega, int64_t r, float *
   const int64_t kc = pl.kchunk;
   const dim3 grid((unsigned)(nt * sp));
   if (pl.tile == 256) {
-    if (mfma_x3() && A.m % 4 == 0 && r % 4 == 0) {
+    // (k_proj_x3 forms its load addresses as 32-bit offsets from the stage's
+    // first k: 32 columns of A and 32 rows of Omega must span under 2^31 bytes)
+    const int64_t es = A.dtype == DT_F32 ? 4 : A.dtype == DT_BF16 ? 2 : 1;
+    const bool off32 = 32 * A.lda * es < (1LL << 31) && 32 * r * 4 < (1LL << 31);
+    if (mfma_x3() && A.m % 4 == 0 && r % 4 == 0 && off32) {
       switch (A.dtype) {
         case DT_F32: hipLaunchKernelGGL(k_proj_x3<DT_F32>, grid, dim3(kG2Threads), 0, s, A, omega, r, P, ldp, tm, nt, kc); break;
         case DT_BF16: hipLaunchKernelGGL(k_proj_x3<DT_BF16>, grid, dim3(kG2Threads), 0, s, A, omega, r, P, ldp, tm, nt, kc); break;
