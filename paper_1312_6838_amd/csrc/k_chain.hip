@@ -51,11 +51,12 @@ __device__ __forceinline__ double to_f64(T v) {
   else return (double)v;
 }
 
-// sum over y < nrb (in order) of P[y * lp + c]: all loads in flight at once.
+// sum over y < nrb (in order) of P[y * lp + c]: all loads in flight at once
+// (unconditional: y >= nrb reads row nrb - 1 again, nrb >= 1).
 __device__ __forceinline__ double psum(const double *P, int64_t lp, int nrb, int64_t c) {
   double v[kMaxRB];
 #pragma unroll
-  for (int y = 0; y < kMaxRB; ++y) v[y] = y < nrb ? P[(int64_t)y * lp + c] : 0.0;
+  for (int y = 0; y < kMaxRB; ++y) v[y] = P[(int64_t)(y < nrb ? y : nrb - 1) * lp + c];
   double s = 0.0;
 #pragma unroll
   for (int y = 0; y < kMaxRB; ++y)
@@ -76,33 +77,99 @@ __device__ __forceinline__ double block_sum(double v, double *wsum) {
   return s;
 }
 
-// Four consecutive elements as doubles (p aligned to four elements).
-__device__ __forceinline__ void load_quad(const float *p, double (&o)[4]) {
-  const float4 v = *(const float4 *)p;
-  o[0] = v.x;
-  o[1] = v.y;
-  o[2] = v.z;
-  o[3] = v.w;
+// Raw loads of four consecutive elements (p aligned to four elements), kept
+// as loaded until raw_f64 turns them into doubles.
+template <typename T> struct Quad;
+template <> struct Quad<float> { float4 v; };
+template <> struct Quad<uint16_t> { uint2 v; };  // bfloat16
+template <> struct Quad<double> { double2 a, b; };
+__device__ __forceinline__ void raw_load(const float *p, Quad<float> &q) { q.v = *(const float4 *)p; }
+__device__ __forceinline__ void raw_load(const uint16_t *p, Quad<uint16_t> &q) { q.v = *(const uint2 *)p; }
+__device__ __forceinline__ void raw_load(const double *p, Quad<double> &q) {
+  q.a = *(const double2 *)p;
+  q.b = *(const double2 *)(p + 2);
 }
-__device__ __forceinline__ void load_quad(const uint16_t *p, double (&o)[4]) {  // bfloat16
-  const uint2 w = *(const uint2 *)p;
-  o[0] = (double)__uint_as_float(w.x << 16);
-  o[1] = (double)__uint_as_float(w.x & 0xFFFF0000u);
-  o[2] = (double)__uint_as_float(w.y << 16);
-  o[3] = (double)__uint_as_float(w.y & 0xFFFF0000u);
+__device__ __forceinline__ void raw_f64(const Quad<float> &q, double (&o)[4]) {
+  o[0] = q.v.x;
+  o[1] = q.v.y;
+  o[2] = q.v.z;
+  o[3] = q.v.w;
 }
-__device__ __forceinline__ void load_quad(const double *p, double (&o)[4]) {
-  const double2 a = *(const double2 *)p, b = *(const double2 *)(p + 2);
-  o[0] = a.x;
-  o[1] = a.y;
-  o[2] = b.x;
-  o[3] = b.y;
+__device__ __forceinline__ void raw_f64(const Quad<uint16_t> &q, double (&o)[4]) {
+  o[0] = (double)__uint_as_float(q.v.x << 16);
+  o[1] = (double)__uint_as_float(q.v.x & 0xFFFF0000u);
+  o[2] = (double)__uint_as_float(q.v.y << 16);
+  o[3] = (double)__uint_as_float(q.v.y & 0xFFFF0000u);
+}
+__device__ __forceinline__ void raw_f64(const Quad<double> &q, double (&o)[4]) {
+  o[0] = q.a.x;
+  o[1] = q.a.y;
+  o[2] = q.b.x;
+  o[3] = q.b.y;
+}
+
+// The partial dots of one workgroup: P[y * lp + c] for its kDotCols columns
+// c0 .. (< cend) of one matrix M (type T, ld ldm, column c - cbase), rows of
+// block y.  Every load (the column quads, then x) is issued before the first
+// is used.
+template <typename T>
+__device__ __forceinline__ void dots_block(const T *__restrict__ M, int64_t ldm, int cbase, int c0,
+                                           int cend, const double *__restrict__ x, int64_t m,
+                                           double *__restrict__ P, int64_t lp,
+                                           double (&red)[4][kDotCols]) {
+  // four consecutive rows per thread (one 16- or 32-byte load per column);
+  // a quad past m reads the last quad of the column (every leading
+  // dimension is a multiple of four elements) and its terms are dropped
+  const int64_t jq = (int64_t)blockIdx.y * kDotRows + 4 * threadIdx.x;
+  const int64_t jb = jq < m ? jq : (m - 1) & ~(int64_t)3;
+  Quad<T> raw[kDotCols];
+#pragma unroll
+  for (int c = 0; c < kDotCols; ++c) {
+    const int cc = c0 + c < cend ? c0 + c : cend - 1;
+    raw_load(M + (int64_t)(cc - cbase) * ldm + jb, raw[c]);
+  }
+  Quad<double> xq;
+  raw_load(x + jb, xq);
+  double xv[4];
+  raw_f64(xq, xv);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // (a row block wholly inside m uses every term unconditionally, so no load
+  // is moved under a condition)
+  const bool full = (int64_t)(blockIdx.y + 1) * kDotRows <= m;
+#pragma unroll
+  for (int c = 0; c < kDotCols; ++c) {
+    double mv[4];
+    raw_f64(raw[c], mv);
+    double a = 0.0;
+    if (full) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a = fma(mv[u], xv[u], a);
+    } else {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (jq + u < m) a = fma(mv[u], xv[u], a);
+    }
+    a = wave_sum(a);
+    if (lane == 0) red[wave][c] = a;
+  }
+  __syncthreads();
+  if (threadIdx.x < kDotCols && c0 + (int)threadIdx.x < cend) {
+    const int c = threadIdx.x;
+    P[(int64_t)blockIdx.y * lp + c0 + c] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+  }
+}
+
+// Number of column workgroups of k_dots: the columns of M1 and those of M2
+// are never mixed in one workgroup.
+inline int dots_col_blocks(int nfix, int kmax) {
+  return (nfix + kDotCols - 1) / kDotCols + (kmax + kDotCols - 1) / kDotCols;
 }
 
 // P[y * lp + c] = sum over rows j of block y of M_c[j] * x[j] for c < ncols,
 // ncols = nfix + t: column c < nfix is column c of M1 (type T1, ld ld1; the
 // target B, or C for B = A), column c >= nfix is column c - nfix of M2 (FP64,
-// ld ld2).
+// ld ld2).  Workgroups x < ceil(nfix / 4) take four columns of M1 each, the
+// rest four columns of M2.
 template <typename T1>
 __global__ __launch_bounds__(256) void k_dots(const T1 *__restrict__ M1, int64_t ld1, int nfix,
                                               const double *__restrict__ M2, int64_t ld2,
@@ -120,39 +187,32 @@ __global__ __launch_bounds__(256) void k_dots(const T1 *__restrict__ M1, int64_t
   }
   if (st->done || st->skip) return;
   const int ncols = nfix + st->t;
-  const int c0 = blockIdx.x * kDotCols;
-  if (c0 >= ncols) return;
-  // four consecutive rows per thread (one 16- or 32-byte load per column);
-  // a quad past m reads the last quad of the column (every leading
-  // dimension is a multiple of four elements) and its terms are dropped
-  const int64_t jq = (int64_t)blockIdx.y * kDotRows + 4 * threadIdx.x;
-  const int64_t jb = jq < m ? jq : (m - 1) & ~(int64_t)3;
-  double xv[4];
-  load_quad(x + jb, xv);
-  // every load issued before the first use
-  double mv[kDotCols][4];
-#pragma unroll
-  for (int c = 0; c < kDotCols; ++c) {
-    const int cc = c0 + c < ncols ? c0 + c : ncols - 1;
-    if (cc < nfix)
-      load_quad(M1 + (int64_t)cc * ld1 + jb, mv[c]);
-    else
-      load_quad(M2 + (int64_t)(cc - nfix) * ld2 + jb, mv[c]);
+  const int nb1 = (nfix + kDotCols - 1) / kDotCols;
+  if ((int)blockIdx.x < nb1) {
+    dots_block(M1, ld1, 0, (int)blockIdx.x * kDotCols, nfix, x, m, P, lp, red);
+  } else {
+    const int c0 = nfix + ((int)blockIdx.x - nb1) * kDotCols;
+    if (c0 >= ncols) return;
+    dots_block(M2, ld2, nfix, c0, ncols, x, m, P, lp, red);
   }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+}
+
+// Loads of one round of a thread's row sum: M[j + s ld] for the columns
+// s = s0 + 32 u (u < kRowU), raw, all issued before any is used; a column
+// s >= ns reads column ns - 1 instead, and is dropped by the caller (ns <= 0:
+// nothing is read).
+template <typename T>
+__device__ __forceinline__ void row_loads(const T *__restrict__ col0, int64_t ld, int s0, int ns,
+                                          T (&raw)[kRowU]) {
+  if (ns <= 0) {  // (the same in the whole workgroup)
 #pragma unroll
-  for (int c = 0; c < kDotCols; ++c) {
-    double a = 0.0;
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (jq + u < m) a = fma(mv[c][u], xv[u], a);
-    a = wave_sum(a);
-    if (lane == 0) red[wave][c] = a;
+    for (int u = 0; u < kRowU; ++u) raw[u] = T(0);
+    return;
   }
-  __syncthreads();
-  if (threadIdx.x < kDotCols && c0 + (int)threadIdx.x < ncols) {
-    const int c = threadIdx.x;
-    P[(int64_t)blockIdx.y * lp + c0 + c] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+#pragma unroll
+  for (int u = 0; u < kRowU; ++u) {
+    const int s = s0 + kRowGroups * u;
+    raw[u] = col0[(int64_t)(s < ns ? s : ns - 1) * ld];
   }
 }
 
@@ -169,30 +229,32 @@ __device__ __forceinline__ double row_sum(const T *__restrict__ col0, int64_t ld
     if (s < ns) acc = fma(pre[u], c[s], acc);
   }
   for (int s0 = g + kRowGroups * kRowU; s0 < ns; s0 += kRowGroups * kRowU) {
-    double x[kRowU];
+    T raw[kRowU];
+    row_loads(col0, ld, s0, ns, raw);
 #pragma unroll
     for (int u = 0; u < kRowU; ++u) {
       const int s = s0 + kRowGroups * u;
-      x[u] = s < ns ? to_f64(col0[(int64_t)s * ld]) : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < kRowU; ++u) {
-      const int s = s0 + kRowGroups * u;
-      if (s < ns) acc = fma(x[u], c[s], acc);
+      if (s < ns) acc = fma(to_f64(raw[u]), c[s], acc);
     }
   }
   return acc;
 }
 
-// The first kRowU values of a thread's row sum (columns g + 32 u < ns).
+// The first kRowU values of a thread's row sum (columns g + 32 u < ns; the
+// others 0).  The loads are unconditional (clamped columns), so they are all
+// in flight together instead of each waited for inside its own branch.
+template <typename T>
+__device__ __forceinline__ void row_convert(const T (&raw)[kRowU], int g, int ns,
+                                            double (&pre)[kRowU]) {
+#pragma unroll
+  for (int u = 0; u < kRowU; ++u) pre[u] = g + kRowGroups * u < ns ? to_f64(raw[u]) : 0.0;
+}
 template <typename T>
 __device__ __forceinline__ void row_preload(const T *__restrict__ col0, int64_t ld, int g, int ns,
                                             double (&pre)[kRowU]) {
-#pragma unroll
-  for (int u = 0; u < kRowU; ++u) {
-    const int s = g + kRowGroups * u;
-    pre[u] = s < ns ? to_f64(col0[(int64_t)s * ld]) : 0.0;
-  }
+  T raw[kRowU];
+  row_loads(col0, ld, g, ns, raw);
+  row_convert(raw, g, ns, pre);
 }
 
 // out = v - Q c for this workgroup's 32 rows, c[s] = sum_y P[y * lp + s]
@@ -304,11 +366,12 @@ __global__ __launch_bounds__(1024) void k_rows_z(ZArgs za, DevState *st) {
   const int64_t j0 = (int64_t)blockIdx.x * kRowRB;
   const int64_t j = j0 + rr;
   const int64_t jc = j < m ? j : m - 1;
-  // every load of the kernel at once: rows of B and Q, e2, the norm partials,
-  // the coefficient partials
-  double bpre[kRowU], qpre[kRowU];
-  if constexpr (!GRAM) row_preload((const TB *)za.B + jc, za.ldb, g, r, bpre);
-  row_preload(za.Q + jc, za.ldq, g, t, qpre);
+  // every load of the kernel at once: rows of B and Q (kept raw until the
+  // row sums), e2, the norm partials, the coefficient partials
+  TB braw[kRowU];
+  double qraw[kRowU];
+  row_loads(za.Q + jc, za.ldq, g, t, qraw);
+  if constexpr (!GRAM) row_loads((const TB *)za.B + jc, za.ldb, g, r, braw);
   const double e2j = za.e2[jc];
   double pn = 0.0;
   for (int x = threadIdx.x; x < za.npn; x += kRowThreads) pn += za.Pn[x];
@@ -335,7 +398,12 @@ __global__ __launch_bounds__(1024) void k_rows_z(ZArgs za, DevState *st) {
   for (int s = threadIdx.x; s < t; s += kRowThreads) c3[s] *= inv;
   __syncthreads();
   // w = B upsilon and Q c3 for this workgroup's rows
-  if constexpr (!GRAM) redw[g][rr] = row_sum((const TB *)za.B + jc, za.ldb, g, r, bpre, ups);
+  double bpre[kRowU], qpre[kRowU];
+  if constexpr (!GRAM) {
+    row_convert(braw, g, r, bpre);
+    redw[g][rr] = row_sum((const TB *)za.B + jc, za.ldb, g, r, bpre, ups);
+  }
+  row_convert(qraw, g, t, qpre);
   redz[g][rr] = row_sum(za.Q + jc, za.ldq, g, t, qpre, c3);
   __syncthreads();
   if (threadIdx.x < 64) {
@@ -584,7 +652,7 @@ hipError_t launch_chain(const ChainArgs &ca, hipStream_t s) {
   const int64_t m = ca.m;
   const int nrb = chain_row_blocks(m), nrg = chain_row_groups(m);
   if (nrb > kMaxRB) return hipErrorInvalidValue;
-  const unsigned qdots = (unsigned)((ca.kmax + kDotCols - 1) / kDotCols);
+  const unsigned qdots = (unsigned)dots_col_blocks(0, ca.kmax);
   const size_t lds_t = (size_t)(ca.kmax + 1) * sizeof(double);
   const unsigned np = (unsigned)(ca.nprob > 0 ? ca.nprob : 1);
   // K1: c1 partials
@@ -605,7 +673,7 @@ hipError_t launch_chain(const ChainArgs &ca, hipStream_t s) {
                      ca.s_p, ca.s_pn);
   // K5: [B^T e2 ; V^T e2] partials (B = A: [C e2 ; V^T e2])
   const int nfix = ca.gram ? (int)m : (int)ca.r;
-  const unsigned tdots = (unsigned)((nfix + ca.kmax + kDotCols - 1) / kDotCols);
+  const unsigned tdots = (unsigned)dots_col_blocks(nfix, ca.kmax);
   if (ca.b_bf16 && !ca.gram)
     hipLaunchKernelGGL((k_dots<uint16_t>), dim3(tdots, nrb, np), dim3(256), 0, s,
                        (const uint16_t *)ca.B, ca.ldb, nfix, ca.V, ca.ldq, ca.e2, m, ca.P, ca.lp,
