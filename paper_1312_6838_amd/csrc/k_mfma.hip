@@ -632,21 +632,26 @@ __global__ __launch_bounds__(kI2Threads, 1) void k_init256(const float *__restri
 // part products; the FP8 column scale enters f and g at the end).  X rows
 // and A columns both hold k contiguously, so a thread loads eight
 // consecutive k of one row or column and writes each plane with one 16-byte
-// LDS store.  One workgroup per 256 columns of A, all row chunks.
-template <bool TRI, int DT>
+// LDS store.  One workgroup per 256 columns of A, all row chunks of RT rows
+// of X: 256 (eight waves of 128 x 64), or 128 for narrow targets (R <= 128:
+// eight waves of 64 x 64, one X load task per thread).
+template <bool TRI, int DT, int RT>
 __global__ __launch_bounds__(kI2Threads, 1) void k_init_x3(const float *__restrict__ X,
                                                            int64_t ldx, int64_t R, AView A,
                                                            double *__restrict__ f0,
                                                            double *__restrict__ g0,
                                                            uint8_t *__restrict__ mask0) {
-  constexpr int RT = 256, NT = 256;
+  constexpr int NT = 256;
   static_assert(kI2Threads == 512, "two load tasks per operand and thread");
+  static_assert(RT == 256 || (RT == 128 && !TRI), "row chunk of 256, or 128 without the triangle");
+  constexpr int XT = RT * 4 / kI2Threads;  // X load tasks per thread (2 or 1)
+  constexpr int RBW = RT / 32;             // 16-row blocks per wave
   __shared__ __align__(16) __bf16 Ls[2][3][kX3Plane];  // [X rows / A columns][plane][.][k]
   __shared__ double red[2][NT];     // f partial sums per row-wave, over the row chunks
   __shared__ double gpart[4][NT];   // g partial sums per k group
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wr = (wave >> 2) * 128, wc = (wave & 3) * 64;
+  const int wr = (wave >> 2) * (RT / 2), wc = (wave & 3) * 64;
   const int lr = lane & 15, kq = (lane >> 4) * 8;
   const int64_t m = A.m, n = A.n;
   const int64_t j0 = (int64_t)blockIdx.x * NT;
@@ -654,7 +659,8 @@ __global__ __launch_bounds__(kI2Threads, 1) void k_init_x3(const float *__restri
   constexpr int ES = EInfo<DT>::esize;
   constexpr int YP = DT == DT_F32 ? 3 : 1;  // bfloat16 parts of an A element
 
-  // load tasks: task t (0..1023) of an operand = row / column t & 255, k group t >> 8
+  // load tasks: task t of X = row t % RT, k group t / RT; task t (0..1023) of
+  // A = column t & 255, k group t >> 8
   // (partial sums live in LDS, keeping registers for the operands)
   for (int t = tid; t < 2 * NT; t += kI2Threads) red[t >> 8][t & 255] = 0.0;
   for (int t = tid; t < 4 * NT; t += kI2Threads) gpart[t >> 8][t & 255] = 0.0;
@@ -664,9 +670,9 @@ __global__ __launch_bounds__(kI2Threads, 1) void k_init_x3(const float *__restri
   const int64_t nchunks = (R + RT - 1) / RT;
   for (int64_t rc = 0; rc < nchunks; ++rc) {
     const int64_t r0 = rc * RT;
-    f32x4 acc[8][4];
+    f32x4 acc[RBW][4];
 #pragma unroll
-    for (int x = 0; x < 8; ++x)
+    for (int x = 0; x < RBW; ++x)
 #pragma unroll
       for (int y = 0; y < 4; ++y) acc[x][y] = f32x4{0.f, 0.f, 0.f, 0.f};
 
@@ -676,25 +682,29 @@ __global__ __launch_bounds__(kI2Threads, 1) void k_init_x3(const float *__restri
         const int t = tid + kI2Threads * u;
         const int row = t & 255, kg = (t >> 8) * 8;
         const int64_t gk = k0 + kg;
-        // X row r0 + row, k gk .. gk + 7 (weighted for TRI)
-        const int64_t gr = r0 + row;
         float v[8];
-        if (gr < R && gk < m) {
-          const float *src = X + gr * ldx + gk;
-          if (gk + 7 < m) {
-            const float4 p0 = *(const float4 *)src, p1 = *(const float4 *)(src + 4);
-            v[0] = p0.x; v[1] = p0.y; v[2] = p0.z; v[3] = p0.w;
-            v[4] = p1.x; v[5] = p1.y; v[6] = p1.z; v[7] = p1.w;
+        if (u < XT) {
+          // X row r0 + xrow, k xgk .. xgk + 7 (weighted for TRI)
+          const int xrow = t % RT;
+          const int64_t xgk = k0 + (t / RT) * 8;
+          const int64_t gr = r0 + xrow;
+          if (gr < R && xgk < m) {
+            const float *src = X + gr * ldx + xgk;
+            if (xgk + 7 < m) {
+              const float4 p0 = *(const float4 *)src, p1 = *(const float4 *)(src + 4);
+              v[0] = p0.x; v[1] = p0.y; v[2] = p0.z; v[3] = p0.w;
+              v[4] = p1.x; v[5] = p1.y; v[6] = p1.z; v[7] = p1.w;
+            } else {
+#pragma unroll
+              for (int e = 0; e < 8; ++e) v[e] = xgk + e < m ? src[e] : 0.f;
+            }
           } else {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) v[e] = gk + e < m ? src[e] : 0.f;
+            for (int e = 0; e < 8; ++e) v[e] = 0.f;
           }
-        } else {
-#pragma unroll
-          for (int e = 0; e < 8; ++e) v[e] = 0.f;
+          xr[u][0] = make_float4(v[0], v[1], v[2], v[3]);
+          xr[u][1] = make_float4(v[4], v[5], v[6], v[7]);
         }
-        xr[u][0] = make_float4(v[0], v[1], v[2], v[3]);
-        xr[u][1] = make_float4(v[4], v[5], v[6], v[7]);
         // A column j0 + row, k gk .. gk + 7
         const int64_t gj = j0 + row;
         if constexpr (DT == DT_F32) {
@@ -737,9 +747,11 @@ __global__ __launch_bounds__(kI2Threads, 1) void k_init_x3(const float *__restri
       for (int u = 0; u < 2; ++u) {
         const int t = tid + kI2Threads * u;
         const int row = t & 255, kg = (t >> 8) * 8;
-        const int off = row * kX3RP + kg;
+        const int xrow = t % RT, xkg = (t / RT) * 8;
 #pragma unroll
         for (int op = 0; op < 2; ++op) {
+          if (op == 0 && u >= XT) continue;
+          const int off = op == 0 ? xrow * kX3RP + xkg : row * kX3RP + kg;
           float v[8];
           if (op == 0 || DT == DT_F32) {
             const float4 q0 = op == 0 ? xr[u][0] : yr[u][0], q1 = op == 0 ? xr[u][1] : yr[u][1];
@@ -762,7 +774,7 @@ __global__ __launch_bounds__(kI2Threads, 1) void k_init_x3(const float *__restri
           if (TRI && op == 0 && k0 < r0 + RT) {
             // weights of the triangle: 1 above the diagonal, 1/2 on it, 0 below
             // (stages from k = r0 + 256 on lie wholly above it: weight 1)
-            const int d0 = (int)(k0 + kg - (r0 + row));
+            const int d0 = (int)(k0 + xkg - (r0 + xrow));
 #pragma unroll
             for (int e = 0; e < 8; ++e) v[e] *= d0 + e > 0 ? 1.f : (d0 + e == 0 ? 0.5f : 0.f);
           }
@@ -809,7 +821,7 @@ __global__ __launch_bounds__(kI2Threads, 1) void k_init_x3(const float *__restri
         for (int p = 0; p < YP; ++p)
           b[nb][p] = *(const bf16x8 *)(&Ls[1][p][(wc + 16 * nb + lr) * kX3RP + kq]);
 #pragma unroll
-      for (int rb = 0; rb < 8; ++rb) {
+      for (int rb = 0; rb < RBW; ++rb) {
         bf16x8 av[3];
 #pragma unroll
         for (int p = 0; p < 3; ++p) av[p] = *(const bf16x8 *)(&Ls[0][p][(wr + 16 * rb + lr) * kX3RP + kq]);
@@ -836,7 +848,7 @@ __global__ __launch_bounds__(kI2Threads, 1) void k_init_x3(const float *__restri
     // epilogue of this row chunk (as in k_init256), summed into red
     double colacc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int rb = 0; rb < 8; ++rb) {
+    for (int rb = 0; rb < RBW; ++rb) {
       const int64_t i = r0 + wr + 16 * rb + 4 * (lane >> 4);
       if constexpr (TRI) {
         const int64_t ic = i < m ? i : 0;
@@ -1430,7 +1442,11 @@ __global__ __launch_bounds__(kG2Threads, 1) void k_gram_x3(AView A, float *__res
 // their way into LDS (a thread loads four rows of A or four columns of
 // Omega for eight consecutive k) so that each plane row holds 32
 // consecutive k.  Needs m and r to be multiples of 4.
-template <int DT>
+//
+// TN is the tile's width in columns of Omega: 256 (eight waves of 128 rows x
+// 64 columns), or 128 for narrow targets (eight waves of 64 x 64, so every
+// wave multiplies; the Omega loads of waves 6-7 are then empty).
+template <int DT, int TN>
 __global__ __launch_bounds__(kG2Threads, 1) void k_proj_x3(AView A, const float *__restrict__ Om,
                                                            int64_t r, float *__restrict__ P,
                                                            int64_t ldp, int ntm, int ntile,
@@ -1442,7 +1458,7 @@ __global__ __launch_bounds__(kG2Threads, 1) void k_proj_x3(AView A, const float 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t m = A.m, n = A.n;
   const int64_t tile = blockIdx.x % ntile, split = blockIdx.x / ntile;
-  const int64_t i0 = (tile % ntm) * 256, j0 = (tile / ntm) * 256;
+  const int64_t i0 = (tile % ntm) * 256, j0 = (tile / ntm) * TN;
   const int64_t kb = split * kchunk;
   const int64_t ke = (kb + kchunk) < n ? (kb + kchunk) : n;
   float *Pout = P + split * ldp * r;
@@ -1454,12 +1470,15 @@ __global__ __launch_bounds__(kG2Threads, 1) void k_proj_x3(AView A, const float 
   const int op = __builtin_amdgcn_readfirstlane(tid >> 8), task = tid & 255;
   const int q0 = x3_task_row(task), k8 = x3_task_k(task);
 
-  f32x4 acc[8][4];
+  // a wave's block of the tile: RBW blocks of 16 rows x 4 blocks of 16 columns
+  constexpr int CW = TN / 64;          // waves across the tile's columns
+  constexpr int RBW = 8 * CW / 4;      // 16-row blocks per wave (8 or 4)
+  f32x4 acc[RBW][4];
 #pragma unroll
-  for (int x = 0; x < 8; ++x)
+  for (int x = 0; x < RBW; ++x)
 #pragma unroll
     for (int y = 0; y < 4; ++y) acc[x][y] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const int wr = (wave >> 2) * 128, wc = (wave & 3) * 64;
+  const int wr = (wave / CW) * (16 * RBW), wc = (wave % CW) * 64;
   const int lr = lane & 15, kq = (lane >> 4) * 8;
 
   // the matrix products of one stage from the LDS planes
@@ -1470,7 +1489,7 @@ __global__ __launch_bounds__(kG2Threads, 1) void k_proj_x3(AView A, const float 
 #pragma unroll
       for (int p = 0; p < 3; ++p) b[nb][p] = *(const bf16x8 *)(&Lo[p][(wc + 16 * nb + lr) * kX3RP + kq]);
 #pragma unroll
-    for (int rb = 0; rb < 8; ++rb) {
+    for (int rb = 0; rb < RBW; ++rb) {
       bf16x8 av[AP];
 #pragma unroll
       for (int p = 0; p < AP; ++p) av[p] = *(const bf16x8 *)(&La[p][(wr + 16 * rb + lr) * kX3RP + kq]);
@@ -1521,6 +1540,8 @@ __global__ __launch_bounds__(kG2Threads, 1) void k_proj_x3(AView A, const float 
     const int64_t qg = (OP == 0 ? i0 : j0) + q0;
     const bool inq = qg < qn;
     const uint32_t qoff = (uint32_t)(inq ? qg : qn - 4);
+    // (TN = 128: the Omega tasks of columns 128 .. 255, waves 6-7, have no work)
+    const bool idle = OP == 1 && q0 >= TN;
     const uint32_t colb = OP == 0 ? (uint32_t)(A.lda * ES) : (uint32_t)(r * 4);  // bytes per k
     const uint32_t qb = qoff * (OP == 0 ? (uint32_t)ES : 4u);
     const char *src0 = OP == 0 ? abase : (const char *)Om;
@@ -1595,12 +1616,12 @@ __global__ __launch_bounds__(kG2Threads, 1) void k_proj_x3(AView A, const float 
       }
     };
 
-    if (kb < ke) gload(kb);
+    if (kb < ke && !idle) gload(kb);
     for (int64_t k0 = kb; k0 < ke; k0 += kX3BK) {
       __syncthreads();  // the previous stage's operands are consumed
-      lstore();
+      if (!idle) lstore();
       __syncthreads();
-      if (k0 + kX3BK < ke) gload(k0 + kX3BK);
+      if (k0 + kX3BK < ke && !idle) gload(k0 + kX3BK);
       mma();
     }
   };
@@ -1613,7 +1634,7 @@ __global__ __launch_bounds__(kG2Threads, 1) void k_proj_x3(AView A, const float 
     const int64_t j = j0 + wc + 16 * nb + lr;
     if (j >= r) continue;
 #pragma unroll
-    for (int rb = 0; rb < 8; ++rb) {
+    for (int rb = 0; rb < RBW; ++rb) {
       const int64_t i = i0 + wr + 16 * rb + 4 * (lane >> 4);
       float *dst = Pout + j * ldp + i;
       const f32x4 v = acc[rb][nb];
@@ -2019,15 +2040,22 @@ static hipError_t init_dt(const float *X, int64_t ldx, int64_t R, const AView &A
     const char *e = std::getenv("GCSS_MFMA_INIT256");
     return !(e && std::atoi(e) == 0);
   }();
+  // narrow targets (64 <= R <= 128) on the BF16 matrix cores: 128-row chunks
+  if (big_ok && mfma_x3() && !gram && R >= 64 && R <= 128 && A.n >= 1024) {
+    const unsigned grid = (unsigned)((A.n + 255) / 256);
+    hipLaunchKernelGGL((k_init_x3<false, DT, 128>), dim3(grid), dim3(kI2Threads), 0, s, X, ldx, R,
+                       A, f0, g0, mask0);
+    return hipGetLastError();
+  }
   if (big_ok && R >= 192 && A.n >= 1024) {
     const unsigned grid = (unsigned)((A.n + 255) / 256);
     if (mfma_x3()) {
       if (gram)
-        hipLaunchKernelGGL((k_init_x3<true, DT>), dim3(grid), dim3(kI2Threads), 0, s, X, ldx, R, A,
-                           f0, g0, mask0);
+        hipLaunchKernelGGL((k_init_x3<true, DT, 256>), dim3(grid), dim3(kI2Threads), 0, s, X, ldx,
+                           R, A, f0, g0, mask0);
       else
-        hipLaunchKernelGGL((k_init_x3<false, DT>), dim3(grid), dim3(kI2Threads), 0, s, X, ldx, R, A,
-                           f0, g0, mask0);
+        hipLaunchKernelGGL((k_init_x3<false, DT, 256>), dim3(grid), dim3(kI2Threads), 0, s, X, ldx,
+                           R, A, f0, g0, mask0);
       return hipGetLastError();
     }
     if (gram)
@@ -2180,14 +2208,25 @@ hipError_t launch_gram(const AView &A, float *C, int64_t ldc, void *scratch, int
   return hipGetLastError();
 }
 
-static KPlan proj_plan(int64_t m, int64_t n, int64_t r, bool force256 = false) {
+// Narrow targets (64 <= r <= 128) on the BF16-split projection take tiles of
+// 256 rows x 128 columns when m >= 256 (k_proj_x3<.., 128>).
+static bool proj_narrow(int64_t m, int64_t r) { return m >= 256 && r >= 64 && r <= 128; }
+
+static KPlan proj_plan(int64_t m, int64_t n, int64_t r, bool force256 = false,
+                       bool narrow = false) {
   KPlan p{};
   // keep the partials within ~128 MiB and every split at least 256 columns long
   const int64_t ldp = ((m + 3) / 4) * 4;
   const int64_t per = ldp * r * (int64_t)sizeof(float);
   int64_t cap = (int64_t)(128LL << 20) / (per > 0 ? per : 1);
   if (cap < 1) cap = 1;
-  if (force256 || (m >= 256 && r >= 192)) {
+  if (narrow) {
+    p.tile = 256;  // 256 rows x 128 columns, one column tile
+    const int64_t tm = (m + 255) / 256;
+    p.ntm = (int)tm;
+    p.ntile = (int)tm;
+    finish_plan(n, pick_split(tm, n, cap, kPlanSlots256), &p);
+  } else if (force256 || (m >= 256 && r >= 192)) {
     p.tile = 256;
     const int64_t tm = (m + 255) / 256, tn = (r + 255) / 256;
     p.ntm = (int)tm;
@@ -2212,7 +2251,11 @@ size_t proj_scratch_bytes(int64_t m, int64_t n, int64_t r, int num_cu) {
   (void)num_cu;
   const KPlan p = proj_plan(m, n, r), p2 = proj_plan(m, n, r, true);
   const int64_t ldp = ((m + 3) / 4) * 4;
-  const int64_t sp = p.nsplit > p2.nsplit ? p.nsplit : p2.nsplit;
+  int64_t sp = p.nsplit > p2.nsplit ? p.nsplit : p2.nsplit;
+  if (proj_narrow(m, r)) {
+    const KPlan p3 = proj_plan(m, n, r, false, true);
+    if (p3.nsplit > sp) sp = p3.nsplit;
+  }
   return (size_t)sp * ldp * r * sizeof(float);
 }
 
@@ -2247,23 +2290,37 @@ hipError_t launch_project_sign_dense(const AView &A, uint32_t k0, uint32_t k1, u
 hipError_t launch_project(const AView &A, const float *omega, int64_t r, float *B,
                           int64_t ldb, void *scratch, int num_cu, hipStream_t s) {
   (void)num_cu;
-  const KPlan pl = proj_plan(A.m, A.n, r);
   const int64_t ldp = ((A.m + 3) / 4) * 4;
   float *P = (float *)scratch;
+  // (k_proj_x3 forms its load addresses as 32-bit offsets from the stage's
+  // first k: 32 columns of A and 32 rows of Omega must span under 2^31 bytes)
+  const int64_t es = A.dtype == DT_F32 ? 4 : A.dtype == DT_BF16 ? 2 : 1;
+  const bool off32 = 32 * A.lda * es < (1LL << 31) && 32 * r * 4 < (1LL << 31);
+  const bool x3 = mfma_x3() && A.m % 4 == 0 && r % 4 == 0 && off32;
+  if (x3 && proj_narrow(A.m, r)) {
+    const KPlan pn = proj_plan(A.m, A.n, r, false, true);
+    const dim3 gn((unsigned)(pn.ntile * pn.nsplit));
+    switch (A.dtype) {
+      case DT_F32: hipLaunchKernelGGL((k_proj_x3<DT_F32, 128>), gn, dim3(kG2Threads), 0, s, A, omega, r, P, ldp, pn.ntm, pn.ntile, pn.kchunk); break;
+      case DT_BF16: hipLaunchKernelGGL((k_proj_x3<DT_BF16, 128>), gn, dim3(kG2Threads), 0, s, A, omega, r, P, ldp, pn.ntm, pn.ntile, pn.kchunk); break;
+      case DT_FP8: hipLaunchKernelGGL((k_proj_x3<DT_FP8, 128>), gn, dim3(kG2Threads), 0, s, A, omega, r, P, ldp, pn.ntm, pn.ntile, pn.kchunk); break;
+      default: return hipErrorInvalidValue;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_proj_reduce(P, ldp, A.m, r, pn.nsplit, B, ldb, s);
+  }
+  const KPlan pl = proj_plan(A.m, A.n, r);
   const int tm = pl.ntm, nt = pl.ntile, sp = pl.nsplit;
   const int tn = nt / tm;
   const int64_t kc = pl.kchunk;
   const dim3 grid((unsigned)(nt * sp));
   if (pl.tile == 256) {
-    // (k_proj_x3 forms its load addresses as 32-bit offsets from the stage's
-    // first k: 32 columns of A and 32 rows of Omega must span under 2^31 bytes)
-    const int64_t es = A.dtype == DT_F32 ? 4 : A.dtype == DT_BF16 ? 2 : 1;
-    const bool off32 = 32 * A.lda * es < (1LL << 31) && 32 * r * 4 < (1LL << 31);
-    if (mfma_x3() && A.m % 4 == 0 && r % 4 == 0 && off32) {
+    if (x3) {
       switch (A.dtype) {
-        case DT_F32: hipLaunchKernelGGL(k_proj_x3<DT_F32>, grid, dim3(kG2Threads), 0, s, A, omega, r, P, ldp, tm, nt, kc); break;
-        case DT_BF16: hipLaunchKernelGGL(k_proj_x3<DT_BF16>, grid, dim3(kG2Threads), 0, s, A, omega, r, P, ldp, tm, nt, kc); break;
-        case DT_FP8: hipLaunchKernelGGL(k_proj_x3<DT_FP8>, grid, dim3(kG2Threads), 0, s, A, omega, r, P, ldp, tm, nt, kc); break;
+        case DT_F32: hipLaunchKernelGGL((k_proj_x3<DT_F32, 256>), grid, dim3(kG2Threads), 0, s, A, omega, r, P, ldp, tm, nt, kc); break;
+        case DT_BF16: hipLaunchKernelGGL((k_proj_x3<DT_BF16, 256>), grid, dim3(kG2Threads), 0, s, A, omega, r, P, ldp, tm, nt, kc); break;
+        case DT_FP8: hipLaunchKernelGGL((k_proj_x3<DT_FP8, 256>), grid, dim3(kG2Threads), 0, s, A, omega, r, P, ldp, tm, nt, kc); break;
         default: return hipErrorInvalidValue;
       }
     } else

@@ -38,7 +38,9 @@ def test_quantizers_bit_exact(gpu, m, n):
     np.testing.assert_array_equal(h.cpu().numpy().view(np.uint16), h_ref)
 
 
-@pytest.mark.parametrize("m,n,r", [(37, 300, 7), (300, 1000, 256), (1000, 700, 130)])
+@pytest.mark.parametrize("m,n,r", [(37, 300, 7), (300, 1000, 256), (1000, 700, 130),
+                                   # 64 <= r <= 128, m >= 256: 256 x 128 tiles
+                                   (1024, 3000, 128), (260, 1500, 64)])
 def test_projection_matches_oracle_dots(gpu, m, n, r):
     import torch
     A = synth.gauss_lowrank_dense(m, n, 10, 0.1, seed=m)
@@ -65,7 +67,9 @@ def _quantized(gpu, A32, m, dt):
 
 
 @pytest.mark.parametrize("m,n,r,dt", [(300, 1000, 256, "bf16"), (520, 700, 200, "fp8"),
-                                        (516, 900, 260, "bf16"), (1028, 1500, 512, "fp8")])
+                                        (516, 900, 260, "bf16"), (1028, 1500, 512, "fp8"),
+                                        (516, 2000, 96, "bf16"), (300, 1500, 128, "fp8"),
+                                        (1024, 1300, 124, "bf16")])
 def test_projection_quantized_storage(gpu, m, n, r, dt):
     """B = A_hat Omega from BF16 / FP8 codes (large-tile path), entry by entry."""
     A32 = colstore32(synth.gauss_lowrank_dense(m, n, 10, 0.1, seed=m + 1))
@@ -119,10 +123,13 @@ def test_gram_quantized_storage(gpu, m, n, dt):
 # ---------------------------------------------------------------- a1 ---------
 @pytest.mark.parametrize("m,n,r,dt", [(37, 70, 3, "f32"), (500, 1000, 64, "f32"), (1000, 300, 256, "f32"),
                                       (300, 500, 300, "f32"), (600, 400, 130, "bf16"), (700, 333, 40, "fp8"),
-                                      # n >= 1024: binary32 128-row tiles (r < 192) and the
-                                      # bfloat16 matrix-core kernel (r >= 192), ragged tiles
+                                      # n >= 1024: the bfloat16 matrix-core kernel with
+                                      # 128-row chunks (64 <= r <= 128) or 256-row chunks
+                                      # (r >= 192), binary32 128-row tiles between, ragged tiles
                                       (1024, 3000, 128, "f32"), (1000, 2500, 150, "bf16"),
-                                      (520, 1100, 128, "fp8"), (300, 2049, 200, "f32")])
+                                      (520, 1100, 128, "fp8"), (300, 2049, 200, "f32"),
+                                      (1000, 2500, 96, "bf16"), (516, 1500, 64, "f32"),
+                                      (260, 1030, 100, "fp8")])
 def test_initial_scores_factor(gpu, m, n, r, dt):
     A = synth.gauss_lowrank_dense(m, n, 8, 0.05, seed=n)
     A[:, 5] = 0.0
