@@ -27,45 +27,89 @@ constexpr int kMT = 64;  // Gram tile edge
 constexpr int kMK = 32;  // contraction chunk
 constexpr int kMergeCPW = 32;  // candidates per workgroup of a step (8 lanes each)
 
-// Decoded, scaled element k of pool column c.
+// Element k of pool column c as stored (binary32, or the BF16 / E4M3 code),
+// and its decoded, scaled value.
 template <int DT>
-__device__ __forceinline__ double pool_elem(const MergeArgs &a, int64_t c, int64_t k) {
-  const double s = DT == DT_FP8 ? (double)a.sc0[c] : 1.0;
+struct PoolRaw;
+template <> struct PoolRaw<DT_F32> { using T = float; };
+template <> struct PoolRaw<DT_BF16> { using T = uint16_t; };
+template <> struct PoolRaw<DT_FP8> { using T = uint8_t; };
+template <int DT>
+__device__ __forceinline__ typename PoolRaw<DT>::T pool_raw(const MergeArgs &a, int64_t c, int64_t k) {
+  return ((const typename PoolRaw<DT>::T *)a.a0)[c * a.lda + k];
+}
+// (sc: the column's FP8 scale; 1 otherwise)
+template <int DT>
+__device__ __forceinline__ double pool_dec(typename PoolRaw<DT>::T v, double sc) {
   if constexpr (DT == DT_F32) {
-    return (double)((const float *)a.a0)[c * a.lda + k];
+    return (double)v;
   } else if constexpr (DT == DT_BF16) {
-    return (double)__uint_as_float((uint32_t)((const uint16_t *)a.a0)[c * a.lda + k] << 16);
+    return (double)__uint_as_float((uint32_t)v << 16);
   } else {
-    const uint8_t code = ((const uint8_t *)a.a0)[c * a.lda + k];
-    f32x2 v = __builtin_amdgcn_cvt_pk_f32_fp8((uint32_t)code, false);
-    return s * (double)v[0];
+    f32x2 d = __builtin_amdgcn_cvt_pk_f32_fp8((uint32_t)v, false);
+    return sc * (double)d[0];
   }
 }
 
 // GH[i][j] = pool column i . Y_j, Y_j = pool column j (j < P) or target
 // column j - P; 64 x 64 tiles, FP64, fixed summation order (chunks of 32
 // rows in order).  G comes out exactly symmetric: entries (i, j) and (j, i)
-// multiply the same pairs in the same order.
+// multiply the same pairs in the same order.  A chunk's loads come from
+// clamped in-range addresses, all issued before any is used, and entries
+// outside the matrices are zeroed as they go to LDS; a tile takes its Y
+// columns from the pool, the target, or (the one tile that straddles
+// j = P) both.
 template <int DT>
 __global__ __launch_bounds__(256) void k_pool_gh(MergeArgs a) {
+  using RT = typename PoolRaw<DT>::T;
   __shared__ double xs[kMK][kMT + 1];
   __shared__ double ys[kMK][kMT + 1];
   const int64_t i0 = (int64_t)blockIdx.x * kMT, j0 = (int64_t)blockIdx.y * kMT;
   const int64_t P = a.P, m = a.m, ncol = a.P + a.r;
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   const int lr = threadIdx.x & 31, lc = threadIdx.x >> 5;
+  // (the same in the whole workgroup) where the tile's Y columns live
+  const bool ypool = j0 + kMT <= P, ytarget = j0 >= P;
+  // this thread's columns (clamped into range) and their FP8 scales
+  int64_t xc[8], yc[8];
+  double xsc[8], ysc[8];
+#pragma unroll
+  for (int x = 0; x < 8; ++x) {
+    const int64_t ci = i0 + lc + 8 * x, cj = j0 + lc + 8 * x;
+    xc[x] = ci < P ? ci : P - 1;
+    yc[x] = cj < P ? cj : P - 1;
+    xsc[x] = DT == DT_FP8 ? (double)a.sc0[xc[x]] : 1.0;
+    ysc[x] = DT == DT_FP8 ? (double)a.sc0[yc[x]] : 1.0;
+  }
   double acc[4][4] = {};
   for (int64_t kb = 0; kb < m; kb += kMK) {
     const int64_t k = kb + lr;
+    const int64_t kc = k < m ? k : m - 1;
+    RT xr[8], yp[8];
+    float yb[8];
+#pragma unroll
+    for (int x = 0; x < 8; ++x) {
+      const int64_t cj = j0 + lc + 8 * x;
+      xr[x] = pool_raw<DT>(a, xc[x], kc);
+      if (!ytarget) yp[x] = pool_raw<DT>(a, yc[x], kc);
+      if (!ypool) {
+        const int64_t bj = cj < P ? 0 : (cj < ncol ? cj - P : a.r - 1);
+        yb[x] = a.B[bj * a.ldb + kc];
+      }
+    }
 #pragma unroll
     for (int x = 0; x < 8; ++x) {
       const int cc = lc + 8 * x;
       const int64_t ci = i0 + cc, cj = j0 + cc;
-      xs[lr][cc] = (k < m && ci < P) ? pool_elem<DT>(a, ci, k) : 0.0;
-      double yv = 0.0;
-      if (k < m && cj < ncol)
-        yv = cj < P ? pool_elem<DT>(a, cj, k) : (double)a.B[(cj - P) * a.ldb + k];
-      ys[lr][cc] = yv;
+      xs[lr][cc] = (k < m && ci < P) ? pool_dec<DT>(xr[x], xsc[x]) : 0.0;
+      double yv;
+      if (ypool)
+        yv = pool_dec<DT>(yp[x], ysc[x]);
+      else if (ytarget)
+        yv = (double)yb[x];
+      else
+        yv = cj < P ? pool_dec<DT>(yp[x], ysc[x]) : (double)yb[x];
+      ys[lr][cc] = (k < m && cj < ncol) ? yv : 0.0;
     }
     __syncthreads();
 #pragma unroll 8
