@@ -39,8 +39,10 @@ def test_quantizers_bit_exact(gpu, m, n):
 
 
 @pytest.mark.parametrize("m,n,r", [(37, 300, 7), (300, 1000, 256), (1000, 700, 130),
-                                   # 64 <= r <= 128, m >= 256: 256 x 128 tiles
-                                   (1024, 3000, 128), (260, 1500, 64)])
+                                   # 64 <= r <= 128, m >= 256: 256 x 128 tiles (exact and
+                                   # ragged row tiles, one short k split)
+                                   (1024, 3000, 128), (260, 1500, 64), (256, 300, 64),
+                                   (512, 257, 128)])
 def test_projection_matches_oracle_dots(gpu, m, n, r):
     import torch
     A = synth.gauss_lowrank_dense(m, n, 10, 0.1, seed=m)
@@ -129,7 +131,8 @@ def test_gram_quantized_storage(gpu, m, n, dt):
                                       (1024, 3000, 128, "f32"), (1000, 2500, 150, "bf16"),
                                       (520, 1100, 128, "fp8"), (300, 2049, 200, "f32"),
                                       (1000, 2500, 96, "bf16"), (516, 1500, 64, "f32"),
-                                      (260, 1030, 100, "fp8")])
+                                      (260, 1030, 100, "fp8"), (256, 1024, 128, "bf16"),
+                                      (256, 1024, 64, "fp8")])
 def test_initial_scores_factor(gpu, m, n, r, dt):
     A = synth.gauss_lowrank_dense(m, n, 8, 0.05, seed=n)
     A[:, 5] = 0.0
