@@ -46,6 +46,34 @@ __device__ __forceinline__ double sum_waves(const double (&v)[kStreamWaves]) {
   return s;
 }
 
+// Sum over the 64 lanes of a wave, returned wave-uniform: four DPP steps sum
+// each row of 16 lanes into all of its lanes (quad swaps, then the half-row
+// and row mirrors), two row broadcasts carry rows 0-2 into row 3, and lane 63
+// holds the total.  All VALU: no LDS crossbar round trips per column.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_step(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
+}
+__device__ __forceinline__ float wave_total(float v) {
+  v += dpp_step<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+  v += dpp_step<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+  v += dpp_step<0x141, 0xF>(v);  // row_half_mirror
+  v += dpp_step<0x140, 0xF>(v);  // row_mirror
+  v += dpp_step<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_step<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_step(double v) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, ROW_MASK, 0xF, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, ROW_MASK, 0xF, false);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+// (FP64 sums, EX only, keep the shuffle butterfly: DPP on both halves of each
+// double measured no faster)
+__device__ __forceinline__ double wave_total(double v) { return wave_sum(v); }
+
 // EX (Gram target B = A): omega_i = A_i . q is formed in FP64 from the FP64
 // basis vector (every product of a decoded element and q is exact before the
 // FP64 accumulation), and the pass also returns sum_i omega_i^2 = ||A^T q||^2,
@@ -176,7 +204,9 @@ __global__ __launch_bounds__(512) void k_stream(AView A, int ucol, const float *
   QT mw = 0;
   float mz = 0.f;
   double qacc = 0.0;  // EX: sum of omega^2 over this lane's columns
-  auto consume = [&](int x, const uint4 (&b)[U][NJ]) {
+  // FULL: every chunk of every lane lies inside m, so no element is masked
+  auto consume = [&](auto full_c, int x, const uint4 (&b)[U][NJ]) {
+    constexpr bool FULL = decltype(full_c)::value;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       QT dq = 0;
@@ -185,10 +215,12 @@ __global__ __launch_bounds__(512) void k_stream(AView A, int ucol, const float *
       for (int j = 0; j < NJ; ++j) {
         float v[EPC];
         decode_chunk<DT>(b[u][j], v);
-        if (valid[j] < EPC) {
+        if constexpr (!FULL) {
+          if (valid[j] < EPC) {
 #pragma unroll
-          for (int e = 0; e < EPC; ++e)
-            if (e >= valid[j]) v[e] = 0.f;
+            for (int e = 0; e < EPC; ++e)
+              if (e >= valid[j]) v[e] = 0.f;
+          }
         }
 #pragma unroll
         for (int e = 0; e < EPC; ++e) {
@@ -196,14 +228,15 @@ __global__ __launch_bounds__(512) void k_stream(AView A, int ucol, const float *
           dz = fmaf(v[e], zv[j][e], dz);
         }
       }
-      dq = wave_sum(dq);
-      dz = wave_sum(dz);
-      if (lane == x * U + u) {
-        mw = dq;
-        mz = dz;
-      }
+      dq = wave_total(dq);
+      dz = wave_total(dz);
+      const bool me = lane == x * U + u;
+      mw = me ? dq : mw;
+      mz = me ? dz : mz;
     }
   };
+  // one instance of the unit loop for full-height chunks, one for a ragged m
+  auto run = [&](auto full_c) {
   if (!rescore) {
 #pragma unroll
     for (int d = 0; d < PD; ++d) fetch(su_cur, d, buf[d]);
@@ -235,7 +268,7 @@ __global__ __launch_bounds__(512) void k_stream(AView A, int ucol, const float *
           const int xt = x0 + d + PD;
           const bool nx = xt >= gpu;
           fetch(nx ? su_nxt : su_cur, nx ? xt - gpu : xt, buf[(d + PD) % (PD + 1)]);
-          consume(x0 + d, buf[d]);
+          consume(full_c, x0 + d, buf[d]);
           // keeps the scheduler from hoisting later loads into renamed
           // registers, which would force a full drain at the loop head
           __builtin_amdgcn_sched_barrier(0);
@@ -283,6 +316,11 @@ __global__ __launch_bounds__(512) void k_stream(AView A, int ucol, const float *
     su_nxt = unit_of(kth + 1);
     if constexpr (W > 1) __syncthreads();  // redq/redz are rewritten by the next unit
   }
+  };
+  if (m == (int64_t)64 * NJ * W * EPC)
+    run(std::true_type{});
+  else
+    run(std::false_type{});
 
   // workgroup winner (and, EX, the workgroup's sum of omega^2, fixed order)
   wave_argmax(best, besti);

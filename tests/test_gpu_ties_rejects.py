@@ -70,13 +70,16 @@ def _reject_case(m=4096, n=2000, r=16, seed=3):
     """Explicit target B = X diag(sqrt(s2)) Y^T with known left singular
     vectors X.  Column 10 is v = 3 (x1 + x2)/sqrt(2) (the best candidate) and
     column 1005 an exact copy of it; columns 1100..1139 are near copies
-    3 (v - 3e-5 w + 1e-6 noise) with w = (x1 - x2)/sqrt(2): their exact
+    c_j (v - 3e-5 w + 1e-6 noise) with w = (x1 - x2)/sqrt(2): their exact
     residual after v is about 9e-10 of their squared norm (below TAU), while
     the binary32 rounding of the dot products that track it is a few 1e-8 of
     it, so some of them stay candidates after v is picked, with scores of
     rounding noise over rounding noise; their first-step score is 2e-5 below
-    v's.  Ten more columns are x3 .. x12 (scores s2[2..11], 25% apart) over a
-    1e-3 noise background."""
+    v's.  The scales c_j (spread over [1.5, 4.5]; a score does not depend on
+    a column's scale) give each copy its own rounding, so the sign of the
+    noise is not shared by all of them whatever the summation order.  Ten
+    more columns are x3 .. x12 (scores s2[2..11], 25% apart) over a 1e-3
+    noise background."""
     rng = np.random.default_rng(seed)
     X, _ = np.linalg.qr(rng.standard_normal((m, r)))
     Y, _ = np.linalg.qr(rng.standard_normal((r, r)))
@@ -89,7 +92,7 @@ def _reject_case(m=4096, n=2000, r=16, seed=3):
     A[:, 1005] = 3.0 * v
     near = list(range(1100, 1140))
     for j in near:
-        A[:, j] = 3.0 * (v - 3e-5 * w + 1e-6 * rng.standard_normal(m) / math.sqrt(m))
+        A[:, j] = rng.uniform(1.5, 4.5) * (v - 3e-5 * w + 1e-6 * rng.standard_normal(m) / math.sqrt(m))
     planted = [50, 120, 300, 777, 900, 1010, 1200, 1500, 1700, 1900]
     for t, j in enumerate(planted):
         A[:, j] = X[:, 2 + t]
