@@ -4,6 +4,8 @@
 // fused stream below walks a table of column groups, each group inside one
 // block, so one launch streams all blocks' columns.  Each group writes its
 // own argmax candidate; k_block_argmax then picks every block's next column.
+#include <type_traits>
+
 #include "gcss_device.h"
 
 namespace gcss {
@@ -47,6 +49,18 @@ __device__ __forceinline__ void bdecode(const uint4 &r, float *v) {
 
 typedef uint32_t bu32x4 __attribute__((ext_vector_type(4)));
 
+// 16-byte non-temporal load (A is read once per pass)
+__device__ __forceinline__ uint4 bload(const char *p) {
+  const bu32x4 v = __builtin_nontemporal_load((const bu32x4 *)p);
+  return make_uint4(v[0], v[1], v[2], v[3]);
+}
+
+__device__ __forceinline__ int64_t uniform_i64(int64_t v) {
+  const uint32_t l = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t h = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)h << 32) | l);
+}
+
 template <int DT, int NJ, int W>
 __global__ __launch_bounds__(256) void k_stream_b(AView A, const GroupEnt *__restrict__ groups,
                                                   int64_t ngroups, const float *__restrict__ q32,
@@ -71,6 +85,10 @@ __global__ __launch_bounds__(256) void k_stream_b(AView A, const GroupEnt *__res
   const int64_t nsuper = (ngroups + TEAMS - 1) / TEAMS;
   const char *abase = (const char *)A.a;
   const int64_t col_bytes = A.lda * BElem<DT>::esize;
+  // Every load is unconditional, so the waits for a load group are exact: a
+  // chunk past the end of the column reads its last chunk (masked below), a
+  // column past the end of the group reads this block's q (in L2; unused).
+  const int64_t nchunk = (m + EPC - 1) / EPC;
   int valid[NJ];
   const char *lane_off[NJ];
 #pragma unroll
@@ -78,8 +96,10 @@ __global__ __launch_bounds__(256) void k_stream_b(AView A, const GroupEnt *__res
     const int64_t ci = (int64_t)ws * 64 * NJ + j * 64 + lane;
     const int64_t e0 = ci * EPC;
     valid[j] = (int)(e0 < m ? (m - e0 < EPC ? m - e0 : EPC) : 0);
-    lane_off[j] = abase + ci * 16;
+    lane_off[j] = abase + (ci < nchunk ? ci : nchunk - 1) * 16;
   }
+  // every chunk of every lane inside m: the loop instance without masking
+  const bool full = m == (int64_t)64 * NJ * W * EPC;
 
   // super-groups come from a shared counter; the next one is claimed while
   // the current one's epilogue runs
@@ -98,13 +118,15 @@ __global__ __launch_bounds__(256) void k_stream_b(AView A, const GroupEnt *__res
     float scv = 1.f;
     int mk = 1;
     if (grp < ngroups) {
+      // one group per team: read back as wave-uniform values, so the column
+      // loop and its loads stay under uniform control flow
       const GroupEnt ge = groups[grp];
-      col0 = ge.col0;
-      ncol = ge.ncol;
-      blk = ge.blk;
+      col0 = uniform_i64(ge.col0);
+      ncol = __builtin_amdgcn_readfirstlane(ge.ncol);
+      blk = __builtin_amdgcn_readfirstlane(ge.blk);
       const DevState *st = stb + blk;
-      live = !st->done;
-      rescore = score_only || st->skip;
+      live = __builtin_amdgcn_readfirstlane(st->done) == 0;
+      rescore = score_only || __builtin_amdgcn_readfirstlane(st->skip) != 0;
       u2 = st->u2;
       tau = st->tau;
       if (ws == 0) {
@@ -138,37 +160,34 @@ __global__ __launch_bounds__(256) void k_stream_b(AView A, const GroupEnt *__res
           zv[j][e + 3] = b.w;
         }
       }
-      uint4 cur[U][NJ], nxt[U][NJ];
+      const char *dummy = (const char *)qb + lane * 16;
+      // two load groups of U columns, used in turn: one in flight while the
+      // other is reduced
+      uint4 b0[U][NJ], b1[U][NJ];
       auto fetch = [&](int c0, uint4 (&buf)[U][NJ]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const bool cv = (c0 + u) < ncol;
           const int64_t cb = (col0 + c0 + u) * col_bytes;
 #pragma unroll
-          for (int j = 0; j < NJ; ++j) {
-            if (cv && valid[j] > 0) {
-              const bu32x4 v = __builtin_nontemporal_load((const bu32x4 *)(lane_off[j] + cb));
-              buf[u][j] = make_uint4(v[0], v[1], v[2], v[3]);
-            } else {
-              buf[u][j] = make_uint4(0u, 0u, 0u, 0u);
-            }
-          }
+          for (int j = 0; j < NJ; ++j) buf[u][j] = bload(cv ? lane_off[j] + cb : dummy);
         }
       };
-      fetch(0, cur);
-      for (int c0 = 0; c0 < ncol; c0 += U) {
-        if (c0 + U < ncol) fetch(c0 + U, nxt);
+      auto consume = [&](auto full_c, int c0, const uint4 (&buf)[U][NJ]) {
+        constexpr bool FULL = decltype(full_c)::value;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           float dq = 0.f, dz = 0.f;
 #pragma unroll
           for (int j = 0; j < NJ; ++j) {
             float v[EPC];
-            bdecode<DT>(cur[u][j], v);
-            if (valid[j] < EPC) {
+            bdecode<DT>(buf[u][j], v);
+            if constexpr (!FULL) {
+              if (valid[j] < EPC) {
 #pragma unroll
-              for (int e = 0; e < EPC; ++e)
-                if (e >= valid[j]) v[e] = 0.f;
+                for (int e = 0; e < EPC; ++e)
+                  if (e >= valid[j]) v[e] = 0.f;
+              }
             }
 #pragma unroll
             for (int e = 0; e < EPC; ++e) {
@@ -176,18 +195,27 @@ __global__ __launch_bounds__(256) void k_stream_b(AView A, const GroupEnt *__res
               dz = fmaf(v[e], zv[j][e], dz);
             }
           }
-          dq = wave_sum(dq);
-          dz = wave_sum(dz);
-          if (lane == c0 + u) {
-            mw = dq;
-            mz = dz;
-          }
+          dq = wave_total(dq);
+          dz = wave_total(dz);
+          const bool me = lane == c0 + u;
+          mw = me ? dq : mw;
+          mz = me ? dz : mz;
         }
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-          for (int j = 0; j < NJ; ++j) cur[u][j] = nxt[u][j];
-      }
+      };
+      auto run = [&](auto full_c) {
+        fetch(0, b0);
+        for (int c0 = 0; c0 < ncol; c0 += 2 * U) {
+          fetch(c0 + U, b1);
+          consume(full_c, c0, b0);
+          if (c0 + U >= ncol) break;
+          fetch(c0 + 2 * U, b0);
+          consume(full_c, c0 + U, b1);
+        }
+      };
+      if (full)
+        run(std::true_type{});
+      else
+        run(std::false_type{});
     }
     // every thread has read sg_s: claim the next super-group
     __syncthreads();

@@ -46,30 +46,6 @@ __device__ __forceinline__ double sum_waves(const double (&v)[kStreamWaves]) {
   return s;
 }
 
-// Sum over the 64 lanes of a wave, returned wave-uniform: four DPP steps sum
-// each row of 16 lanes into all of its lanes (quad swaps, then the half-row
-// and row mirrors), two row broadcasts carry rows 0-2 into row 3, and lane 63
-// holds the total.  All VALU: no LDS crossbar round trips per column.
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ float dpp_step(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
-}
-__device__ __forceinline__ float wave_total(float v) {
-  v += dpp_step<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
-  v += dpp_step<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
-  v += dpp_step<0x141, 0xF>(v);  // row_half_mirror
-  v += dpp_step<0x140, 0xF>(v);  // row_mirror
-  v += dpp_step<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
-  v += dpp_step<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
-}
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ double dpp_step(double v) {
-  const uint64_t u = (uint64_t)__double_as_longlong(v);
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, ROW_MASK, 0xF, false);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, ROW_MASK, 0xF, false);
-  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
-}
 // (FP64 sums, EX only, keep the shuffle butterfly: DPP on both halves of each
 // double measured no faster)
 __device__ __forceinline__ double wave_total(double v) { return wave_sum(v); }
