@@ -42,12 +42,24 @@ __global__ __launch_bounds__(kEThreads) void k_err_qtb(const double *__restrict_
   for (int64_t jb = j0; jb < j1; jb += kEK) {
     const int64_t j = jb + lr;
     const bool jok = j < j1;
+    // every load unconditional, from a clamped row and column (so all 16 are
+    // in flight together); out-of-range values are zeroed at the LDS store
+    const int64_t jc = jok ? j : j1 - 1;
+    double qv[8];
+    float bv[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int cc = lc + 8 * i;
       const int s = s0 + cc, c = c0 + cc;
-      qs[lr][cc] = (jok && s < k) ? Q[(int64_t)s * ldq + j] : 0.0;
-      bs[lr][cc] = (jok && c < r) ? (double)B[(int64_t)c * ldb + j] : 0.0;
+      qv[i] = Q[(int64_t)(s < k ? s : k - 1) * ldq + jc];
+      bv[i] = B[(int64_t)(c < r ? c : r - 1) * ldb + jc];
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int cc = lc + 8 * i;
+      const int s = s0 + cc, c = c0 + cc;
+      qs[lr][cc] = (jok && s < k) ? qv[i] : 0.0;
+      bs[lr][cc] = (jok && c < r) ? (double)bv[i] : 0.0;
     }
     __syncthreads();
 #pragma unroll 8
@@ -106,17 +118,28 @@ __global__ __launch_bounds__(kEThreads) void k_err_resid(const double *__restric
   // loaders: Q as 64 rows x 32 s (a wave: one s, 64 rows), Y as 32 s x 64 c
   const int qj = threadIdx.x & 63, qs0 = threadIdx.x >> 6;
   const int ysl = threadIdx.x & 31, yc0 = threadIdx.x >> 5;
+  const int64_t jq = j0 + qj;
+  const int64_t jqc = jq < m ? jq : m - 1;
   for (int sb = 0; sb < k; sb += kEK) {
+    // unconditional loads from clamped indices, zeroed at the LDS store
+    double qv[8], yv[8];
+    const int s2 = sb + ysl;
+    const int s2c = s2 < k ? s2 : k - 1;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int s = sb + qs0 + 4 * i;
+      const int c = c0 + yc0 + 8 * i;
+      qv[i] = Q[(int64_t)(s < k ? s : k - 1) * ldq + jqc];
+      yv[i] = Y[(int64_t)(c < r ? c : r - 1) * ky + s2c];
+    }
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int sl = qs0 + 4 * i;
       const int s = sb + sl;
-      const int64_t j = j0 + qj;
-      qs[sl][qj] = (s < k && j < m) ? Q[(int64_t)s * ldq + j] : 0.0;
+      qs[sl][qj] = (s < k && jq < m) ? qv[i] : 0.0;
       const int cl = yc0 + 8 * i;
       const int c = c0 + cl;
-      const int s2 = sb + ysl;
-      ys[ysl][cl] = (s2 < k && c < r) ? Y[(int64_t)c * ky + s2] : 0.0;
+      ys[ysl][cl] = (s2 < k && c < r) ? yv[i] : 0.0;
     }
     __syncthreads();
 #pragma unroll 8
@@ -134,6 +157,17 @@ __global__ __launch_bounds__(kEThreads) void k_err_resid(const double *__restric
     }
     __syncthreads();
   }
+  // the tile's target values: 16 unconditional loads from clamped indices
+  float bt[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int64_t j = j0 + ty + 16 * u;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int c = c0 + tx + 16 * v;
+      bt[u][v] = B[(int64_t)(c < r ? c : r - 1) * ldb + (j < m ? j : m - 1)];
+    }
+  }
   double sq = 0.0;
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
@@ -141,10 +175,8 @@ __global__ __launch_bounds__(kEThreads) void k_err_resid(const double *__restric
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int c = c0 + tx + 16 * v;
-      if (j < m && c < r) {
-        const double e = (double)B[(int64_t)c * ldb + j] - acc[u][v];
-        sq = fma(e, e, sq);
-      }
+      const double e = (double)bt[u][v] - acc[u][v];
+      sq = (j < m && c < r) ? fma(e, e, sq) : sq;
     }
   }
   sq = wave_sum(sq);
