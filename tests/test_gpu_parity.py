@@ -388,9 +388,12 @@ def test_argument_and_state_errors(gpu):
 
 
 # ---------------------------------------------------------------- a6 ---------
-@pytest.mark.parametrize("dt", ["f32", "bf16"])
-def test_batched_blocks_and_merge_match_oracle(gpu, dt):
-    m, r, kb, km = 256, 32, 5, 12
+# m = 256: in binary32 every lane's chunks lie inside m (the unmasked column
+# loop); in BF16, and at the ragged m = 333 (a partial last chunk) in both,
+# the masked loop
+@pytest.mark.parametrize("dt,m", [("f32", 256), ("bf16", 256), ("f32", 333), ("bf16", 333)])
+def test_batched_blocks_and_merge_match_oracle(gpu, dt, m):
+    r, kb, km = 32, 5, 12
     widths = synth.block_widths(8, 150, 1500, seed=3)
     off = np.concatenate([[0], np.cumsum(widths)]).astype(np.int64)
     n = int(off[-1])
